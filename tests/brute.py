@@ -1,0 +1,133 @@
+"""Slow, independent checks for tiny grids -- used only to pin the oracle.
+
+Nothing here is shared with the oracle or the GPU library.  Adjacency is derived
+from explicit simplices (the Kuhn split of each cube into six tetrahedra, one
+per ordering of the axes, and of each square into two triangles), not from an
+offset table; labels are found by walking integral lines one step at a time;
+bounds are checked with exact rationals.
+"""
+from fractions import Fraction
+from itertools import permutations
+
+import numpy as np
+
+
+def vid(x, y, z, nx, ny):
+    return x + nx * (y + ny * z)
+
+
+def adjacency(ndim, nx, ny, nz=1):
+    """Vertex -> set of mesh neighbours, from the edges of every top simplex of
+    the Freudenthal triangulation.  A simplex walks from a cell's lowest corner
+    to its highest corner adding one unit vector at a time, in the order given
+    by a permutation of the axes (Sec. III-A: PL function on a triangular /
+    tetrahedral mesh).  A grid one vertex thick along an axis has no cells
+    along it; its edges come from the same split of the remaining axes."""
+    n = nx * ny * nz
+    adj = [set() for _ in range(n)]
+    dims = [nx, ny, nz] if ndim == 3 else [nx, ny]
+    live = [a for a, d in enumerate(dims) if d > 1]
+    # cells span the live axes only
+    ranges = [range(d - 1) if d > 1 else range(1) for d in dims]
+    for cell in np.ndindex(*[len(r) for r in ranges]):
+        base = list(cell) + ([0] if ndim == 2 else [])
+        for perm in permutations(live):
+            p = list(base) if ndim == 3 else base[:2] + [0]
+            verts = [vid(p[0], p[1], p[2], nx, ny)]
+            for a in perm:
+                p[a] += 1
+                verts.append(vid(p[0], p[1], p[2], nx, ny))
+            for u in verts:
+                for v in verts:
+                    if u != v:
+                        adj[u].add(v)
+    return adj
+
+
+def edge_count_closed_form(ndim, nx, ny, nz=1):
+    if ndim == 2:
+        return (nx - 1) * ny + nx * (ny - 1) + (nx - 1) * (ny - 1)
+    return ((nx - 1) * ny * nz + nx * (ny - 1) * nz + nx * ny * (nz - 1)
+            + (nx - 1) * (ny - 1) * nz + (nx - 1) * ny * (nz - 1) + nx * (ny - 1) * (nz - 1)
+            + (nx - 1) * (ny - 1) * (nz - 1))
+
+
+def steepest(vals, adj, i):
+    """(n_max(i), n_min(i)) over {i} + neighbours; ties by vertex index."""
+    cand = [i] + sorted(adj[i])
+    up = max(cand, key=lambda j: (vals[j], j))
+    down = min(cand, key=lambda j: (vals[j], j))
+    return up, down
+
+
+def walk(vals, adj, i, ascending=True):
+    while True:
+        up, down = steepest(vals, adj, i)
+        nxt = up if ascending else down
+        if nxt == i:
+            return i
+        i = nxt
+
+
+def rational(x):
+    return Fraction(float(x)) if not isinstance(x, Fraction) else x
+
+
+def exact_lower(f, xi_t, dtype):
+    """Smallest value of dtype that is >= f - xi_t, found by exact rationals."""
+    target = rational(f) - rational(xi_t)
+    t = dtype(float(target))  # nearest, then fix up
+    while rational(t) < target:
+        t = np.nextafter(t, dtype(np.inf))
+    while True:
+        p = np.nextafter(t, dtype(-np.inf))
+        if rational(p) >= target:
+            t = p
+        else:
+            return t
+
+
+def exact_upper(f, xi_t, dtype):
+    target = rational(f) + rational(xi_t)
+    t = dtype(float(target))
+    while rational(t) > target:
+        t = np.nextafter(t, dtype(-np.inf))
+    while True:
+        p = np.nextafter(t, dtype(np.inf))
+        if rational(p) <= target:
+            t = p
+        else:
+            return t
+
+
+def slow_correct(f, fhat, xi_t, adj, max_iters=10 ** 6):
+    """Reference correction loop written from the rules of Sec. IV-A, in the
+    field's own numpy scalar type.  Returns (g, iterations, status)."""
+    dt = f.dtype.type
+    fl = f.reshape(-1)
+    g = fhat.reshape(-1).copy()
+    n = fl.size
+    lb = [exact_lower(fl[i], xi_t, dt) for i in range(n)]
+    dir_f = [steepest(fl, adj, i) for i in range(n)]
+    k = 0
+    while True:
+        targets = set()
+        for i in range(n):
+            up, down = steepest(g, adj, i)
+            if up != dir_f[i][0]:
+                targets.add(up)          # spurious maximum / false maximum
+            if down != dir_f[i][1]:
+                targets.add(dir_f[i][1])  # original minimum must be lowered
+        if not targets:
+            return g.reshape(f.shape), k, "OK"
+        if all(g[t] == lb[t] for t in targets):
+            return g.reshape(f.shape), k, "STALLED"
+        if k == max_iters:
+            return g.reshape(f.shape), k, "NOT_CONVERGED"
+        new = g.copy()
+        for t in targets:
+            half = dt(0.5) * (g[t] - lb[t])
+            m = lb[t] + half
+            new[t] = m if m < g[t] else lb[t]
+        g = new
+        k += 1
