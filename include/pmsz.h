@@ -1,0 +1,184 @@
+/*
+ * pmsz.h -- C ABI of libpmsz, the gfx950 (MI355X) implementation of the
+ * pMSz correction of piecewise-linear Morse-Smale segmentations (PLMSS) in
+ * lossy-compressed scalar fields (Li et al., pMSz, arXiv 2601.01787).
+ *
+ * Problem (Sec. III-B, problem statement): given an original field f, a
+ * decompressed field fhat with |f - fhat| <= xi everywhere, produce
+ * g = fhat + delta with |f - g| <= xi whose extrema and PLMSS equal those of f.
+ * pMSz reaches this with the relaxed sufficient condition of Sec. IV-A: every
+ * vertex keeps the steepest-ascent and steepest-descent neighbour it has in f
+ * (extrema included), enforced by decrease-only edits (Eq. 1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Grid.  Values are stored densely, x fastest: index = x + nx*(y + ny*z).  A 2D
+ *   grid has ndim = 2 and nz = 1.  The mesh is the Freudenthal (Kuhn)
+ *   triangulation: each square is split along its (0,0)-(1,1) diagonal, each
+ *   cube into six tetrahedra around its (0,0,0)-(1,1,1) diagonal.  The
+ *   neighbours of a vertex are the 6 (2D) or 14 (3D) offsets +-b where b is a
+ *   non-zero 0/1 vector; there is no periodic wrap.  nx*ny*nz must be below
+ *   2^31 (vertex ids are int32).
+ * Order.  Vertex a is above vertex b iff h_a > h_b, or h_a == h_b and a > b
+ *   (ties broken by index).  n_max(i) / n_min(i) are the highest / lowest
+ *   vertex of {i} plus its neighbours (Sec. IV-A); i is a maximum iff
+ *   n_max(i) == i (Sec. III-A, extrema).
+ * Direction byte.  One uint8 per vertex: bits 0-3 hold the code of n_max(i),
+ *   bits 4-7 the code of n_min(i).  Code 0 = the vertex itself; codes 1..7 =
+ *   offset +b, and 9..15 = offset -b, where b = (code&1, code>>1&1, code>>2&1)
+ *   as (dx, dy, dz).  Code 8 is never produced.
+ * Bounds.  xi_T is xi in the field type (for binary32 the nearest float,
+ *   stepped toward zero if it rounded up).  lb_i is the smallest value of the
+ *   field type >= f_i - xi_T and ub_i the largest <= f_i + xi_T, so a value in
+ *   [lb_i, ub_i] satisfies |f_i - g_i| <= xi exactly.
+ * Memory.  All array arguments are DEVICE pointers owned by the caller and
+ *   must stay valid until the stream work finishes.  Scratch space is a caller
+ *   supplied workspace whose size pmsz_workspace_size() reports; the library
+ *   keeps no device memory between calls.  Structs marked "host" live in host
+ *   memory.
+ * Streams.  `stream` is a hipStream_t (NULL = the null stream).  Work is
+ *   enqueued on it; the functions that must read results back (correct,
+ *   verify, labels) synchronise with it before returning.
+ * Errors.  Every function returns a pmsz_status code and never aborts.
+ *   Argument errors are reported before any device work is enqueued and
+ *   before any caller buffer is written.  pmsz_last_error() returns a
+ *   thread-local message about the last failure.
+ */
+#ifndef PMSZ_H
+#define PMSZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  PMSZ_OK = 0,
+  PMSZ_ERR_INVALID_ARG = 1,   /* bad grid, dtype, pointer, xi or size        */
+  PMSZ_ERR_NONFINITE = 2,     /* f or fhat holds a NaN or an infinity        */
+  PMSZ_ERR_INPUT_BOUND = 3,   /* fhat outside [lb, ub] somewhere             */
+  PMSZ_ERR_NOT_CONVERGED = 4, /* max_iters edit rounds ran, flags remain     */
+  PMSZ_ERR_STALLED = 5,       /* every flagged vertex already at its bound   */
+  PMSZ_ERR_OOM = 6,           /* workspace too small                         */
+  PMSZ_ERR_DEVICE = 7         /* a HIP runtime call failed                   */
+} pmsz_status;
+
+typedef enum { PMSZ_F32 = 0, PMSZ_F64 = 1 } pmsz_dtype;
+
+typedef struct {
+  int32_t ndim;  /* 2 or 3 */
+  int32_t dtype; /* pmsz_dtype */
+  int64_t nx, ny, nz;
+} pmsz_grid;
+
+/* Result of a correction (host struct). */
+typedef struct {
+  int64_t iterations;       /* edit rounds applied (0 if fhat already conforms) */
+  int64_t steps_applied;    /* value changes summed over all rounds              */
+  int64_t flagged_final;    /* size of the flag set at exit (0 when OK)          */
+  int64_t stalled_flags;    /* flagged vertices at exit already at their bound   */
+  int64_t mismatch_initial; /* (vertex, direction) mismatches of fhat vs f       */
+  int32_t status;           /* pmsz_status of the run                            */
+  int32_t reserved;
+} pmsz_stats;
+
+/* Evaluation counts (Sec. V-D: wrongly labelled points, false extrema). */
+typedef struct {
+  int64_t bound_violations; /* g outside [lb, ub] or non-finite              */
+  int64_t asc_mismatch;     /* n_max under g differs from n_max under f      */
+  int64_t desc_mismatch;    /* n_min under g differs from n_min under f      */
+  int64_t false_max;        /* maximum in g, not in f                        */
+  int64_t false_min;
+  int64_t missed_max;       /* maximum in f, not in g                        */
+  int64_t missed_min;
+  int64_t wrong_max_label;  /* ascending-segmentation label differs          */
+  int64_t wrong_min_label;  /* descending-segmentation label differs         */
+  int64_t wrong_label;      /* either label differs (PLMSS region differs)   */
+  int64_t vertices_edited;  /* g != fhat; -1 when fhat is not given          */
+  double max_abs_err;       /* max |g - f| evaluated in binary64             */
+} pmsz_report;
+
+/* One member of a batch (host struct). */
+typedef struct {
+  pmsz_grid grid;
+  const void* f; /* device, original field                        */
+  void* g;       /* device, in: fhat, out: corrected field        */
+  double xi;     /* absolute error bound of this field            */
+} pmsz_field;
+
+/* Workspace kinds for pmsz_workspace_size. */
+enum { PMSZ_WS_CORRECT = 0, PMSZ_WS_VERIFY = 1, PMSZ_WS_LABELS = 2 };
+
+/* Bytes of device workspace that operation `op` needs for `grid`
+ * (*bytes, host).  Returns PMSZ_ERR_INVALID_ARG for a bad grid or op. */
+int pmsz_workspace_size(const pmsz_grid* grid, int op, size_t* bytes);
+
+/* Steepest directions of a field (Sec. IV-A: n_min(i) and n_max(i) over the
+ * neighbourhood; Sec. III-A: extrema are the vertices pointing at themselves).
+ * field: device, nx*ny*nz values of grid->dtype.  dirs: device, nx*ny*nz
+ * direction bytes (layout above), written.  Values must be finite; with a
+ * non-finite value the bytes are unspecified.  Asynchronous on `stream`. */
+int pmsz_directions(const pmsz_grid* grid, const void* field, uint8_t* dirs, void* stream);
+
+/* The pMSz correction (Sec. III-B Eq. 1 with the FPmax rule; Sec. IV-A
+ * ascending and descending rules), on one field:
+ *   k = 0; repeat:
+ *     F = { n_max^g(i) : n_max^g(i) != n_max^f(i) } u { n_min^f(i) : n_min^g(i) != n_min^f(i) }
+ *         computed from g^k alone (Jacobi);
+ *     F empty                        -> PMSZ_OK
+ *     every t in F has g_t == lb_t   -> PMSZ_ERR_STALLED
+ *     k == max_iters                 -> PMSZ_ERR_NOT_CONVERGED
+ *     for t in F at once: g_t <- lb_t + (g_t - lb_t)/2 rounded, or lb_t when
+ *     that would not decrease g_t (the edit size delta is left open by the
+ *     paper; this halving is the reading used here); k += 1.
+ * f: device, original field.  g: device, in: fhat, out: the last iterate
+ * (always within [lb, fhat]).  dirs_f: device direction bytes of f, or NULL
+ * to compute them into the workspace.  ws: device workspace of at least
+ * pmsz_workspace_size(grid, PMSZ_WS_CORRECT) bytes, 256-byte aligned.
+ * max_iters >= 0.  stats: host, filled on every return after argument checks
+ * (status mirrors the return code).  Validation failures (NONFINITE,
+ * INPUT_BOUND) leave g unchanged.  Synchronises with `stream`. */
+int pmsz_correct(const pmsz_grid* grid, const void* f, void* g, double xi,
+                 const uint8_t* dirs_f, void* ws, size_t ws_bytes, int64_t max_iters,
+                 pmsz_stats* stats, void* stream);
+
+/* Batched correction of n independent fields in one persistent launch.  Each
+ * field follows exactly the iteration of pmsz_correct (bit-identical results
+ * and statistics); fields retire independently.  fields, stats: host arrays
+ * of n.  ws: device workspace of pmsz_batched_workspace_size() bytes.
+ * Returns PMSZ_OK when every field converged, otherwise the first non-OK
+ * field status (per-field codes are in stats).  Synchronises with `stream`. */
+int pmsz_batched_workspace_size(int32_t n, const pmsz_field* fields, size_t* bytes);
+int pmsz_correct_batched(int32_t n, const pmsz_field* fields, void* ws, size_t ws_bytes,
+                         int64_t max_iters, pmsz_stats* stats, void* stream);
+
+/* Segmentation labels (Sec. III-A: integral lines end at an extremum; the
+ * ascending / descending segmentation groups vertices by that extremum).
+ * dirs: device direction bytes.  max_label / min_label: device int32 arrays of
+ * nx*ny*nz, written with the index of the maximum (resp. minimum) reached by
+ * following n_max (resp. n_min); either may be NULL.  ws: device workspace of
+ * pmsz_workspace_size(grid, PMSZ_WS_LABELS) bytes.  Synchronises. */
+int pmsz_labels(const pmsz_grid* grid, const uint8_t* dirs, int32_t* max_label,
+                int32_t* min_label, void* ws, size_t ws_bytes, void* stream);
+
+/* Evaluation counts of Sec. V-D, recomputed from (f, g) from scratch: bound
+ * violations, direction mismatches, false / missed extrema, wrong labels,
+ * edited vertices (needs fhat, else -1) and max |g - f|.  f, g, fhat: device
+ * (fhat may be NULL).  ws: pmsz_workspace_size(grid, PMSZ_WS_VERIFY) bytes.
+ * report: host.  Synchronises with `stream`. */
+int pmsz_verify(const pmsz_grid* grid, const void* f, const void* g, const void* fhat,
+                double xi, void* ws, size_t ws_bytes, pmsz_report* report, void* stream);
+
+/* Name of a status code (static string). */
+const char* pmsz_status_string(int status);
+
+/* Thread-local description of the last failure on this thread ("" if none). */
+const char* pmsz_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PMSZ_H */

@@ -1,0 +1,238 @@
+"""pMSz on MI355X: Python binding of libpmsz (gfx950 HIP kernels behind a C ABI).
+
+Argument marshalling only: every step of the correction runs in the library's
+HIP kernels.  PyTorch supplies device memory and the current stream.  There is
+no CPU fallback: if ``libpmsz.so`` is missing or fails to load, every call
+raises.
+
+Names follow the paper (pMSz, arXiv 2601.01787): ``directions`` computes
+n_max / n_min (Sec. IV-A), ``correct`` runs the decrease-only edit loop
+(Eq. 1, Sec. IV-A rules), ``labels`` the ascending / descending segmentations
+(Sec. III-A), ``verify`` the evaluation counts of Sec. V-D.
+"""
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpmsz.so")
+
+F32, F64 = 0, 1
+WS_CORRECT, WS_VERIFY, WS_LABELS = 0, 1, 2
+STATUS = {0: "OK", 1: "INVALID_ARG", 2: "NONFINITE", 3: "INPUT_BOUND", 4: "NOT_CONVERGED",
+          5: "STALLED", 6: "OOM", 7: "DEVICE"}
+DEFAULT_MAX_ITERS = 1 << 40
+
+EXPORTS = ("pmsz_workspace_size", "pmsz_directions", "pmsz_correct",
+           "pmsz_batched_workspace_size", "pmsz_correct_batched", "pmsz_labels",
+           "pmsz_verify", "pmsz_status_string", "pmsz_last_error")
+
+
+class PmszError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__("%s: %s" % (STATUS.get(status, status), message))
+        self.status = status
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("dtype", ctypes.c_int32), ("nx", ctypes.c_int64),
+                ("ny", ctypes.c_int64), ("nz", ctypes.c_int64)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int64), ("steps_applied", ctypes.c_int64),
+                ("flagged_final", ctypes.c_int64), ("stalled_flags", ctypes.c_int64),
+                ("mismatch_initial", ctypes.c_int64), ("status", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        d["status"] = STATUS.get(d["status"], d["status"])
+        return d
+
+
+class Report(ctypes.Structure):
+    _fields_ = [("bound_violations", ctypes.c_int64), ("asc_mismatch", ctypes.c_int64),
+                ("desc_mismatch", ctypes.c_int64), ("false_max", ctypes.c_int64),
+                ("false_min", ctypes.c_int64), ("missed_max", ctypes.c_int64),
+                ("missed_min", ctypes.c_int64), ("wrong_max_label", ctypes.c_int64),
+                ("wrong_min_label", ctypes.c_int64), ("wrong_label", ctypes.c_int64),
+                ("vertices_edited", ctypes.c_int64), ("max_abs_err", ctypes.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class Field(ctypes.Structure):
+    _fields_ = [("grid", Grid), ("f", ctypes.c_void_p), ("g", ctypes.c_void_p),
+                ("xi", ctypes.c_double)]
+
+
+_lib = None
+
+
+def load():
+    """Load libpmsz.so (built by ``build.py``); raises if it is not there."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libpmsz.so is not built (run paper_2601_01787_amd/build.py); "
+                          "there is no fallback path")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64, dbl, sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double,
+                             ctypes.c_size_t)
+    G = ctypes.POINTER(Grid)
+    L.pmsz_workspace_size.argtypes = [G, ctypes.c_int, ctypes.POINTER(sz)]
+    L.pmsz_directions.argtypes = [G, vp, vp, vp]
+    L.pmsz_correct.argtypes = [G, vp, vp, dbl, vp, vp, sz, i64, ctypes.POINTER(Stats), vp]
+    L.pmsz_batched_workspace_size.argtypes = [i32, ctypes.POINTER(Field), ctypes.POINTER(sz)]
+    L.pmsz_correct_batched.argtypes = [i32, ctypes.POINTER(Field), vp, sz, i64,
+                                       ctypes.POINTER(Stats), vp]
+    L.pmsz_labels.argtypes = [G, vp, vp, vp, vp, sz, vp]
+    L.pmsz_verify.argtypes = [G, vp, vp, vp, dbl, vp, sz, ctypes.POINTER(Report), vp]
+    L.pmsz_status_string.argtypes = [ctypes.c_int]
+    L.pmsz_status_string.restype = ctypes.c_char_p
+    L.pmsz_last_error.restype = ctypes.c_char_p
+    for name in EXPORTS[:-2]:
+        getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _raise_if(code, allowed=(0,)):
+    if code not in allowed:
+        raise PmszError(code, load().pmsz_last_error().decode())
+
+
+def grid_of(t):
+    """pmsz_grid of a C-contiguous device tensor shaped (ny, nx) or (nz, ny, nx)."""
+    if t.dtype == torch.float32:
+        dt = F32
+    elif t.dtype == torch.float64:
+        dt = F64
+    elif t.dtype == torch.uint8:
+        dt = F32  # direction bytes: only the shape matters
+    else:
+        raise TypeError("fields must be float32 or float64, got %s" % t.dtype)
+    if t.dim() == 2:
+        return Grid(2, dt, t.shape[1], t.shape[0], 1)
+    if t.dim() == 3:
+        return Grid(3, dt, t.shape[2], t.shape[1], t.shape[0])
+    raise ValueError("fields must be 2D (ny, nx) or 3D (nz, ny, nx)")
+
+
+def _dev(t, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError("%s must be a device tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    return t
+
+
+def _stream(t):
+    return ctypes.c_void_p(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def workspace_size(grid, op):
+    n = ctypes.c_size_t()
+    _raise_if(load().pmsz_workspace_size(ctypes.byref(grid), op, ctypes.byref(n)))
+    return n.value
+
+
+def workspace(grid, op, device):
+    """A caller-owned workspace tensor (uint8, 256-byte aligned)."""
+    n = workspace_size(grid, op)
+    ws = torch.empty(n + 256, dtype=torch.uint8, device=device)
+    off = (-ws.data_ptr()) % 256
+    return ws[off:off + n]
+
+
+def directions(h, out=None):
+    """Direction bytes of a field: low nibble = code of n_max, high = n_min."""
+    _dev(h, "field")
+    grid = grid_of(h)
+    if out is None:
+        out = torch.empty(h.shape, dtype=torch.uint8, device=h.device)
+    _dev(out, "out")
+    _raise_if(load().pmsz_directions(ctypes.byref(grid), ctypes.c_void_p(h.data_ptr()),
+                                     ctypes.c_void_p(out.data_ptr()), _stream(h)))
+    return out
+
+
+def correct(f, fhat, xi, *, inplace=False, max_iters=DEFAULT_MAX_ITERS, dirs_f=None, ws=None):
+    """Correct fhat toward f's topology within |g - f| <= xi.
+
+    Returns (g, stats).  ``stats['status']`` is "OK", "STALLED",
+    "NOT_CONVERGED", "NONFINITE" or "INPUT_BOUND"; argument and device errors
+    raise PmszError."""
+    _dev(f, "f")
+    _dev(fhat, "fhat")
+    if fhat.shape != f.shape or fhat.dtype != f.dtype or fhat.device != f.device:
+        raise ValueError("f and fhat must match in shape, dtype and device")
+    g = fhat if inplace else fhat.clone()
+    grid = grid_of(f)
+    if ws is None:
+        ws = workspace(grid, WS_CORRECT, f.device)
+    st = Stats()
+    dptr = ctypes.c_void_p(_dev(dirs_f, "dirs_f").data_ptr()) if dirs_f is not None else None
+    code = load().pmsz_correct(ctypes.byref(grid), ctypes.c_void_p(f.data_ptr()),
+                               ctypes.c_void_p(g.data_ptr()), float(xi), dptr,
+                               ctypes.c_void_p(ws.data_ptr()), ws.numel(), int(max_iters),
+                               ctypes.byref(st), _stream(f))
+    _raise_if(code, allowed=(0, 2, 3, 4, 5))
+    return g, st.as_dict()
+
+
+def correct_batched(fields, *, max_iters=DEFAULT_MAX_ITERS):
+    """Correct a list of (f, g, xi) in place (g holds fhat on entry); returns
+    the list of per-field stats."""
+    n = len(fields)
+    arr = (Field * max(n, 1))()
+    for i, (f, g, xi) in enumerate(fields):
+        _dev(f, "f")
+        _dev(g, "g")
+        arr[i] = Field(grid_of(f), f.data_ptr(), g.data_ptr(), float(xi))
+    need = ctypes.c_size_t()
+    _raise_if(load().pmsz_batched_workspace_size(n, arr, ctypes.byref(need)))
+    dev = fields[0][0].device if n else torch.device("cuda")
+    ws = torch.empty(need.value + 256, dtype=torch.uint8, device=dev)
+    off = (-ws.data_ptr()) % 256
+    st = (Stats * max(n, 1))()
+    code = load().pmsz_correct_batched(n, arr, ctypes.c_void_p(ws.data_ptr() + off),
+                                       need.value, int(max_iters), st,
+                                       ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream))
+    _raise_if(code, allowed=(0, 2, 3, 4, 5))
+    return [st[i].as_dict() for i in range(n)]
+
+
+def labels(dirs):
+    """(max_label, min_label) int32 tensors: index of the extremum each vertex
+    reaches along n_max / n_min."""
+    _dev(dirs, "dirs")
+    grid = grid_of(dirs)
+    mx = torch.empty(dirs.shape, dtype=torch.int32, device=dirs.device)
+    mn = torch.empty(dirs.shape, dtype=torch.int32, device=dirs.device)
+    ws = workspace(grid, WS_LABELS, dirs.device)
+    _raise_if(load().pmsz_labels(ctypes.byref(grid), ctypes.c_void_p(dirs.data_ptr()),
+                                 ctypes.c_void_p(mx.data_ptr()), ctypes.c_void_p(mn.data_ptr()),
+                                 ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(dirs)))
+    return mx, mn
+
+
+def verify(f, g, fhat, xi):
+    """Evaluation counts (Sec. V-D) of g against f."""
+    _dev(f, "f")
+    _dev(g, "g")
+    if fhat is not None:
+        _dev(fhat, "fhat")
+    grid = grid_of(f)
+    ws = workspace(grid, WS_VERIFY, f.device)
+    rep = Report()
+    _raise_if(load().pmsz_verify(ctypes.byref(grid), ctypes.c_void_p(f.data_ptr()),
+                                 ctypes.c_void_p(g.data_ptr()),
+                                 ctypes.c_void_p(fhat.data_ptr()) if fhat is not None else None,
+                                 float(xi), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                 ctypes.byref(rep), _stream(f)))
+    return rep.as_dict()

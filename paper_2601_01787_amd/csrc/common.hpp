@@ -1,0 +1,149 @@
+// common.hpp -- device-side building blocks of libpmsz (gfx950).
+//
+// Everything here is the GPU library's own: it shares nothing with the CPU
+// oracle that checks it.  Arithmetic follows IEEE-754 round-to-nearest in the
+// field type; every source is compiled with -ffp-contract=off so that no
+// product is fused into an add, and without fast-math.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/pmsz.h"
+
+namespace pmsz {
+
+// ---------------------------------------------------------------------------
+// Control block of one correction (lives at the start of the workspace).  All
+// counters are device-scope atomics; the last block of each apply launch
+// folds them into the iteration state (Sec. IV-A loop, convergence of
+// Sec. III-B) and clears them for the next round.
+// ---------------------------------------------------------------------------
+struct Ctl {
+  unsigned long long mism;       // (vertex, direction) mismatches this round
+  unsigned long long nflag;      // |F| this round
+  unsigned long long at_lb;      // flagged vertices already at their bound
+  unsigned long long k;          // edit rounds applied so far
+  unsigned long long steps;      // value changes over all rounds
+  unsigned long long mism0;      // mismatches of fhat
+  unsigned long long flagged_final;
+  unsigned long long stalled_final;
+  unsigned long long bad_nonfinite;  // validation counters
+  unsigned long long bad_bound;
+  unsigned int ticket;           // arrival counter of the apply launch
+  int done;                      // nonzero once the status is final
+  int status;                    // pmsz_status
+  int pad[3];
+};
+static_assert(sizeof(Ctl) <= 256, "control block must fit its 256-byte slot");
+
+constexpr int kBlock = 256;
+
+// ---------------------------------------------------------------------------
+// Direction codes: 0 = self, m in 1..7 = offset +(m&1, m>>1&1, m>>2&1),
+// 8+m = the negated offset.  Linear index delta of a code.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t code_delta(int code, int64_t nx, int64_t sxy) {
+  int m = code & 7;
+  int64_t d = (int64_t)(m & 1) + (int64_t)((m >> 1) & 1) * nx + (int64_t)((m >> 2) & 1) * sxy;
+  return (code & 8) ? -d : d;
+}
+
+// ---------------------------------------------------------------------------
+// Floating-point helpers, per type.
+// ---------------------------------------------------------------------------
+template <class T> struct FP;
+
+template <> struct FP<float> {
+  using U = uint32_t;
+  __device__ static __forceinline__ float nan() { return __builtin_nanf(""); }
+  __device__ static __forceinline__ float maxv() { return 3.40282347e+38f; }
+  __device__ static __forceinline__ float min_sub() { return __uint_as_float(1u); }
+  __device__ static __forceinline__ U bits(float x) { return __float_as_uint(x); }
+  __device__ static __forceinline__ float from(U b) { return __uint_as_float(b); }
+};
+
+template <> struct FP<double> {
+  using U = uint64_t;
+  __device__ static __forceinline__ double nan() { return __builtin_nan(""); }
+  __device__ static __forceinline__ double maxv() { return 1.7976931348623157e+308; }
+  __device__ static __forceinline__ double min_sub() { return __longlong_as_double(1ll); }
+  __device__ static __forceinline__ U bits(double x) { return (U)__double_as_longlong(x); }
+  __device__ static __forceinline__ double from(U b) { return __longlong_as_double((long long)b); }
+};
+
+// Next representable value toward +inf (x finite).
+template <class T>
+__device__ __forceinline__ T next_up(T x) {
+  if (x == T(0)) return FP<T>::min_sub();
+  typename FP<T>::U b = FP<T>::bits(x);
+  return FP<T>::from(x > T(0) ? b + 1 : b - 1);
+}
+template <class T>
+__device__ __forceinline__ T next_down(T x) {
+  return -next_up<T>(-x);
+}
+
+// Knuth's TwoSum: a + b == s + e exactly (round-to-nearest, no fusion).
+template <class T>
+__device__ __forceinline__ void two_sum(T a, T b, T& s, T& e) {
+  s = a + b;
+  T bp = s - a;
+  T ap = s - bp;
+  e = (a - ap) + (b - bp);
+}
+
+// Smallest value >= f - xi and largest value <= f + xi (exact bounds).
+template <class T>
+__device__ __forceinline__ T lower_bound(T f, T xi) {
+  T s, e;
+  two_sum<T>(f, -xi, s, e);
+  if (__builtin_isinf(s)) return -FP<T>::maxv();
+  return e > T(0) ? next_up<T>(s) : s;
+}
+template <class T>
+__device__ __forceinline__ T upper_bound(T f, T xi) {
+  T s, e;
+  two_sum<T>(f, xi, s, e);
+  if (__builtin_isinf(s)) return FP<T>::maxv();
+  return e < T(0) ? next_down<T>(s) : s;
+}
+
+// Eq. 1 with the halving edit: lb + (g - lb)/2, or lb when that would not
+// decrease g.
+template <class T>
+__device__ __forceinline__ T halving_edit(T g, T lb) {
+  T h = g - lb;
+  T m = lb + T(0.5) * h;
+  return (m < g) ? m : lb;
+}
+
+// ---------------------------------------------------------------------------
+// Reductions.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long wave_sum(unsigned long long v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Sum over the block; the result is valid in thread 0.  `sh` needs one slot
+// per wave.
+__device__ __forceinline__ unsigned long long block_sum(unsigned long long v,
+                                                        unsigned long long* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  unsigned long long r = 0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += sh[w];
+  __syncthreads();
+  return r;
+}
+
+// Device-scope load that bypasses stale caches.
+__device__ __forceinline__ unsigned long long load_acquire(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+}  // namespace pmsz

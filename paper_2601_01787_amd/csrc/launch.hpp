@@ -1,0 +1,54 @@
+// launch.hpp -- host-side launchers of the libpmsz kernels (internal).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.hpp"
+
+namespace pmsz {
+
+struct Geo {
+  int ndim;
+  int64_t nx, ny, nz, sxy, n;
+};
+
+inline Geo make_geo(const pmsz_grid& g) {
+  Geo G;
+  G.ndim = g.ndim;
+  G.nx = g.nx;
+  G.ny = g.ny;
+  G.nz = g.nz;
+  G.sxy = g.nx * g.ny;
+  G.n = G.sxy * g.nz;
+  return G;
+}
+
+inline int64_t bitmap_words(int64_t n) { return (n + 31) / 32; }
+
+// stencil.hip
+hipError_t launch_init(Ctl* ctl, uint32_t* bm, int64_t nwords, hipStream_t s);
+hipError_t launch_dirs(int dtype, const void* h, const Geo& G, uint8_t* dirs, hipStream_t s);
+hipError_t launch_validate(int dtype, const void* f, const void* fhat, int64_t n, double xi_t,
+                           Ctl* ctl, hipStream_t s);
+hipError_t launch_detect(int dtype, const void* g, const Geo& G, const uint8_t* dirs_f,
+                         uint32_t* bm, Ctl* ctl, hipStream_t s);
+hipError_t launch_apply(int dtype, const void* f, void* g, const Geo& G, uint32_t* bm,
+                        double xi_t, Ctl* ctl, int64_t max_iters, hipStream_t s);
+
+// labels.hip
+hipError_t launch_labels_init(const uint8_t* dirs, const Geo& G, int32_t* lmax, int32_t* lmin,
+                              hipStream_t s);
+hipError_t launch_labels_jump(int32_t* lab, int64_t n, unsigned int* changed, hipStream_t s);
+
+// verify.hip
+struct VerifyCounts {
+  unsigned long long c[11];  // bound, asc, desc, fmax, fmin, mmax, mmin, wmax, wmin, wany, edited
+  unsigned long long max_err_bits;
+};
+hipError_t launch_verify(int dtype, const void* f, const void* g, const void* fhat, int64_t n,
+                         double xi_t, const uint8_t* df, const uint8_t* dg, const int32_t* lf_max,
+                         const int32_t* lf_min, const int32_t* lg_max, const int32_t* lg_min,
+                         VerifyCounts* out, hipStream_t s);
+
+}  // namespace pmsz

@@ -1,0 +1,233 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, bit for
+bit, on seeded inputs that span several tiles with ragged tails, plus the
+edge cases of the method (stall, out-of-rounds, validation failures,
+subnormal values, degenerate grids)."""
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2601_01787_amd as pmsz
+import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+STAT_KEYS = ("iterations", "steps_applied", "flagged_final", "stalled_flags",
+             "mismatch_initial", "status")
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def same_bits(a, b):
+    a, b = np.ascontiguousarray(a), np.ascontiguousarray(b)
+    return a.shape == b.shape and a.dtype == b.dtype and np.array_equal(a.view(np.uint8),
+                                                                       b.view(np.uint8))
+
+
+def random_case(shape, dtype, seed, ties=False, xi=0.05):
+    rng = np.random.default_rng(seed)
+    if ties:
+        f = (rng.integers(0, 8, size=shape) * 0.125).astype(dtype)
+    else:
+        f = rng.uniform(0, 1, size=shape)
+        f = (f + np.roll(f, 1, axis=-1) + np.roll(f, 1, axis=0)) / 3.0
+        f = f.astype(dtype)
+    lb, ub = oracle.bounds(f, xi)
+    fhat = (f.astype(np.float64) + rng.uniform(-xi, xi, size=shape)).astype(dtype)
+    if ties:
+        fhat[rng.uniform(size=shape) < 0.3] = dtype(0.5)
+    fhat = np.minimum(np.maximum(fhat, lb), ub)
+    return f, fhat, xi
+
+
+SHAPES = [(64, 64, 64), (7, 9, 70), (3, 130, 67), (33, 1, 65), (1, 5, 300), (70, 2, 3),
+          (300, 517), (1, 1000), (1000, 1), (257, 255), (1, 1)]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("ties", [False, True])
+def test_directions_match_oracle(shape, dtype, ties):
+    f, fhat, _ = random_case(shape, dtype, seed=sum(shape) + ties, ties=ties)
+    for h in (f, fhat):
+        d = host(pmsz.directions(dev(h)))
+        assert same_bits(d, oracle.directions(h))
+
+
+@pytest.mark.parametrize("shape", SHAPES[:-1], ids=lambda s: "x".join(map(str, s)))
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("ties", [False, True])
+def test_correct_matches_oracle(shape, dtype, ties):
+    f, fhat, xi = random_case(shape, dtype, seed=3 * sum(shape) + ties, ties=ties)
+    g_ref, st_ref = oracle.correct(f, fhat, xi)
+    g, st = pmsz.correct(dev(f), dev(fhat), xi)
+    g = host(g)
+    for k in STAT_KEYS:
+        assert st[k] == st_ref[k], (k, st, st_ref)
+    assert same_bits(g, g_ref)
+
+
+def test_small_perlin_workload():
+    """64^3 float32 Perlin, eps = 1e-3 (the small workload the oracle finishes
+    in seconds)."""
+    f, fhat, xi = synth.small_perlin_case()
+    f, fhat = f.numpy(), fhat.numpy()
+    g_ref, st_ref = oracle.correct(f, fhat, xi)
+    g, st = pmsz.correct(dev(f), dev(fhat), xi)
+    assert st_ref["iterations"] > 2
+    for k in STAT_KEYS:
+        assert st[k] == st_ref[k], (k, st, st_ref)
+    assert same_bits(host(g), g_ref)
+
+
+def test_gaussian_peaks_2d_and_grf_3d():
+    f, fhat, xi = synth.make_2d_case(613, 401, 1e-3, 99)
+    f, fhat = f.numpy(), fhat.numpy()
+    g_ref, st_ref = oracle.correct(f, fhat, xi)
+    g, st = pmsz.correct(dev(f), dev(fhat), xi)
+    assert [st[k] for k in STAT_KEYS] == [st_ref[k] for k in STAT_KEYS]
+    assert same_bits(host(g), g_ref)
+    f = synth.grf3d((40, 48, 72), 1024).numpy()
+    fhat = synth.quantise_proxy(f, 1e-5, 1024)
+    g_ref, st_ref = oracle.correct(f, fhat, 1e-5)
+    g, st = pmsz.correct(dev(f), dev(fhat), 1e-5)
+    assert [st[k] for k in STAT_KEYS] == [st_ref[k] for k in STAT_KEYS]
+    assert same_bits(host(g), g_ref)
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_round_limit_gives_the_same_iterate(k):
+    f, fhat, xi = random_case((20, 30, 40), np.float32, 5)
+    g_ref, st_ref = oracle.correct(f, fhat, xi, max_iters=k)
+    g, st = pmsz.correct(dev(f), dev(fhat), xi, max_iters=k)
+    assert st_ref["status"] == "NOT_CONVERGED"
+    assert [st[k2] for k2 in STAT_KEYS] == [st_ref[k2] for k2 in STAT_KEYS]
+    assert same_bits(host(g), g_ref)
+
+
+def _hand_cases():
+    with open(os.path.join(GOLDEN, "hand_examples.json")) as fh:
+        return json.load(fh)["cases"]
+
+
+@pytest.mark.parametrize("case", _hand_cases(), ids=lambda c: c["name"])
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_hand_examples_on_gpu(case, dtype):
+    if case.get("dtype") and np.dtype(case["dtype"]) != np.dtype(dtype):
+        pytest.skip("case is specific to " + case["dtype"])
+    shape = (case["ny"], case["nx"])
+    f = np.array(case["f"], dtype=dtype).reshape(shape)
+    if case["fhat"] == "lower_bound":
+        fhat, _ = oracle.bounds(f, case["xi"])
+    else:
+        fhat = np.array(case["fhat"], dtype=dtype).reshape(shape)
+    g, st = pmsz.correct(dev(f), dev(fhat), case["xi"])
+    assert st["status"] == case["status"] and st["iterations"] == case["iterations"]
+    if "g_final" in case:
+        assert host(g).reshape(-1).tolist() == case["g_final"]
+
+
+def test_validation_failures_leave_g_untouched():
+    f, fhat, xi = random_case((9, 10, 70), np.float32, 8)
+    bad = fhat.copy()
+    bad[3, 4, 5] = np.nan
+    g, st = pmsz.correct(dev(f), dev(bad), xi)
+    assert st["status"] == "NONFINITE" and same_bits(host(g), bad)
+    out = fhat.copy()
+    out[1, 2, 3] = f[1, 2, 3] + np.float32(2 * xi)
+    g, st = pmsz.correct(dev(f), dev(out), xi)
+    assert st["status"] == "INPUT_BOUND" and same_bits(host(g), out)
+    g, st = pmsz.correct(dev(f), dev(f), 0.0)
+    assert st["status"] == "OK" and st["iterations"] == 0
+
+
+def test_subnormal_values():
+    """Bounds and edits in the binary32 subnormal range (no flush to zero)."""
+    rng = np.random.default_rng(17)
+    tiny = np.float32(1e-40)
+    f = (rng.uniform(-1, 1, size=(6, 40, 70)) * tiny).astype(np.float32)
+    xi = 3e-41
+    lb, ub = oracle.bounds(f, xi)
+    fhat = (f + rng.uniform(-1, 1, size=f.shape).astype(np.float32) * np.float32(xi)).astype(
+        np.float32)
+    fhat = np.minimum(np.maximum(fhat, lb), ub)
+    g_ref, st_ref = oracle.correct(f, fhat, xi)
+    g, st = pmsz.correct(dev(f), dev(fhat), xi)
+    assert st_ref["steps_applied"] > 0
+    assert [st[k] for k in STAT_KEYS] == [st_ref[k] for k in STAT_KEYS]
+    assert same_bits(host(g), g_ref)
+
+
+@pytest.mark.parametrize("shape", [(64, 64, 64), (3, 130, 67), (300, 517), (1000, 1)],
+                         ids=lambda s: "x".join(map(str, s)))
+def test_labels_match_oracle(shape):
+    f, fhat, xi = random_case(shape, np.float32, 21)
+    for h in (f, fhat):
+        d = pmsz.directions(dev(h))
+        mx, mn = pmsz.labels(d)
+        rmx, rmn = oracle.labels(oracle.directions(h))
+        assert np.array_equal(host(mx), rmx) and np.array_equal(host(mn), rmn)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_verify_matches_oracle(dtype):
+    f, fhat, xi = random_case((17, 40, 70), dtype, 31)
+    rep = pmsz.verify(dev(f), dev(fhat), None, xi)
+    assert rep == oracle.verify(f, fhat, None, xi)
+    assert rep["asc_mismatch"] > 0
+    g, _ = pmsz.correct(dev(f), dev(fhat), xi)
+    rep = pmsz.verify(dev(f), g, dev(fhat), xi)
+    ref = oracle.verify(f, host(g), fhat, xi)
+    assert rep == ref
+    assert rep["wrong_label"] == 0 and rep["vertices_edited"] > 0
+
+
+def test_batched_matches_alone():
+    cases = [synth.make_2d_case(nx, ny, rel, seed) for nx, ny, rel, seed in
+             [(300, 257, 1e-2, 1), (129, 700, 1e-3, 2), (256, 256, 1e-4, 3), (70, 90, 1e-3, 4)]]
+    alone = []
+    for f, fhat, xi in cases:
+        g, st = pmsz.correct(dev(f.numpy()), dev(fhat.numpy()), xi)
+        alone.append((host(g), st))
+    fields = [(dev(f.numpy()), dev(fhat.numpy()), xi) for f, fhat, xi in cases]
+    stats = pmsz.correct_batched(fields)
+    for (g_a, st_a), (_, g_b, _), st_b in zip(alone, fields, stats):
+        assert st_a == st_b
+        assert same_bits(g_a, host(g_b))
+
+
+def test_full_size_perlin_512():
+    """512^3 binary32 Perlin (one GPU's weak-scaling share): the corrected field
+    and the directions are compared through hashes the oracle wrote, and the
+    labels at sampled vertices through the oracle's walked labels."""
+    import hashlib
+    path = os.path.join(GOLDEN, "perlin512_f32.json")
+    gold = json.load(open(path))
+    f, fhat, xi = synth.large_perlin_case(device=DEV)
+    sha = lambda t: hashlib.sha256(host(t).view(np.uint8)).hexdigest()  # noqa: E731
+    assert sha(f) == gold["sha256_f"], "input generator differs on this host"
+    assert sha(fhat) == gold["sha256_fhat"]
+    d = pmsz.directions(f)
+    assert sha(d) == gold["sha256_dirs_f"]
+    g, st = pmsz.correct(f, fhat, xi, dirs_f=d)
+    for k in STAT_KEYS:
+        assert st[k] == gold["stats"][k], (k, st, gold["stats"])
+    assert sha(g) == gold["sha256_g"]
+    mx, mn = pmsz.labels(d)
+    idx = torch.tensor(gold["label_sample_idx"], device=DEV)
+    assert host(mx.reshape(-1)[idx]).tolist() == gold["label_sample_max"]
+    assert host(mn.reshape(-1)[idx]).tolist() == gold["label_sample_min"]
+    rep = pmsz.verify(f, g, fhat, xi)
+    assert rep["wrong_label"] == 0 and rep["bound_violations"] == 0
+    assert rep["asc_mismatch"] == 0 and rep["desc_mismatch"] == 0

@@ -1,0 +1,57 @@
+"""CPU-side checks of the C ABI: the library loads and exports every symbol
+the public header declares (no kernel is launched)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pmsz.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pmsz_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_entry_points():
+    names = declared_functions()
+    for must in ("pmsz_directions", "pmsz_correct", "pmsz_labels", "pmsz_verify",
+                 "pmsz_correct_batched", "pmsz_workspace_size", "pmsz_status_string"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    import paper_2601_01787_amd as pmsz
+    lib = pmsz.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert set(pmsz.EXPORTS) <= set(declared_functions())
+
+
+def test_host_only_calls():
+    """Calls that never touch the device: status names, workspace sizes and
+    argument rejection."""
+    import paper_2601_01787_amd as pmsz
+    lib = pmsz.load()
+    assert lib.pmsz_status_string(0) == b"OK"
+    assert lib.pmsz_status_string(5) == b"STALLED"
+    g = pmsz.Grid(3, pmsz.F32, 512, 512, 512)
+    n = pmsz.workspace_size(g, pmsz.WS_CORRECT)
+    N = 512 ** 3
+    assert N + N // 8 <= n <= N + N // 8 + 4096
+    with pytest.raises(pmsz.PmszError) as e:
+        pmsz.workspace_size(pmsz.Grid(2, pmsz.F32, 4, 4, 3), pmsz.WS_CORRECT)
+    assert e.value.status == 1
+    with pytest.raises(pmsz.PmszError):
+        pmsz.workspace_size(pmsz.Grid(3, pmsz.F32, 1 << 11, 1 << 11, 1 << 10), pmsz.WS_CORRECT)
+    with pytest.raises(pmsz.PmszError):
+        pmsz.workspace_size(pmsz.Grid(3, 7, 4, 4, 4), pmsz.WS_CORRECT)
+    st = pmsz.Stats()
+    # NULL pointers are rejected before any device work
+    code = lib.pmsz_correct(ctypes.byref(g), None, None, 0.1, None, None, 0, 10,
+                            ctypes.byref(st), None)
+    assert code == 1
+    assert b"NULL" in lib.pmsz_last_error()
