@@ -1,0 +1,217 @@
+"""Benchmark of the pMSz correction on one MI355X.
+
+A step is one full correction (pmsz_correct: directions of f, validation of
+fhat, every detect/apply round until convergence) of the 512^3 binary32
+Perlin workload (6 octaves, 8 lattice cells, eps = 1e-4 of the unit range,
+seed 512): one GPU's share of the paper's weak-scaling study.  Inputs are
+resident in HBM before timing starts; every timed step corrects its own copy
+of fhat.  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Gvoxels/s corrected at 512^3 fp32 ε=1e-4; batched vs plain; serve p50/p99 ms"
+HBM_PEAK_GBS = 8000.0
+ENGINE_KERNEL = "k_engine<float>"
+ENGINE_SOURCES = ["engine.hip", "engine.hpp", "tiles.hpp", "common.hpp"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "engine_perlin512_f32_traffic.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for name in ENGINE_SOURCES:
+        with open(os.path.join(ROOT, "paper_2601_01787_amd", "csrc", name), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(voxels, swept, edits, s):
+    """Bytes the method must move (per-unit figures): once per vertex f and fhat
+    read and its direction byte written (2s+1); per vertex examined by a later
+    detect pass g and the direction byte read and a flag bit written
+    (s + 1 + 1/8); per edit f and g read and g written (3s)."""
+    return voxels * (2 * s + 1) + max(swept - voxels, 0) * (s + 1.125) + edits * 3 * s
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter runs, if they
+    were taken on the current engine source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    with open(TRAFFIC_FILE) as fh:
+        t = json.load(fh)
+    if t.get("source_hash") != source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def cpu_baseline(f, fhat, xi, planes):
+    """The oracle (untuned) on a bounded sample: the first `planes` z-planes of
+    the same field, corrected as a field of their own."""
+    import oracle
+    fs = f[:planes].cpu().numpy().copy()
+    hs = fhat[:planes].cpu().numpy().copy()
+    t0 = time.perf_counter()
+    _, st = oracle.correct(fs, hs, xi)
+    dt = time.perf_counter() - t0
+    return {"value": fs.size / dt / 1e9, "unit": "Gvoxels/s", "cores": oracle.threads(),
+            "kind": "oracle",
+            "sample": "first %d z-planes (%dx%dx%d, %d vertices) of the same field, corrected "
+                      "as their own field: %d rounds, %.1f s" % (
+                          planes, planes, fs.shape[1], fs.shape[2], fs.size,
+                          st["iterations"], dt)}
+
+
+def bench_batched(dev, n_fields, seed):
+    """Uneven 2D batch: n_fields Gaussian-peak fields, sizes log-uniform in
+    [256, 4096] per axis, relative bound from {1e-2, 1e-3, 1e-4}.  Plain =
+    one pmsz_correct per field in sequence; batched = one
+    pmsz_correct_batched.  Results must be bit-identical."""
+    import torch
+
+    import paper_2601_01787_amd as pmsz
+    import synth
+    cases = []
+    for c in synth.batch_recipe(n_fields, seed):
+        f, fhat, xi = synth.make_2d_case(c["nx"], c["ny"], c["rel_eps"], c["seed"], device=dev)
+        cases.append((f, fhat, xi))
+    vox = sum(f.numel() for f, _, _ in cases)
+    torch.cuda.synchronize()
+    # warm both paths on one field
+    pmsz.correct(cases[0][0], cases[0][1], cases[0][2])
+    pmsz.correct_batched([(cases[0][0], cases[0][1].clone(), cases[0][2])])
+    g_plain = [fh.clone() for _, fh, _ in cases]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st_plain = [pmsz.correct(f, g, xi, inplace=True)[1] for (f, _, xi), g in zip(cases, g_plain)]
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    g_batch = [fh.clone() for _, fh, _ in cases]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st_batch = pmsz.correct_batched([(f, g, xi) for (f, _, xi), g in zip(cases, g_batch)])
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    same = all(torch.equal(a, b) for a, b in zip(g_plain, g_batch)) and st_plain == st_batch
+    return {"fields": n_fields, "voxels": vox,
+            "plain_gvox_s": round(vox / t_plain / 1e9, 3),
+            "batched_gvox_s": round(vox / t_batch / 1e9, 3),
+            "plain_ms": round(t_plain * 1e3, 2), "batched_ms": round(t_batch * 1e3, 2),
+            "speedup": round(t_plain / t_batch, 2), "identical": bool(same),
+            "max_iterations": max(s["iterations"] for s in st_batch)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-planes", type=int, default=512)
+    ap.add_argument("--batch-fields", type=int, default=256,
+                    help="fields of the uneven 2D batch (0 skips the batched comparison)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="also run one plain device copy of this size (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2601_01787_amd as pmsz
+    import synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log("generating 512^3 Perlin workload on", torch.cuda.get_device_name(dev))
+    f, fhat, xi = synth.large_perlin_case(device=dev)
+    n_vox = f.numel()
+    grid = pmsz.grid_of(f)
+    ws = pmsz.workspace(grid, pmsz.WS_CORRECT, dev)
+    K, W = args.steps, args.warmup
+    gs = [fhat.clone() for _ in range(W + K)]
+    torch.cuda.synchronize()
+
+    if args.copy_probe_mib:
+        src = torch.empty(args.copy_probe_mib << 18, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: %d MiB read, %d MiB written" % (args.copy_probe_mib, args.copy_probe_mib))
+        del src, dst
+
+    log("warmup", W)
+    for i in range(W):
+        _, st = pmsz.correct(f, gs[i], xi, inplace=True, ws=ws)
+        assert st["status"] == "OK", st
+    torch.cuda.synchronize()
+
+    log("timing", K, "steps")
+    eng_ms, tims, stats = [], [], []
+    t0 = time.perf_counter()
+    for i in range(K):
+        _, st = pmsz.correct(f, gs[W + i], xi, inplace=True, ws=ws)
+        tm = pmsz.last_timing()
+        eng_ms.append(tm["engine_ms"])
+        tims.append(tm)
+        stats.append(st)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_per_step = (t1 - t0) * 1e3 / K
+    value = n_vox / (ms_per_step * 1e-3) / 1e9
+    for st in stats:
+        assert st["status"] == "OK" and st["iterations"] == stats[0]["iterations"], st
+
+    tm = tims[-1]
+    s = f.element_size()
+    alg = algorithmic_bytes(tm["voxels"], tm["swept"], tm["edits"], s)
+    avg_ms = sum(eng_ms) / len(eng_ms)
+    achieved = alg / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(), "kernel": ENGINE_KERNEL,
+                "kernel_avg_ms": round(avg_ms, 4), "algorithmic_bytes": int(alg)}
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Gvoxels/s", "n_gpus": 1,
+        "steps": K, "warmup": W, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "perlin 512^3 f32, 6 octaves, 8 cells, eps 1e-4, seed 512; "
+                               "one field per launch", "voxels": n_vox,
+                   "parallelism": "1 GPU"},
+        "roofline": roofline,
+        "detail": {"iterations": stats[0]["iterations"], "edits": stats[0]["steps_applied"],
+                   "mismatch_initial": stats[0]["mismatch_initial"], "rounds": tm["rounds"],
+                   "swept_vertices": tm["swept"], "tiles": tm["tiles"], "grid": tm["grid"],
+                   "engine_ms_per_step": round(avg_ms, 4)},
+    }
+    del gs
+    torch.cuda.empty_cache()
+    if args.batch_fields:
+        log("batched vs plain on", args.batch_fields, "2D fields")
+        out["batched"] = bench_batched(dev, args.batch_fields, 256)
+        torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) on", args.cpu_planes, "planes")
+        out["cpu_baseline"] = cpu_baseline(f, fhat, xi, args.cpu_planes)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -171,6 +171,60 @@ int pmsz_labels(const pmsz_grid* grid, const uint8_t* dirs, int32_t* max_label,
 int pmsz_verify(const pmsz_grid* grid, const void* f, const void* g, const void* fhat,
                 double xi, void* ws, size_t ws_bytes, pmsz_report* report, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Serving sessions (continuous batching).  Fields are admitted and retired
+ * between steps; one step is one launch of the persistent correction kernel
+ * over every admitted, unfinished field, running at most max_rounds rounds.
+ * A field's iterate sequence, result and statistics are those of
+ * pmsz_correct on the same field alone, whatever else shares its steps.
+ * All calls except pmsz_session_sync are asynchronous on the session stream.
+ * ------------------------------------------------------------------------- */
+typedef struct pmsz_session pmsz_session;
+
+/* Device bytes of a session's own workspace for up to max_fields fields. */
+int pmsz_session_workspace_size(int32_t max_fields, size_t* bytes);
+/* Device bytes of the per-field workspace of one admitted field (its flag
+ * bitmap, direction bytes, tile activity and iteration state). */
+int pmsz_field_workspace_size(const pmsz_grid* grid, size_t* bytes);
+/* Create a session for fields of one dtype.  ws: device, 256-byte aligned,
+ * pmsz_session_workspace_size(max_fields) bytes, owned by the caller until
+ * pmsz_session_destroy.  stream: the hipStream_t every step runs on. */
+int pmsz_session_create(int32_t dtype, int32_t max_fields, void* ws, size_t ws_bytes,
+                        void* stream, pmsz_session** out);
+/* Admit a field: f and g (fhat on entry) as in pmsz_correct, plus its own
+ * field workspace (device, 256-byte aligned).  It joins the next step.  The
+ * caller keeps f, g and field_ws alive until the field is removed.  *handle
+ * receives the field's id.  Fails with PMSZ_ERR_OOM when the session is full. */
+int pmsz_session_add(pmsz_session* s, const pmsz_field* field, int64_t max_iters, void* field_ws,
+                     size_t field_ws_bytes, int32_t* handle);
+/* Enqueue one step (max_rounds >= 1).  At most one step may be in flight. */
+int pmsz_session_step(pmsz_session* s, int64_t max_rounds);
+/* Wait for the step in flight and collect its results; *n_done (nullable)
+ * receives how many fields finished in it. */
+int pmsz_session_sync(pmsz_session* s, int32_t* n_done);
+/* Statistics of a field after the last sync (host structs); *done is 1 once
+ * the field has finished (stats->status is then final). */
+int pmsz_session_result(pmsz_session* s, int32_t handle, pmsz_stats* stats, int32_t* done);
+/* Retire a field (no step in flight); its buffers may be freed afterwards. */
+int pmsz_session_remove(pmsz_session* s, int32_t handle);
+int pmsz_session_destroy(pmsz_session* s);
+
+/* Measurements of the last pmsz_correct / pmsz_correct_batched call made on
+ * this thread (host struct): the duration of its persistent correction
+ * kernel, timed with HIP events recorded on the caller's stream around that
+ * launch, and the work it did.  Used by the benchmark for roofline figures. */
+typedef struct {
+  double engine_ms;  /* duration of the correction kernel launch             */
+  int64_t rounds;    /* detect/apply rounds it ran                            */
+  int64_t swept;     /* vertices examined by detect passes, all rounds        */
+  int64_t edits;     /* value changes, all fields                             */
+  int64_t voxels;    /* vertices of the batch                                 */
+  int64_t tiles;     /* tiles of the batch                                    */
+  int32_t grid;      /* blocks of the cooperative launch                      */
+  int32_t reserved;
+} pmsz_timing;
+int pmsz_last_timing(pmsz_timing* out);
+
 /* Name of a status code (static string). */
 const char* pmsz_status_string(int status);
 

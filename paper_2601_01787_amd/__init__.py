@@ -26,7 +26,11 @@ DEFAULT_MAX_ITERS = 1 << 40
 
 EXPORTS = ("pmsz_workspace_size", "pmsz_directions", "pmsz_correct",
            "pmsz_batched_workspace_size", "pmsz_correct_batched", "pmsz_labels",
-           "pmsz_verify", "pmsz_status_string", "pmsz_last_error")
+           "pmsz_verify", "pmsz_last_timing", "pmsz_session_workspace_size",
+           "pmsz_field_workspace_size", "pmsz_session_create", "pmsz_session_add",
+           "pmsz_session_step", "pmsz_session_sync", "pmsz_session_result",
+           "pmsz_session_remove", "pmsz_session_destroy", "pmsz_status_string",
+           "pmsz_last_error")
 
 
 class PmszError(RuntimeError):
@@ -64,6 +68,15 @@ class Report(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Timing(ctypes.Structure):
+    _fields_ = [("engine_ms", ctypes.c_double), ("rounds", ctypes.c_int64),
+                ("swept", ctypes.c_int64), ("edits", ctypes.c_int64), ("voxels", ctypes.c_int64),
+                ("tiles", ctypes.c_int64), ("grid", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+
+
 class Field(ctypes.Structure):
     _fields_ = [("grid", Grid), ("f", ctypes.c_void_p), ("g", ctypes.c_void_p),
                 ("xi", ctypes.c_double)]
@@ -92,6 +105,18 @@ def load():
                                        ctypes.POINTER(Stats), vp]
     L.pmsz_labels.argtypes = [G, vp, vp, vp, vp, sz, vp]
     L.pmsz_verify.argtypes = [G, vp, vp, vp, dbl, vp, sz, ctypes.POINTER(Report), vp]
+    L.pmsz_last_timing.argtypes = [ctypes.POINTER(Timing)]
+    L.pmsz_session_workspace_size.argtypes = [i32, ctypes.POINTER(sz)]
+    L.pmsz_field_workspace_size.argtypes = [G, ctypes.POINTER(sz)]
+    L.pmsz_session_create.argtypes = [i32, i32, vp, sz, vp, ctypes.POINTER(vp)]
+    L.pmsz_session_add.argtypes = [vp, ctypes.POINTER(Field), i64, vp, sz,
+                                   ctypes.POINTER(ctypes.c_int32)]
+    L.pmsz_session_step.argtypes = [vp, i64]
+    L.pmsz_session_sync.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
+    L.pmsz_session_result.argtypes = [vp, i32, ctypes.POINTER(Stats),
+                                      ctypes.POINTER(ctypes.c_int32)]
+    L.pmsz_session_remove.argtypes = [vp, i32]
+    L.pmsz_session_destroy.argtypes = [vp]
     L.pmsz_status_string.argtypes = [ctypes.c_int]
     L.pmsz_status_string.restype = ctypes.c_char_p
     L.pmsz_last_error.restype = ctypes.c_char_p
@@ -205,6 +230,88 @@ def correct_batched(fields, *, max_iters=DEFAULT_MAX_ITERS):
                                        ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream))
     _raise_if(code, allowed=(0, 2, 3, 4, 5))
     return [st[i].as_dict() for i in range(n)]
+
+
+def last_timing():
+    """Engine duration (HIP events on the caller's stream) and work of the last
+    correction made on this thread."""
+    t = Timing()
+    _raise_if(load().pmsz_last_timing(ctypes.byref(t)))
+    return t.as_dict()
+
+
+def field_workspace_size(grid):
+    """Device bytes of one admitted field's workspace in a serving session."""
+    n = ctypes.c_size_t()
+    _raise_if(load().pmsz_field_workspace_size(ctypes.byref(grid), ctypes.byref(n)))
+    return n.value
+
+
+class Session:
+    """A serving session of the C library (continuous batching): fields are
+    admitted and retired between steps; each step runs the persistent
+    correction kernel over every admitted, unfinished field."""
+
+    def __init__(self, dtype, max_fields, device):
+        L = load()
+        self._dt = F32 if dtype == torch.float32 else F64
+        n = ctypes.c_size_t()
+        _raise_if(L.pmsz_session_workspace_size(int(max_fields), ctypes.byref(n)))
+        buf = torch.empty(n.value + 256, dtype=torch.uint8, device=device)
+        off = (-buf.data_ptr()) % 256
+        self._ws = buf[off:off + n.value]
+        self._stream = torch.cuda.current_stream(device)
+        h = ctypes.c_void_p()
+        _raise_if(L.pmsz_session_create(self._dt, int(max_fields),
+                                        ctypes.c_void_p(self._ws.data_ptr()), n.value,
+                                        ctypes.c_void_p(self._stream.cuda_stream),
+                                        ctypes.byref(h)))
+        self._h = h
+        self._keep = {}
+
+    def add(self, f, g, xi, ws, max_iters=DEFAULT_MAX_ITERS):
+        """Admit (f, g) -- g holds fhat and is corrected in place -- with its
+        field workspace `ws` (a 256-byte aligned uint8 device tensor)."""
+        for t, name in ((f, "f"), (g, "g"), (ws, "ws")):
+            _dev(t, name)
+        fld = Field(grid_of(f), f.data_ptr(), g.data_ptr(), float(xi))
+        h = ctypes.c_int32()
+        _raise_if(load().pmsz_session_add(self._h, ctypes.byref(fld), int(max_iters),
+                                          ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                          ctypes.byref(h)))
+        self._keep[h.value] = (f, g, ws)
+        return h.value
+
+    def step(self, max_rounds):
+        _raise_if(load().pmsz_session_step(self._h, int(max_rounds)))
+
+    def sync(self):
+        n = ctypes.c_int32()
+        _raise_if(load().pmsz_session_sync(self._h, ctypes.byref(n)))
+        return n.value
+
+    def result(self, handle):
+        st = Stats()
+        done = ctypes.c_int32()
+        _raise_if(load().pmsz_session_result(self._h, int(handle), ctypes.byref(st),
+                                             ctypes.byref(done)))
+        return st.as_dict(), bool(done.value)
+
+    def remove(self, handle):
+        _raise_if(load().pmsz_session_remove(self._h, int(handle)))
+        self._keep.pop(handle, None)
+
+    def close(self):
+        if self._h:
+            load().pmsz_session_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def labels(dirs):

@@ -9,6 +9,10 @@
 #include <algorithm>
 #include <string>
 
+#include <unordered_map>
+#include <vector>
+
+#include "engine.hpp"
 #include "launch.hpp"
 
 using namespace pmsz;
@@ -61,18 +65,6 @@ double xi_in_type(int dtype, double xi) {
   return (double)x;
 }
 
-struct CorrectLayout {
-  size_t ctl, bm, dirs, total;
-};
-CorrectLayout correct_layout(const Geo& G) {
-  CorrectLayout L;
-  L.ctl = 0;
-  L.bm = align_up(sizeof(Ctl));
-  L.dirs = L.bm + align_up((size_t)bitmap_words(G.n) * 4);
-  L.total = L.dirs + align_up((size_t)G.n);
-  return L;
-}
-
 struct VerifyLayout {
   size_t counts, df, dg, lfx, lfn, lgx, lgn, flag, total;
 };
@@ -91,38 +83,221 @@ VerifyLayout verify_layout(const Geo& G) {
   return L;
 }
 
-// Per-thread pinned slots for reading the control block back while the next
-// rounds are already queued.
-struct HostSlots {
-  Ctl* pinned = nullptr;
+// ---------------------------------------------------------------------------
+// Workspace plan of the correction engine for n fields:
+//   [EngineCtl][FieldDesc x n][FieldIter x n]
+//   [field 0: state, activity, bitmap] ... [field n-1: ...]
+//   [directions of field 0] ... [directions of field n-1]
+// Every region starts on a 256-byte boundary; everything before the direction
+// bytes is cleared by one kernel before the launch.
+// ---------------------------------------------------------------------------
+struct BatchPlan {
+  size_t ctl = 0, desc = 0, out = 0, fields = 0, dirs = 0, total = 0;
+  int64_t total_tiles = 0, total_segs = 0;
+  std::vector<FieldDesc> fd;
+  std::vector<size_t> field_off, dirs_off;
+};
+
+// Descriptor of one field with everything but its device pointers.
+int describe_field(const pmsz_field& fld, int64_t max_iters, int dirs_given, FieldDesc& d) {
+  const pmsz_grid& g = fld.grid;
+  int r = check_grid(&g);
+  if (r) return r;
+  if (!isfinite(fld.xi) || fld.xi < 0) return fail(PMSZ_ERR_INVALID_ARG, "xi must be finite and >= 0");
+  memset(&d, 0, sizeof(d));
+  d.f = fld.f;
+  d.g = fld.g;
+  d.geo = make_tile_geo(g.ndim, g.nx, g.ny, g.nz, engine_chunk(g.ndim, g.nx, g.ny, g.nz));
+  d.xi_t = xi_in_type(g.dtype, fld.xi);
+  d.max_iters = max_iters;
+  d.words = bitmap_words(d.geo.n);
+  d.dirs_given = dirs_given;
+  return PMSZ_OK;
+}
+
+int plan_batch(int32_t n, const pmsz_field* fields, const uint8_t* const* dirs_given,
+               int64_t max_iters, BatchPlan& P) {
+  P.fd.resize(n);
+  P.field_off.resize(n);
+  P.dirs_off.resize(n);
+  size_t fbytes = 0, dbytes = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    if (fields[i].grid.dtype != fields[0].grid.dtype)
+      return fail(PMSZ_ERR_INVALID_ARG, "all fields of a batch must share one dtype");
+    FieldDesc& d = P.fd[i];
+    int r = describe_field(fields[i], max_iters, (dirs_given && dirs_given[i]) ? 1 : 0, d);
+    if (r) return r;
+    d.tile_base = P.total_tiles;
+    d.seg_base = P.total_segs;
+    P.total_tiles += tile_count(d.geo);
+    P.total_segs += (d.words + kSegWords - 1) / kSegWords;
+    const FieldLayout L = field_layout(d.geo, true);
+    P.field_off[i] = fbytes;
+    fbytes += L.total;
+    P.dirs_off[i] = dbytes;
+    if (!d.dirs_given) dbytes += align_up((size_t)d.geo.n);
+  }
+  P.ctl = 0;
+  P.desc = align_up(sizeof(EngineCtl));
+  P.out = P.desc + align_up(sizeof(FieldDesc) * (size_t)n);
+  P.fields = P.out + align_up(sizeof(FieldIter) * (size_t)n);
+  P.dirs = P.fields + fbytes;
+  P.total = P.dirs + dbytes;
+  return PMSZ_OK;
+}
+
+// Pinned staging for descriptors going up and states coming back; the calls
+// that use it synchronise before returning, so one buffer per thread serves.
+struct Staging {
+  void* p = nullptr;
+  size_t cap = 0;
+  ~Staging() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+thread_local Staging t_stage;
+
+int staging(Staging& s, size_t bytes, void** out) {
+  if (s.cap < bytes) {
+    if (s.p) (void)hipHostFree(s.p);
+    s.p = nullptr;
+    s.cap = 0;
+    HIP_TRY(hipHostMalloc(&s.p, bytes, hipHostMallocDefault));
+    s.cap = bytes;
+  }
+  *out = s.p;
+  return PMSZ_OK;
+}
+
+// Events around the engine launch and the figures of the last run.
+struct Timing {
   hipEvent_t ev[2] = {nullptr, nullptr};
-  int ok = 0;
-  ~HostSlots() {
-    if (pinned) (void)hipHostFree(pinned);
+  pmsz_timing last;
+  ~Timing() {
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
   }
 };
-thread_local HostSlots t_slots;
+thread_local Timing t_timing;
 
-int host_slots(HostSlots** out) {
-  HostSlots& s = t_slots;
-  if (!s.ok) {
-    HIP_TRY(hipHostMalloc((void**)&s.pinned, 2 * sizeof(Ctl), hipHostMallocDefault));
-    for (auto& e : s.ev) HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    s.ok = 1;
+void fill_stats(const FieldIter& it, pmsz_stats& o) {
+  memset(&o, 0, sizeof(o));
+  o.iterations = (int64_t)it.k;
+  o.steps_applied = (int64_t)it.steps;
+  o.flagged_final = (int64_t)it.flagged_final;
+  o.stalled_flags = (int64_t)it.stalled_final;
+  o.mismatch_initial = (int64_t)it.mism0;
+  o.status = it.status;
+  if (it.status == PMSZ_ERR_NONFINITE || it.status == PMSZ_ERR_INPUT_BOUND) {
+    o.iterations = 0;
+    o.steps_applied = 0;
   }
-  *out = &s;
+}
+
+// Run the engine to completion on a planned batch; fills stats[n].
+int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* ws,
+              pmsz_stats* stats, hipStream_t s) {
+  const int32_t n = (int32_t)P.fd.size();
+  char* base = (char*)ws;
+  for (int32_t i = 0; i < n; ++i) {
+    FieldDesc& d = P.fd[i];
+    const FieldLayout L = field_layout(d.geo, true);
+    char* fb = base + P.fields + P.field_off[i];
+    d.st = (FieldState*)(fb + L.state);
+    d.act = (uint8_t*)(fb + L.act);
+    d.bm = (uint32_t*)(fb + L.bm);
+    d.dirs = d.dirs_given ? (uint8_t*)dirs_given[i] : (uint8_t*)(base + P.dirs + P.dirs_off[i]);
+  }
+  const size_t up = sizeof(FieldDesc) * (size_t)n;
+  const size_t down = sizeof(EngineCtl) + sizeof(FieldIter) * (size_t)n;
+  void* stage;
+  int r = staging(t_stage, up > down ? up : down, &stage);
+  if (r) return r;
+  memcpy(stage, P.fd.data(), up);
+  EngineCtl* ctl = (EngineCtl*)(base + P.ctl);
+  FieldIter* out = (FieldIter*)(base + P.out);
+  HIP_TRY(engine_zero(base, P.dirs, s));
+  HIP_TRY(hipMemcpyAsync(base + P.desc, stage, up, hipMemcpyHostToDevice, s));
+  EngineArgs a;
+  a.fd = (const FieldDesc*)(base + P.desc);
+  a.out = out;
+  a.nf = n;
+  a.has_fresh = 1;
+  a.ctl = ctl;
+  a.total_tiles = P.total_tiles;
+  a.total_segs = P.total_segs;
+  a.max_rounds = -1;
+  Timing& tm = t_timing;
+  if (!tm.ev[0])
+    for (auto& e : tm.ev) HIP_TRY(hipEventCreate(&e));
+  int grid = 0;
+  HIP_TRY(hipEventRecord(tm.ev[0], s));
+  HIP_TRY(engine_launch(dtype, a, s, &grid));
+  HIP_TRY(hipEventRecord(tm.ev[1], s));
+  // the staging buffer is reused for the results: the upload above is
+  // stream-ordered before this copy, so it has been consumed
+  HIP_TRY(hipMemcpyAsync(stage, ctl, sizeof(EngineCtl), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync((char*)stage + sizeof(EngineCtl), out, sizeof(FieldIter) * (size_t)n,
+                         hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  const EngineCtl* hc = (const EngineCtl*)stage;
+  const FieldIter* hs = (const FieldIter*)((char*)stage + sizeof(EngineCtl));
+  if (hc->error) return fail(PMSZ_ERR_DEVICE, "grid barrier timed out in the correction engine");
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, tm.ev[0], tm.ev[1]));
+  memset(&tm.last, 0, sizeof(tm.last));
+  tm.last.engine_ms = ms;
+  tm.last.rounds = (int64_t)hc->rounds;
+  tm.last.tiles = P.total_tiles;
+  tm.last.grid = grid;
+  int first = PMSZ_OK;
+  for (int32_t i = 0; i < n; ++i) {
+    if (!hs[i].done) return fail(PMSZ_ERR_DEVICE, "field %d did not finish", i);
+    fill_stats(hs[i], stats[i]);
+    tm.last.swept += (int64_t)hs[i].swept;
+    tm.last.edits += (int64_t)hs[i].steps;
+    tm.last.voxels += P.fd[i].geo.n;
+    if (hs[i].status != PMSZ_OK && first == PMSZ_OK) first = hs[i].status;
+  }
+  if (first != PMSZ_OK) return fail(first, "%s", pmsz_status_string(first));
   return PMSZ_OK;
 }
 
-int rounds_per_poll() {
-  static int v = [] {
-    const char* e = getenv("PMSZ_ROUNDS_PER_POLL");
-    int r = e ? atoi(e) : 4;
-    return r < 1 ? 1 : (r > 64 ? 64 : r);
-  }();
-  return v;
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Serving sessions: fields are admitted and retired between engine launches;
+// each launch (a step) runs up to max_rounds rounds of every unfinished field.
+// ---------------------------------------------------------------------------
+struct pmsz_session {
+  int dtype = 0;
+  int32_t cap = 0;
+  char* ws = nullptr;  // device: [EngineCtl][FieldDesc x cap][FieldIter x cap]
+  size_t desc_off = 0, out_off = 0;
+  Staging up, down;
+  hipEvent_t ev = nullptr;
+  hipStream_t stream = nullptr;
+  bool pending = false;
+  unsigned long long epoch = 0;
+  int32_t next_handle = 1;
+  struct Entry {
+    FieldDesc d;
+    int done = 0;
+    int started = 0;  // its first round (directions of f, validation) has run
+    pmsz_stats st;
+  };
+  std::unordered_map<int32_t, Entry> fields;
+  std::vector<int32_t> order;  // insertion order of live handles
+  std::vector<int32_t> stepped;  // handles of the last step, in descriptor order
+  pmsz_timing last;
+};
+
+namespace {
+
+static size_t session_ctl_bytes(int32_t cap) {
+  return align_up(sizeof(EngineCtl)) + align_up(sizeof(FieldDesc) * (size_t)cap) +
+         align_up(sizeof(FieldIter) * (size_t)cap);
 }
 
 int label_pass(int32_t* lab, int64_t n, unsigned int* flag, hipStream_t s) {
@@ -171,13 +346,27 @@ const char* pmsz_status_string(int status) {
 
 const char* pmsz_last_error(void) { return g_last_error.c_str(); }
 
+int pmsz_last_timing(pmsz_timing* out) {
+  if (!out) return fail(PMSZ_ERR_INVALID_ARG, "NULL argument");
+  *out = t_timing.last;
+  return PMSZ_OK;
+}
+
 int pmsz_workspace_size(const pmsz_grid* grid, int op, size_t* bytes) {
   int r = check_grid(grid);
   if (r) return r;
   if (!bytes) return fail(PMSZ_ERR_INVALID_ARG, "bytes is NULL");
   const Geo G = make_geo(*grid);
   switch (op) {
-    case PMSZ_WS_CORRECT: *bytes = correct_layout(G).total; break;
+    case PMSZ_WS_CORRECT: {
+      pmsz_field one;
+      memset(&one, 0, sizeof(one));
+      one.grid = *grid;
+      BatchPlan P;
+      if ((r = plan_batch(1, &one, nullptr, 0, P))) return r;
+      *bytes = P.total;
+      break;
+    }
     case PMSZ_WS_VERIFY: *bytes = verify_layout(G).total; break;
     case PMSZ_WS_LABELS: *bytes = kAlign; break;
     default: return fail(PMSZ_ERR_INVALID_ARG, "unknown workspace kind %d", op);
@@ -203,83 +392,17 @@ int pmsz_correct(const pmsz_grid* grid, const void* f, void* g, double xi,
   if (!isfinite(xi) || xi < 0) return fail(PMSZ_ERR_INVALID_ARG, "xi must be finite and >= 0");
   if (max_iters < 0) return fail(PMSZ_ERR_INVALID_ARG, "max_iters must be >= 0");
   if ((uintptr_t)ws % kAlign) return fail(PMSZ_ERR_INVALID_ARG, "workspace not 256-byte aligned");
-  const Geo G = make_geo(*grid);
-  const CorrectLayout L = correct_layout(G);
-  if (ws_bytes < L.total)
-    return fail(PMSZ_ERR_OOM, "workspace %zu bytes, need %zu", ws_bytes, L.total);
+  pmsz_field one;
+  one.grid = *grid;
+  one.f = f;
+  one.g = g;
+  one.xi = xi;
+  const uint8_t* given[1] = {dirs_f};
+  BatchPlan P;
+  if ((r = plan_batch(1, &one, given, max_iters, P))) return r;
+  if (ws_bytes < P.total) return fail(PMSZ_ERR_OOM, "workspace %zu bytes, need %zu", ws_bytes, P.total);
   memset(stats, 0, sizeof(*stats));
-  HostSlots* hs;
-  if ((r = host_slots(&hs))) return r;
-
-  hipStream_t s = (hipStream_t)stream;
-  char* base = (char*)ws;
-  Ctl* ctl = (Ctl*)(base + L.ctl);
-  uint32_t* bm = (uint32_t*)(base + L.bm);
-  const double xt = xi_in_type(grid->dtype, xi);
-  const int dt = grid->dtype;
-
-  HIP_TRY(launch_init(ctl, bm, bitmap_words(G.n), s));
-  if (!dirs_f) {
-    uint8_t* d = (uint8_t*)(base + L.dirs);
-    HIP_TRY(launch_dirs(dt, f, G, d, s));
-    dirs_f = d;
-  }
-  HIP_TRY(launch_validate(dt, f, g, G.n, xt, ctl, s));
-
-  // Rounds are queued in groups; the control block of group j is read while
-  // group j+1 runs.  Rounds queued after the run ended return at once.
-  // Every round either ends the run or applies one edit round, so a run that
-  // is not done after R rounds must report k == R; anything else means the
-  // control block is broken and the loop stops instead of spinning.
-  const int K = rounds_per_poll();
-  int slot = 0, have_prev = 0;
-  long long queued = 0, queued_at[2] = {0, 0};
-  const Ctl* fin = nullptr;
-  for (;;) {
-    for (int k = 0; k < K; ++k) {
-      HIP_TRY(launch_detect(dt, g, G, dirs_f, bm, ctl, s));
-      HIP_TRY(launch_apply(dt, f, g, G, bm, xt, ctl, max_iters, s));
-    }
-    queued += K;
-    queued_at[slot] = queued;
-    HIP_TRY(hipMemcpyAsync(&hs->pinned[slot], ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipEventRecord(hs->ev[slot], s));
-    if (have_prev) {
-      const int p = slot ^ 1;
-      HIP_TRY(hipEventSynchronize(hs->ev[p]));
-      if (hs->pinned[p].done) {
-        fin = &hs->pinned[p];
-        break;
-      }
-      if ((long long)hs->pinned[p].k != queued_at[p]) {
-        (void)hipStreamSynchronize(s);
-        return fail(PMSZ_ERR_DEVICE, "control block inconsistent: k=%llu after %lld rounds",
-                    hs->pinned[p].k, queued_at[p]);
-      }
-    }
-    have_prev = 1;
-    slot ^= 1;
-  }
-  HIP_TRY(hipStreamSynchronize(s));
-  stats->iterations = (int64_t)fin->k;
-  stats->steps_applied = (int64_t)fin->steps;
-  stats->flagged_final = (int64_t)fin->flagged_final;
-  stats->stalled_flags = (int64_t)fin->stalled_final;
-  stats->mismatch_initial = (int64_t)fin->mism0;
-  stats->status = fin->status;
-  if (fin->status == PMSZ_ERR_NONFINITE || fin->status == PMSZ_ERR_INPUT_BOUND) {
-    stats->iterations = 0;
-    stats->steps_applied = 0;
-    stats->flagged_final = 0;
-    stats->stalled_flags = 0;
-    stats->mismatch_initial = 0;
-    return fail(fin->status, "%s: %llu non-finite, %llu outside the bound",
-                pmsz_status_string(fin->status), fin->bad_nonfinite, fin->bad_bound);
-  }
-  if (fin->status != PMSZ_OK)
-    return fail(fin->status, "%s after %lld rounds", pmsz_status_string(fin->status),
-                (long long)fin->k);
-  return PMSZ_OK;
+  return run_batch(grid->dtype, P, given, ws, stats, (hipStream_t)stream);
 }
 
 int pmsz_labels(const pmsz_grid* grid, const uint8_t* dirs, int32_t* max_label,
@@ -340,31 +463,210 @@ int pmsz_verify(const pmsz_grid* grid, const void* f, const void* g, const void*
 
 int pmsz_batched_workspace_size(int32_t n, const pmsz_field* fields, size_t* bytes) {
   if (n < 0 || (n > 0 && !fields) || !bytes) return fail(PMSZ_ERR_INVALID_ARG, "bad batch");
-  size_t tot = 0;
-  for (int32_t i = 0; i < n; ++i) {
-    int r = check_grid(&fields[i].grid);
-    if (r) return r;
-    tot = std::max(tot, correct_layout(make_geo(fields[i].grid)).total);
-  }
-  *bytes = tot;
+  BatchPlan P;
+  int r = plan_batch(n, fields, nullptr, 0, P);
+  if (r) return r;
+  *bytes = P.total;
   return PMSZ_OK;
 }
 
 int pmsz_correct_batched(int32_t n, const pmsz_field* fields, void* ws, size_t ws_bytes,
                          int64_t max_iters, pmsz_stats* stats, void* stream) {
-  size_t need;
-  int r = pmsz_batched_workspace_size(n, fields, &need);
+  if (n < 0 || (n > 0 && (!fields || !stats || !ws)))
+    return fail(PMSZ_ERR_INVALID_ARG, "NULL argument");
+  if (max_iters < 0) return fail(PMSZ_ERR_INVALID_ARG, "max_iters must be >= 0");
+  if (n == 0) return PMSZ_OK;
+  if ((uintptr_t)ws % kAlign) return fail(PMSZ_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  for (int32_t i = 0; i < n; ++i)
+    if (!fields[i].f || !fields[i].g) return fail(PMSZ_ERR_INVALID_ARG, "field %d: NULL array", i);
+  BatchPlan P;
+  int r = plan_batch(n, fields, nullptr, max_iters, P);
   if (r) return r;
-  if (!stats || (n > 0 && !ws)) return fail(PMSZ_ERR_INVALID_ARG, "NULL argument");
-  if (ws_bytes < need) return fail(PMSZ_ERR_OOM, "workspace %zu bytes, need %zu", ws_bytes, need);
-  int first = PMSZ_OK;
-  for (int32_t i = 0; i < n; ++i) {
-    r = pmsz_correct(&fields[i].grid, fields[i].f, fields[i].g, fields[i].xi, nullptr, ws,
-                     ws_bytes, max_iters, &stats[i], stream);
-    if (r == PMSZ_ERR_INVALID_ARG || r == PMSZ_ERR_DEVICE || r == PMSZ_ERR_OOM) return r;
-    if (r != PMSZ_OK && first == PMSZ_OK) first = r;
+  if (ws_bytes < P.total) return fail(PMSZ_ERR_OOM, "workspace %zu bytes, need %zu", ws_bytes, P.total);
+  return run_batch(fields[0].grid.dtype, P, nullptr, ws, stats, (hipStream_t)stream);
+}
+
+
+int pmsz_session_workspace_size(int32_t max_fields, size_t* bytes) {
+  if (max_fields < 1 || !bytes) return fail(PMSZ_ERR_INVALID_ARG, "max_fields must be >= 1");
+  *bytes = session_ctl_bytes(max_fields);
+  return PMSZ_OK;
+}
+
+int pmsz_field_workspace_size(const pmsz_grid* grid, size_t* bytes) {
+  int r = check_grid(grid);
+  if (r) return r;
+  if (!bytes) return fail(PMSZ_ERR_INVALID_ARG, "bytes is NULL");
+  const TileGeo G = make_tile_geo(grid->ndim, grid->nx, grid->ny, grid->nz,
+                                  engine_chunk(grid->ndim, grid->nx, grid->ny, grid->nz));
+  *bytes = field_layout(G, false).total;
+  return PMSZ_OK;
+}
+
+int pmsz_session_create(int32_t dtype, int32_t max_fields, void* ws, size_t ws_bytes,
+                        void* stream, pmsz_session** out) {
+  if (!out || !ws || max_fields < 1 || (dtype != PMSZ_F32 && dtype != PMSZ_F64))
+    return fail(PMSZ_ERR_INVALID_ARG, "bad session arguments");
+  if ((uintptr_t)ws % kAlign) return fail(PMSZ_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  if (ws_bytes < session_ctl_bytes(max_fields))
+    return fail(PMSZ_ERR_OOM, "session workspace %zu bytes, need %zu", ws_bytes,
+                session_ctl_bytes(max_fields));
+  pmsz_session* S = new pmsz_session();
+  S->dtype = dtype;
+  S->cap = max_fields;
+  S->ws = (char*)ws;
+  S->desc_off = align_up(sizeof(EngineCtl));
+  S->out_off = S->desc_off + align_up(sizeof(FieldDesc) * (size_t)max_fields);
+  S->stream = (hipStream_t)stream;
+  hipError_t e = hipEventCreateWithFlags(&S->ev, hipEventDisableTiming);
+  if (e == hipSuccess) e = engine_zero(S->ws, align_up(sizeof(EngineCtl)), S->stream);
+  if (e != hipSuccess) {
+    delete S;
+    return fail(PMSZ_ERR_DEVICE, "session setup failed: %s", hipGetErrorString(e));
   }
-  return first;
+  memset(&S->last, 0, sizeof(S->last));
+  *out = S;
+  return PMSZ_OK;
+}
+
+int pmsz_session_add(pmsz_session* S, const pmsz_field* field, int64_t max_iters, void* field_ws,
+                     size_t field_ws_bytes, int32_t* handle) {
+  if (!S || !field || !field_ws || !handle) return fail(PMSZ_ERR_INVALID_ARG, "NULL argument");
+  if (S->pending) return fail(PMSZ_ERR_INVALID_ARG, "a step is in flight: sync first");
+  if (field->grid.dtype != S->dtype) return fail(PMSZ_ERR_INVALID_ARG, "dtype differs from session");
+  if (!field->f || !field->g) return fail(PMSZ_ERR_INVALID_ARG, "NULL array");
+  if (max_iters < 0) return fail(PMSZ_ERR_INVALID_ARG, "max_iters must be >= 0");
+  if ((int32_t)S->order.size() >= S->cap) return fail(PMSZ_ERR_OOM, "session is full");
+  if ((uintptr_t)field_ws % kAlign) return fail(PMSZ_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  pmsz_session::Entry e;
+  int r = describe_field(*field, max_iters, 0, e.d);
+  if (r) return r;
+  const FieldLayout L = field_layout(e.d.geo, false);
+  if (field_ws_bytes < L.total)
+    return fail(PMSZ_ERR_OOM, "field workspace %zu bytes, need %zu", field_ws_bytes, L.total);
+  char* fb = (char*)field_ws;
+  e.d.st = (FieldState*)(fb + L.state);
+  e.d.act = (uint8_t*)(fb + L.act);
+  e.d.bm = (uint32_t*)(fb + L.bm);
+  e.d.dirs = (uint8_t*)(fb + L.dirs);
+  HIP_TRY(engine_zero(fb, L.dirs, S->stream));
+  memset(&e.st, 0, sizeof(e.st));
+  const int32_t h = S->next_handle++;
+  S->fields[h] = e;
+  S->order.push_back(h);
+  *handle = h;
+  return PMSZ_OK;
+}
+
+int pmsz_session_step(pmsz_session* S, int64_t max_rounds) {
+  if (!S) return fail(PMSZ_ERR_INVALID_ARG, "NULL session");
+  if (S->pending) return fail(PMSZ_ERR_INVALID_ARG, "a step is in flight: sync first");
+  if (max_rounds < 1) return fail(PMSZ_ERR_INVALID_ARG, "max_rounds must be >= 1");
+  S->stepped.clear();
+  std::vector<FieldDesc> fd;
+  int64_t tiles = 0, segs = 0;
+  int fresh = 0;
+  for (int32_t h : S->order) {
+    pmsz_session::Entry& e = S->fields[h];
+    if (e.done) continue;
+    FieldDesc d = e.d;
+    d.tile_base = tiles;
+    d.seg_base = segs;
+    tiles += tile_count(d.geo);
+    segs += (d.words + kSegWords - 1) / kSegWords;
+    fd.push_back(d);
+    S->stepped.push_back(h);
+    fresh |= !e.started;
+  }
+  if (fd.empty()) return PMSZ_OK;
+  const int32_t n = (int32_t)fd.size();
+  void *up, *down;
+  int r = staging(S->up, sizeof(FieldDesc) * (size_t)n, &up);
+  if (r) return r;
+  r = staging(S->down, sizeof(EngineCtl) + sizeof(FieldIter) * (size_t)n, &down);
+  if (r) return r;
+  memcpy(up, fd.data(), sizeof(FieldDesc) * (size_t)n);
+  HIP_TRY(hipMemcpyAsync(S->ws + S->desc_off, up, sizeof(FieldDesc) * (size_t)n,
+                         hipMemcpyHostToDevice, S->stream));
+  EngineArgs a;
+  a.fd = (const FieldDesc*)(S->ws + S->desc_off);
+  a.out = (FieldIter*)(S->ws + S->out_off);
+  a.nf = n;
+  a.has_fresh = fresh;
+  a.ctl = (EngineCtl*)S->ws;
+  a.total_tiles = tiles;
+  a.total_segs = segs;
+  a.max_rounds = max_rounds;
+  int grid = 0;
+  HIP_TRY(engine_launch(S->dtype, a, S->stream, &grid));
+  HIP_TRY(hipMemcpyAsync(down, S->ws, sizeof(EngineCtl), hipMemcpyDeviceToHost, S->stream));
+  HIP_TRY(hipMemcpyAsync((char*)down + sizeof(EngineCtl), a.out, sizeof(FieldIter) * (size_t)n,
+                         hipMemcpyDeviceToHost, S->stream));
+  HIP_TRY(hipEventRecord(S->ev, S->stream));
+  S->last.tiles = tiles;
+  S->last.grid = grid;
+  S->pending = true;
+  return PMSZ_OK;
+}
+
+int pmsz_session_sync(pmsz_session* S, int32_t* n_done) {
+  if (!S) return fail(PMSZ_ERR_INVALID_ARG, "NULL session");
+  int32_t finished = 0;
+  if (S->pending) {
+    HIP_TRY(hipEventSynchronize(S->ev));
+    S->pending = false;
+    const EngineCtl* hc = (const EngineCtl*)S->down.p;
+    const FieldIter* hs = (const FieldIter*)((char*)S->down.p + sizeof(EngineCtl));
+    if (hc->error) return fail(PMSZ_ERR_DEVICE, "grid barrier timed out in the correction engine");
+    S->epoch = hc->epoch;
+    S->last.rounds = (int64_t)hc->rounds;
+    for (size_t i = 0; i < S->stepped.size(); ++i) {
+      pmsz_session::Entry& e = S->fields[S->stepped[i]];
+      fill_stats(hs[i], e.st);
+      if (!hs[i].done) e.st.status = PMSZ_OK;
+      e.started = hs[i].started;
+      if (hs[i].done && !e.done) {
+        e.done = 1;
+        ++finished;
+      }
+    }
+  }
+  if (n_done) *n_done = finished;
+  return PMSZ_OK;
+}
+
+int pmsz_session_result(pmsz_session* S, int32_t handle, pmsz_stats* stats, int32_t* done) {
+  if (!S) return fail(PMSZ_ERR_INVALID_ARG, "NULL session");
+  auto it = S->fields.find(handle);
+  if (it == S->fields.end()) return fail(PMSZ_ERR_INVALID_ARG, "unknown handle %d", handle);
+  if (stats) *stats = it->second.st;
+  if (done) *done = it->second.done;
+  return PMSZ_OK;
+}
+
+int pmsz_session_remove(pmsz_session* S, int32_t handle) {
+  if (!S) return fail(PMSZ_ERR_INVALID_ARG, "NULL session");
+  if (S->pending) return fail(PMSZ_ERR_INVALID_ARG, "a step is in flight: sync first");
+  auto it = S->fields.find(handle);
+  if (it == S->fields.end()) return fail(PMSZ_ERR_INVALID_ARG, "unknown handle %d", handle);
+  S->fields.erase(it);
+  for (size_t i = 0; i < S->order.size(); ++i)
+    if (S->order[i] == handle) {
+      S->order.erase(S->order.begin() + (long)i);
+      break;
+    }
+  return PMSZ_OK;
+}
+
+int pmsz_session_destroy(pmsz_session* S) {
+  if (!S) return PMSZ_OK;
+  if (S->pending) (void)hipEventSynchronize(S->ev);
+  if (S->ev) (void)hipEventDestroy(S->ev);
+  if (S->up.p) (void)hipHostFree(S->up.p);
+  if (S->down.p) (void)hipHostFree(S->down.p);
+  S->up.p = S->down.p = nullptr;
+  delete S;
+  return PMSZ_OK;
 }
 
 }  // extern "C"

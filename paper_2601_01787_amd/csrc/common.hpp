@@ -14,38 +14,18 @@
 namespace pmsz {
 
 // ---------------------------------------------------------------------------
-// Control block of one correction (lives at the start of the workspace).  All
-// counters are device-scope atomics; the last block of each apply launch
-// folds them into the iteration state (Sec. IV-A loop, convergence of
-// Sec. III-B) and clears them for the next round.
-// ---------------------------------------------------------------------------
-struct Ctl {
-  unsigned long long mism;       // (vertex, direction) mismatches this round
-  unsigned long long nflag;      // |F| this round
-  unsigned long long at_lb;      // flagged vertices already at their bound
-  unsigned long long k;          // edit rounds applied so far
-  unsigned long long steps;      // value changes over all rounds
-  unsigned long long mism0;      // mismatches of fhat
-  unsigned long long flagged_final;
-  unsigned long long stalled_final;
-  unsigned long long bad_nonfinite;  // validation counters
-  unsigned long long bad_bound;
-  unsigned int ticket;           // arrival counter of the apply launch
-  int done;                      // nonzero once the status is final
-  int status;                    // pmsz_status
-  int pad[3];
-};
-static_assert(sizeof(Ctl) <= 256, "control block must fit its 256-byte slot");
-
-constexpr int kBlock = 256;
-
-// ---------------------------------------------------------------------------
 // Direction codes: 0 = self, m in 1..7 = offset +(m&1, m>>1&1, m>>2&1),
 // 8+m = the negated offset.  Linear index delta of a code.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int64_t code_delta(int code, int64_t nx, int64_t sxy) {
   int m = code & 7;
   int64_t d = (int64_t)(m & 1) + (int64_t)((m >> 1) & 1) * nx + (int64_t)((m >> 2) & 1) * sxy;
+  return (code & 8) ? -d : d;
+}
+
+__device__ __forceinline__ int32_t code_delta32(int code, int32_t nx, int32_t sxy) {
+  const int m = code & 7;
+  const int32_t d = (m & 1) + ((m >> 1) & 1) * nx + ((m >> 2) & 1) * sxy;
   return (code & 8) ? -d : d;
 }
 

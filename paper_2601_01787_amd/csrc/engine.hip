@@ -1,0 +1,417 @@
+// engine.hip -- the persistent correction kernel (gfx950).
+//
+// One cooperative launch runs the correction loop of Sec. IV-A for one or many
+// fields.  Round E (p = E & 1, q = E % 3), for every field still running:
+//   detect  over the tiles marked active for round E: directions of g^k,
+//           comparison with the directions of f, targets set in the flag
+//           bitmap with fire-and-forget atomicOr (Sec. IV-A ascending and
+//           descending rules, Sec. III-B FPmax rule).  In a field's first
+//           round the same pass computes the directions of f and validates
+//           fhat.
+//   barrier
+//   apply   for fields with mismatches: count the flagged vertices (|F|) and
+//           those already at their bound; unless the field is out of rounds,
+//           give every flagged vertex above its bound one halving edit (Eq. 1)
+//           and mark the tiles within one vertex of it active for round E+1.
+//           Only those tiles can see a different neighbourhood next round, so
+//           examining them alone gives exactly the full-sweep result.
+//   barrier
+// The decision of Sec. IV-A's loop (converged, stalled, out of rounds,
+// continue) is a pure function of the state at the start of a round and that
+// round's counters; every block evaluates it itself when it needs it, and
+// block 0 persists it one round later, so no extra barrier is needed.  The
+// loop ends when a round edits nothing (every field done) or after
+// max_rounds rounds (resumable steps).
+#include "engine.hpp"
+
+namespace pmsz {
+
+// ---------------------------------------------------------------------------
+// Grid barrier for a cooperative launch.  Each block's thread 0 releases its
+// writes (one L2 write-back at agent scope), arrives on a device-scope
+// counter, polls the generation word with relaxed loads (which read the
+// coherent copy without touching the caches), and acquires once at the end
+// (one cache invalidate), so that the next phase sees every block's writes.
+// The spin is bounded: after ~4 s the block records an error and the launch
+// winds down instead of hanging.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned relaxed_load(const unsigned* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ unsigned long long relaxed_load(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void grid_sync(EngineCtl* ctl, unsigned nblocks, unsigned& gen) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned target = gen + 1;
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned arrived =
+        __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == nblocks - 1) {
+      __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&ctl->bar_gen, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      const unsigned long long t0 = wall_clock64();
+      while (relaxed_load(&ctl->bar_gen) != target) {
+        __builtin_amdgcn_s_sleep(1);
+        if (wall_clock64() - t0 > 400000000ull) {  // 100 MHz counter: 4 s
+          __hip_atomic_store(&ctl->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    gen = target;
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ bool engine_failed(EngineCtl* ctl) {
+  return __hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+}
+
+// Field owning global tile / segment v (fields sorted by base).
+__device__ __forceinline__ int field_of_tile(const FieldDesc* fd, int nf, int64_t v) {
+  int lo = 0, hi = nf - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (fd[mid].tile_base <= v) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+__device__ __forceinline__ int field_of_seg(const FieldDesc* fd, int nf, int64_t v) {
+  int lo = 0, hi = nf - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (fd[mid].seg_base <= v) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// The loop decision of Sec. IV-A: state at the start of the next round from
+// the state at the start of this round and this round's counters.
+__device__ __forceinline__ FieldIter next_state(FieldIter s, const FieldCtr& c,
+                                                int64_t max_iters) {
+  if (s.done) return s;
+  const bool first = !s.started;
+  s.started = 1;
+  s.swept += c.swept;
+  if (first) s.mism0 = c.mism;
+  s.flagged_final = c.nflag;
+  s.stalled_final = c.at_lb;
+  if (first && (c.bad_nf || c.bad_b)) {
+    s.done = 1;
+    s.status = c.bad_nf ? PMSZ_ERR_NONFINITE : PMSZ_ERR_INPUT_BOUND;
+    s.mism0 = s.flagged_final = s.stalled_final = 0;
+  } else if (c.mism == 0) {
+    s.done = 1;
+    s.status = PMSZ_OK;
+  } else if (c.at_lb == c.nflag) {
+    s.done = 1;
+    s.status = PMSZ_ERR_STALLED;
+  } else if ((long long)s.k >= max_iters) {
+    s.done = 1;
+    s.status = PMSZ_ERR_NOT_CONVERGED;
+  } else {
+    s.k += 1;
+    s.steps += c.nflag - c.at_lb;
+    s.flagged_final = s.stalled_final = 0;
+  }
+  return s;
+}
+
+// Counters of a finished round (read after the barrier that completed them).
+__device__ __forceinline__ FieldCtr load_ctr(const FieldCtr* c) {
+  FieldCtr r;
+  r.mism = relaxed_load(&c->mism);
+  r.nflag = relaxed_load(&c->nflag);
+  r.at_lb = relaxed_load(&c->at_lb);
+  r.bad_nf = relaxed_load(&c->bad_nf);
+  r.bad_b = relaxed_load(&c->bad_b);
+  r.swept = relaxed_load(&c->swept);
+  return r;
+}
+
+// State of a field at the start of round E.
+__device__ __forceinline__ FieldIter state_at(const FieldDesc& d, unsigned long long E,
+                                              unsigned long long E0) {
+  const FieldState& st = *d.st;
+  if (E == E0) return st.s[E & 1];
+  return next_state(st.s[(E - 1) & 1], load_ctr(&st.c[(E - 1) % 3]), d.max_iters);
+}
+
+// Tiles containing a vertex within one step of target t (Freudenthal
+// neighbours lie in the 3x3x3 box around t).
+struct TileBox {
+  int32_t x0, x1, y0, y1, z0, z1;
+};
+
+__device__ __forceinline__ TileBox box_of(const TileGeo& G, int32_t t) {
+  TileBox b;
+  const int32_t x = t % G.nx;
+  const int32_t xl = x > 0 ? x - 1 : 0, xh = x + 1 < G.nx ? x + 1 : x;
+  if (G.ndim == 3) {
+    const int32_t y = (t / G.nx) % G.ny, z = t / G.sxy;
+    const int32_t yl = y > 0 ? y - 1 : 0, yh = y + 1 < G.ny ? y + 1 : y;
+    const int32_t zl = z > 0 ? z - 1 : 0, zh = z + 1 < G.nz ? z + 1 : z;
+    b = {xl / TX, xh / TX, yl / TY, yh / TY, zl / G.chunk, zh / G.chunk};
+  } else {
+    const int32_t y = t / G.nx;
+    const int32_t yl = y > 0 ? y - 1 : 0, yh = y + 1 < G.ny ? y + 1 : y;
+    b = {xl / RX, xh / RX, yl / G.chunk, yh / G.chunk, 0, 0};
+  }
+  return b;
+}
+
+// Plain byte stores into the field's activity bytes of the next round: every
+// writer stores the same value.
+__device__ __forceinline__ void mark_box(const FieldDesc& d, const TileBox& b, uint8_t* nxt) {
+  for (int32_t bz = b.z0; bz <= b.z1; ++bz)
+    for (int32_t by = b.y0; by <= b.y1; ++by)
+      for (int32_t bx = b.x0; bx <= b.x1; ++bx) {
+        const int32_t T = bx + d.geo.tiles_x * (by + d.geo.tiles_y * bz);
+        if (!nxt[T]) nxt[T] = 1;
+      }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_engine(EngineArgs a) {
+  __shared__ TileLds<T> sm;
+  __shared__ unsigned long long red[4];
+  __shared__ int sh_f, sh_kind;
+  const unsigned G = gridDim.x;
+  const int tid = threadIdx.x;
+  EngineCtl* ctl = a.ctl;
+  unsigned gen = relaxed_load(&ctl->bar_gen);
+  const unsigned long long E0 = ctl->epoch;
+  unsigned long long E = E0;
+
+  // Fields that have not started: every tile is active in their first round.
+  if (a.has_fresh) {
+    for (int64_t tt = (int64_t)blockIdx.x * 256 + tid; tt < a.total_tiles; tt += (int64_t)G * 256) {
+      const FieldDesc& d = a.fd[field_of_tile(a.fd, a.nf, tt)];
+      const FieldIter& s = d.st->s[E0 & 1];
+      if (!s.started && !s.done)
+        d.act[(E0 & 1) * tile_count(d.geo) + (tt - d.tile_base)] = 1;
+    }
+    grid_sync(ctl, G, gen);
+  }
+
+  for (long long r = 0; a.max_rounds < 0 || r < a.max_rounds; ++r) {
+    if (engine_failed(ctl)) break;
+    const int p = (int)(E & 1);
+    const int q = (int)(E % 3), qn = (int)((E + 1) % 3);
+
+    // ---- block 0: persist the state of round E, clear next-but-one counters
+    if (blockIdx.x == 0) {
+      for (int fi = tid; fi < a.nf; fi += 256) {
+        const FieldDesc& d = a.fd[fi];
+        if (E > E0) d.st->s[p] = state_at(d, E, E0);
+        d.st->c[qn] = FieldCtr{0, 0, 0, 0, 0, 0};
+      }
+      if (tid == 0) ctl->edits[qn] = 0;
+    }
+
+    // ---- detect ------------------------------------------------------------
+    unsigned long long acc_m = 0, acc_nf = 0, acc_nb = 0, acc_sw = 0;
+    int cur = -1, cached = -1, cached_kind = -1;
+    for (int64_t tt = blockIdx.x; tt < a.total_tiles; tt += G) {
+      if (tid == 0) {
+        int fi = field_of_tile(a.fd, a.nf, tt), kind = 0;
+        const FieldDesc& d = a.fd[fi];
+        uint8_t* flag = d.act + p * tile_count(d.geo) + (tt - d.tile_base);
+        if (*flag) {
+          *flag = 0;
+          if (fi != cached) {
+            const FieldIter s = state_at(d, E, E0);
+            cached = fi;
+            cached_kind = s.done ? -1
+                        : s.started ? KIND_NEXT
+                        : (a.fd[fi].dirs_given ? KIND_FIRST_GIVEN : KIND_FIRST);
+          }
+          kind = cached_kind;
+          if (kind < 0) fi = -1;
+        } else {
+          fi = -1;
+        }
+        sh_f = fi;
+        sh_kind = kind;
+      }
+      __syncthreads();
+      const int fi = sh_f, kind = sh_kind;
+      __syncthreads();
+      if (fi < 0) continue;
+      const FieldDesc& d = a.fd[fi];
+      if (tid == 0 && fi != cur) {
+        if (cur >= 0) {
+          FieldCtr* c = &a.fd[cur].st->c[q];
+          if (acc_m) atomicAdd(&c->mism, acc_m);
+          if (acc_nf) atomicAdd(&c->bad_nf, acc_nf);
+          if (acc_nb) atomicAdd(&c->bad_b, acc_nb);
+          if (acc_sw) atomicAdd(&c->swept, acc_sw);
+        }
+        acc_m = acc_nf = acc_nb = acc_sw = 0;
+        cur = fi;
+      }
+      const int64_t tile = tt - d.tile_base;
+      const T* g = (const T*)d.g;
+      const T* f = (const T*)d.f;
+      const T xi = (T)d.xi_t;
+      TileCounts tc;
+      if (d.geo.ndim == 3) {
+        if (kind == KIND_NEXT)
+          tc = tile3<T, KIND_NEXT>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile);
+        else if (kind == KIND_FIRST_GIVEN)
+          tc = tile3<T, KIND_FIRST_GIVEN>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile);
+        else
+          tc = tile3<T, KIND_FIRST>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile);
+      } else {
+        if (kind == KIND_NEXT)
+          tc = tile2<T, KIND_NEXT>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile);
+        else if (kind == KIND_FIRST_GIVEN)
+          tc = tile2<T, KIND_FIRST_GIVEN>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile);
+        else
+          tc = tile2<T, KIND_FIRST>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile);
+      }
+      if (tid == 0) {
+        acc_m += unpack3(tc, 0);
+        acc_nf += unpack3(tc, 1);
+        acc_nb += unpack3(tc, 2);
+        acc_sw += (unsigned long long)tile_voxels(d.geo, tile);
+      }
+    }
+    if (tid == 0 && cur >= 0) {
+      FieldCtr* c = &a.fd[cur].st->c[q];
+      if (acc_m) atomicAdd(&c->mism, acc_m);
+      if (acc_nf) atomicAdd(&c->bad_nf, acc_nf);
+      if (acc_nb) atomicAdd(&c->bad_b, acc_nb);
+      if (acc_sw) atomicAdd(&c->swept, acc_sw);
+    }
+    grid_sync(ctl, G, gen);
+    if (engine_failed(ctl)) break;
+
+    // ---- apply -------------------------------------------------------------
+    for (int64_t sg = blockIdx.x; sg < a.total_segs; sg += G) {
+      const int fi = field_of_seg(a.fd, a.nf, sg);
+      const FieldDesc& d = a.fd[fi];
+      const FieldIter s = d.st->s[p];  // persisted by block 0 before the barrier
+      FieldCtr* cq = &d.st->c[q];
+      uint8_t* nxt = d.act + (p ^ 1) * tile_count(d.geo);
+      const unsigned long long mism = relaxed_load(&cq->mism);
+      const bool bad = !s.started && (relaxed_load(&cq->bad_nf) || relaxed_load(&cq->bad_b));
+      if (s.done || bad || mism == 0) continue;
+      const bool edit = (long long)s.k < d.max_iters;
+      const int64_t w0 = (sg - d.seg_base) * kSegWords;
+      const int64_t w1 = (w0 + kSegWords < d.words) ? w0 + kSegWords : d.words;
+      const T* f = (const T*)d.f;
+      T* g = (T*)d.g;
+      const T xi = (T)d.xi_t;
+      unsigned long long nflag = 0, at_lb = 0, edits = 0;
+      for (int32_t w = (int32_t)w0 + tid; w < (int32_t)w1; w += 256) {
+        uint32_t bits = d.bm[w];
+        if (!bits) continue;
+        d.bm[w] = 0u;
+        nflag += __popc(bits);
+        TileBox last = {-1, -1, -1, -1, -1, -1};
+        while (bits) {
+          const int b = __ffs(bits) - 1;
+          bits &= bits - 1;
+          const int32_t t = w * 32 + b;
+          const T gt = g[t];
+          const T lb = lower_bound<T>(f[t], xi);
+          if (gt > lb) {
+            if (edit) {
+              g[t] = halving_edit<T>(gt, lb);
+              ++edits;
+            }
+          } else {
+            ++at_lb;
+          }
+          if (edit) {
+            const TileBox bx = box_of(d.geo, t);
+            if (bx.x0 != last.x0 || bx.x1 != last.x1 || bx.y0 != last.y0 || bx.y1 != last.y1 ||
+                bx.z0 != last.z0 || bx.z1 != last.z1) {
+              mark_box(d, bx, nxt);
+              last = bx;
+            }
+          }
+        }
+      }
+      nflag = block_sum(nflag, red);
+      at_lb = block_sum(at_lb, red);
+      edits = block_sum(edits, red);
+      if (tid == 0) {
+        if (nflag) atomicAdd(&cq->nflag, nflag);
+        if (at_lb) atomicAdd(&cq->at_lb, at_lb);
+        if (edits) atomicAdd(&ctl->edits[q], edits);
+      }
+    }
+    grid_sync(ctl, G, gen);
+    if (engine_failed(ctl)) break;
+    const unsigned long long edited = relaxed_load(&ctl->edits[q]);
+    ++E;
+    if (edited == 0) break;
+  }
+  // persist the state at the start of the next round, and gather it
+  if (blockIdx.x == 0 && !engine_failed(ctl)) {
+    for (int fi = tid; fi < a.nf; fi += 256) {
+      const FieldDesc& d = a.fd[fi];
+      const FieldIter s = state_at(d, E, E0);
+      if (E > E0) d.st->s[E & 1] = s;
+      if (a.out) a.out[fi] = s;
+    }
+    if (tid == 0) {
+      ctl->epoch = E;
+      ctl->rounds = E - E0;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_zero(uint32_t* p, int64_t words) {
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x; w < words; w += stride) p[w] = 0u;
+}
+
+hipError_t engine_zero(void* p, size_t bytes, hipStream_t s) {
+  const int64_t words = (int64_t)(bytes / 4);
+  int64_t b = (words + 255) / 256;
+  if (b < 1) b = 1;
+  if (b > 4096) b = 4096;
+  hipLaunchKernelGGL(k_zero, dim3((unsigned)b), dim3(256), 0, s, (uint32_t*)p, words);
+  return hipGetLastError();
+}
+
+// Cooperative grid: as many resident blocks as the chip holds, but no more
+// than there is work for (fewer arrivals make the barrier cheaper).
+template <class T>
+static hipError_t launch_t(const EngineArgs& a, hipStream_t s, int* grid_out) {
+  static int per_cu = -1, cus = -1, dev_cached = -1;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev != dev_cached) {
+    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_engine<T>, 256, 0);
+    if (e != hipSuccess) return e;
+    dev_cached = dev;
+  }
+  int64_t want = a.total_tiles > a.total_segs ? a.total_tiles : a.total_segs;
+  if (want < 1) want = 1;
+  int64_t cap = (int64_t)per_cu * cus;
+  if (cap < 1) cap = 1;
+  const unsigned grid = (unsigned)(want < cap ? want : cap);
+  if (grid_out) *grid_out = (int)grid;
+  EngineArgs copy = a;
+  void* args[] = {&copy};
+  return hipLaunchCooperativeKernel((const void*)k_engine<T>, dim3(grid), dim3(256), args, 0, s);
+}
+
+hipError_t engine_launch(int dtype, const EngineArgs& a, hipStream_t s, int* grid_out) {
+  if (dtype == PMSZ_F32) return launch_t<float>(a, s, grid_out);
+  return launch_t<double>(a, s, grid_out);
+}
+
+}  // namespace pmsz

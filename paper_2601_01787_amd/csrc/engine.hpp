@@ -1,0 +1,107 @@
+// engine.hpp -- data of the persistent correction engine (internal).
+//
+// One cooperative launch runs the whole correction loop of Sec. IV-A for one
+// or many fields: rounds of [detect over active tiles] -> grid barrier ->
+// [apply edits] -> grid barrier, with per-field state so that fields of any
+// size converge and retire independently.  The same structures serve a single
+// field, a batch run to completion, and resumable serving steps.
+#pragma once
+
+#include "tiles.hpp"
+
+namespace pmsz {
+
+constexpr int64_t kSegWords = 2048;  // bitmap words per apply segment (64K vertices)
+
+// Iteration state of one field at the start of a round.  Double-buffered by
+// round parity: during round E block 0 persists the state of round E while
+// every block derives it on the fly from the state and counters of round E-1.
+struct FieldIter {
+  unsigned long long k, steps, mism0, flagged_final, stalled_final, swept;
+  int32_t status, done, started, pad;
+};
+
+// Counters of one round.  Triple-buffered by round index mod 3: round E adds
+// to c[E%3], reads c[(E-1)%3], and clears c[(E+1)%3].
+struct FieldCtr {
+  unsigned long long mism, nflag, at_lb, bad_nf, bad_b, swept;
+};
+
+struct FieldState {
+  FieldIter s[2];
+  FieldCtr c[3];
+};
+
+// Read-only description of one field (uploaded by the host).
+struct FieldDesc {
+  const void* f;      // original field
+  void* g;            // in: fhat, out: corrected
+  uint8_t* dirs;      // direction bytes of f (workspace, or the caller's)
+  uint32_t* bm;       // flag bitmap of this field
+  FieldState* st;     // iteration state and counters of this field
+  uint8_t* act;       // per tile and round parity: examine in that round
+                      // (act[p * tiles + tile])
+  TileGeo geo;
+  double xi_t;        // xi in the field type, <= xi
+  int64_t max_iters;
+  int64_t tile_base;  // first global tile index
+  int64_t seg_base;   // first global apply segment
+  int64_t words;      // bitmap words
+  int32_t dirs_given; // caller supplied the directions of f
+  int32_t pad;
+};
+
+struct EngineCtl {
+  unsigned bar_count;
+  unsigned bar_gen;
+  unsigned long long epoch;     // rounds run since the workspace was initialised
+  unsigned long long rounds;    // rounds run by the last launch
+  unsigned long long edits[3];  // value changes per round (mod 3), all fields
+  int error;                    // a grid barrier timed out
+  int pad;
+};
+
+struct EngineArgs {
+  const FieldDesc* fd;
+  FieldIter* out;        // state of every field at the end of the launch
+  int32_t nf;
+  int32_t has_fresh;     // some field has not started: all its tiles are active
+  EngineCtl* ctl;
+  int64_t total_tiles;
+  int64_t total_segs;
+  int64_t max_rounds;    // < 0: until every field is done
+};
+
+// Host side (engine.hip).
+hipError_t engine_launch(int dtype, const EngineArgs& a, hipStream_t s, int* grid_out);
+// Zero `bytes` bytes (multiple of 4, 4-byte aligned) with a kernel, so that
+// the call can sit inside a captured graph.
+hipError_t engine_zero(void* p, size_t bytes, hipStream_t s);
+
+// Per-field workspace: [FieldState][activity bytes x 2][bitmap][directions].
+struct FieldLayout {
+  size_t state, act, bm, dirs, total;
+};
+inline size_t ws_align(size_t v) { return (v + 255) / 256 * 256; }
+inline FieldLayout field_layout(const TileGeo& G, bool dirs_given) {
+  FieldLayout L;
+  L.state = 0;
+  L.act = ws_align(sizeof(FieldState));
+  L.bm = L.act + ws_align(2 * (size_t)tile_count(G));
+  L.dirs = L.bm + ws_align(((size_t)G.n + 31) / 32 * 4);
+  L.total = L.dirs + (dirs_given ? 0 : ws_align((size_t)G.n));
+  return L;
+}
+
+// Tile rows per tile for the engine: enough tiles to spread a small field over
+// the chip, 16 planes / rows otherwise.
+inline int engine_chunk(int ndim, int64_t nx, int64_t ny, int64_t nz) {
+  const int64_t cols = ndim == 3 ? ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY) : (nx + RX - 1) / RX;
+  const int64_t depth = ndim == 3 ? nz : ny;
+  int64_t c = depth * cols / 2048;
+  if (c < 2) c = 2;
+  if (c > 16) c = 16;
+  return (int)c;
+}
+
+}  // namespace pmsz

@@ -27,14 +27,7 @@ inline Geo make_geo(const pmsz_grid& g) {
 inline int64_t bitmap_words(int64_t n) { return (n + 31) / 32; }
 
 // stencil.hip
-hipError_t launch_init(Ctl* ctl, uint32_t* bm, int64_t nwords, hipStream_t s);
 hipError_t launch_dirs(int dtype, const void* h, const Geo& G, uint8_t* dirs, hipStream_t s);
-hipError_t launch_validate(int dtype, const void* f, const void* fhat, int64_t n, double xi_t,
-                           Ctl* ctl, hipStream_t s);
-hipError_t launch_detect(int dtype, const void* g, const Geo& G, const uint8_t* dirs_f,
-                         uint32_t* bm, Ctl* ctl, hipStream_t s);
-hipError_t launch_apply(int dtype, const void* f, void* g, const Geo& G, uint32_t* bm,
-                        double xi_t, Ctl* ctl, int64_t max_iters, hipStream_t s);
 
 // labels.hip
 hipError_t launch_labels_init(const uint8_t* dirs, const Geo& G, int32_t* lmax, int32_t* lmin,

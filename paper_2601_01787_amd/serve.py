@@ -1,0 +1,161 @@
+"""Continuous-batching correction server on one GPU.
+
+Requests (f, fhat, xi) arrive over time.  The server keeps a serving session
+of the C library (pmsz_session_*): requests are admitted while their HBM
+footprint fits the budget and a slot is free, each step runs a few rounds of
+the persistent correction kernel over every admitted request, finished
+requests leave at once and the next ones are admitted in their place, so
+requests that arrive while others are on the GPU share the device with them.
+A request's result is the same as correcting it alone (the per-field
+iteration does not depend on what else is in the step).
+
+``FifoServer`` is the baseline: one plain pmsz_correct per request, in
+arrival order.
+"""
+import collections
+import time
+
+import torch
+
+from . import Session, correct, field_workspace_size, grid_of
+
+
+class Request:
+    __slots__ = ("rid", "f", "fhat", "xi", "arrival", "admitted", "done_at", "g", "ws",
+                 "handle", "stats", "footprint")
+
+    def __init__(self, rid, f, fhat, xi, arrival):
+        self.rid = rid
+        self.f, self.fhat, self.xi = f, fhat, xi
+        self.arrival = arrival
+        self.admitted = None
+        self.done_at = None
+        self.g = None
+        self.ws = None
+        self.handle = None
+        self.stats = None
+        self.footprint = None
+
+
+def footprint(f):
+    """Device bytes a request holds while admitted: its f, fhat and g, and its
+    field workspace (flag bitmap, direction bytes, tile flags, state)."""
+    return 3 * f.numel() * f.element_size() + field_workspace_size(grid_of(f)) + 256
+
+
+class BatchingServer:
+    """Admits requests by HBM footprint into a serving session and steps the
+    session until every request is done."""
+
+    def __init__(self, device, hbm_budget, max_fields=64, rounds_per_step=4,
+                 dtype=torch.float32, max_iters=1 << 40):
+        self.device = torch.device(device)
+        self.budget = int(hbm_budget)
+        self.rounds = int(rounds_per_step)
+        self.max_iters = max_iters
+        self.session = Session(dtype, max_fields, self.device)
+        self.max_fields = max_fields
+        self.in_use = 0
+        self.active = {}
+        self.steps = 0
+
+    def can_admit(self, req):
+        return len(self.active) < self.max_fields and self.in_use + req.footprint <= self.budget
+
+    def admit(self, req, now):
+        req.g = req.fhat.clone()
+        n = field_workspace_size(grid_of(req.f))
+        buf = torch.empty(n + 256, dtype=torch.uint8, device=self.device)
+        off = (-buf.data_ptr()) % 256
+        req.ws = buf[off:off + n]
+        req.handle = self.session.add(req.f, req.g, req.xi, req.ws, max_iters=self.max_iters)
+        req.admitted = now
+        self.in_use += req.footprint
+        self.active[req.handle] = req
+
+    def step(self):
+        """One step over every admitted request; returns the finished ones."""
+        if not self.active:
+            return []
+        self.session.step(self.rounds)
+        self.session.sync()
+        self.steps += 1
+        finished = []
+        for h, req in list(self.active.items()):
+            st, done = self.session.result(h)
+            if done:
+                req.stats = st
+                self.session.remove(h)
+                self.in_use -= req.footprint
+                del self.active[h]
+                req.ws = None
+                finished.append(req)
+        return finished
+
+    def close(self):
+        self.session.close()
+
+
+def run_open_loop(server_kind, requests, device, hbm_budget, max_fields=64, rounds_per_step=4,
+                  check=None):
+    """Replay `requests` (sorted by arrival time, seconds from start) against
+    a server in real time.  Returns the served requests.  `check(req)` (if
+    given) is called on every finished request."""
+    dev = torch.device(device)
+    pending = collections.deque()
+    arrivals = collections.deque(sorted(requests, key=lambda r: r.arrival))
+    done = []
+    for r in arrivals:
+        r.footprint = footprint(r.f)
+    if server_kind == "batched":
+        srv = BatchingServer(dev, hbm_budget, max_fields, rounds_per_step)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    while arrivals or pending or (server_kind == "batched" and srv.active):
+        now = time.perf_counter() - t0
+        while arrivals and arrivals[0].arrival <= now:
+            pending.append(arrivals.popleft())
+        if server_kind == "batched":
+            while pending and srv.can_admit(pending[0]):
+                srv.admit(pending.popleft(), now)
+            if pending and not srv.active:
+                raise RuntimeError("request %d does not fit the HBM budget" % pending[0].rid)
+            finished = srv.step()
+            t = time.perf_counter() - t0
+            for r in finished:
+                r.done_at = t
+                if check:
+                    check(r)
+                r.g = None
+            done.extend(finished)
+        else:
+            if pending:
+                r = pending.popleft()
+                r.admitted = now
+                g, st = correct(r.f, r.fhat, r.xi)
+                torch.cuda.synchronize(dev)
+                r.done_at = time.perf_counter() - t0
+                r.g, r.stats = g, st
+                if check:
+                    check(r)
+                r.g = None
+                done.append(r)
+        if not pending and arrivals and (server_kind != "batched" or not srv.active):
+            wait = arrivals[0].arrival - (time.perf_counter() - t0)
+            if wait > 0:
+                time.sleep(min(wait, 0.01))
+    if server_kind == "batched":
+        srv.close()
+    return done
+
+
+def latency_summary(done, duration=None):
+    lat = sorted((r.done_at - r.arrival) * 1e3 for r in done)
+    if not lat:
+        return {}
+    pick = lambda q: lat[min(len(lat) - 1, int(q * (len(lat) - 1) + 0.5))]  # noqa: E731
+    span = max(r.done_at for r in done) - min(r.arrival for r in done)
+    vox = sum(r.f.numel() for r in done)
+    return {"requests": len(lat), "p50_ms": round(pick(0.50), 3), "p99_ms": round(pick(0.99), 3),
+            "mean_ms": round(sum(lat) / len(lat), 3), "req_per_s": round(len(lat) / span, 2),
+            "gvox_per_s": round(vox / span / 1e9, 3)}

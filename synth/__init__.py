@@ -141,7 +141,9 @@ def quantise_proxy(f, eps, seed, chunk=1 << 24):
 
 def gaussian_peaks2d(ny, nx, seed, device="cpu"):
     """Sum of 50..500 Gaussian bumps (sigma 2..20 px, amplitude 0.5..1, each
-    evaluated in a +-4 sigma window) plus 1% white noise; float32."""
+    evaluated in a +-4 sigma window) plus 1% white noise; float32.  Peak
+    parameters come from PCG64; the white noise from torch's generator on
+    `device` (seeded), so a seed is reproducible on the same kind of device."""
     rng = np.random.default_rng(seed)
     k = int(rng.integers(50, 501))
     cx = rng.uniform(0, nx, k)
@@ -160,8 +162,10 @@ def gaussian_peaks2d(ny, nx, seed, device="cpu"):
         d2 = ys.view(-1, 1) ** 2 + xs.view(1, -1) ** 2
         h[y0:y1, x0:x1] += amp[j] * torch.exp(-d2 / (2.0 * sig[j] ** 2))
     rng_h = float(h.max() - h.min())
-    noise = torch.from_numpy(rng.normal(0.0, 0.01 * max(rng_h, 1e-12), size=(ny, nx)))
-    h += noise.to(device)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(int(rng.integers(1 << 62)))
+    noise = torch.randn((ny, nx), generator=gen, dtype=torch.float64, device=device)
+    h += noise * (0.01 * max(rng_h, 1e-12))
     return h.to(torch.float32)
 
 

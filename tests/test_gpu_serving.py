@@ -1,0 +1,122 @@
+"""Serving-session parity on the GPU: a field's result and statistics are the
+same whether it is corrected alone (pmsz_correct) or inside a session that
+admits and retires other fields between steps (continuous batching)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2601_01787_amd as pmsz
+import synth
+from paper_2601_01787_amd import serve
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+KEYS = ("iterations", "steps_applied", "flagged_final", "stalled_flags", "mismatch_initial",
+        "status")
+
+
+def _cases():
+    out = []
+    for n, seed in ((24, 1), (40, 2)):
+        f, fhat, xi = synth.perlin_case(n, 3, 3, 1e-3, seed)
+        out.append((f, fhat, xi))
+    for nx, ny, rel, seed in ((300, 190, 1e-2, 3), (129, 257, 1e-3, 4), (70, 64, 1e-4, 5)):
+        out.append(synth.make_2d_case(nx, ny, rel, seed))
+    return [(f.to(DEV), fh.to(DEV), xi) for f, fh, xi in out]
+
+
+def _alone(cases):
+    res = []
+    for f, fh, xi in cases:
+        g, st = pmsz.correct(f, fh, xi)
+        res.append((g, st))
+    return res
+
+
+def test_session_mix_matches_alone():
+    cases = _cases()
+    alone = _alone(cases)
+    ses = pmsz.Session(torch.float32, 8, torch.device(DEV))
+    live = {}
+    # admit two, step once, admit the rest while those are in flight
+    order = [0, 1, None, 2, 3, None, 4]
+    for item in order:
+        if item is None:
+            ses.step(1)
+            ses.sync()
+            continue
+        f, fh, xi = cases[item]
+        g = fh.clone()
+        n = pmsz.field_workspace_size(pmsz.grid_of(f))
+        buf = torch.empty(n + 256, dtype=torch.uint8, device=DEV)
+        off = (-buf.data_ptr()) % 256
+        ws = buf[off:off + n]
+        live[ses.add(f, g, xi, ws)] = (item, g)
+    finished = {}
+    for _ in range(10000):
+        if len(finished) == len(cases):
+            break
+        ses.step(2)
+        ses.sync()
+        for h, (item, g) in list(live.items()):
+            st, done = ses.result(h)
+            if done:
+                finished[item] = (g, st)
+                ses.remove(h)
+                del live[h]
+    ses.close()
+    assert len(finished) == len(cases)
+    for i, (g_a, st_a) in enumerate(alone):
+        g_b, st_b = finished[i]
+        assert torch.equal(g_a, g_b), i
+        assert [st_a[k] for k in KEYS] == [st_b[k] for k in KEYS], (i, st_a, st_b)
+
+
+def test_session_matches_oracle_on_small_field():
+    f, fh, xi = synth.small_perlin_case()
+    g_ref, st_ref = oracle.correct(f.numpy(), fh.numpy(), xi)
+    f, fh = f.to(DEV), fh.to(DEV)
+    ses = pmsz.Session(torch.float32, 2, torch.device(DEV))
+    g = fh.clone()
+    n = pmsz.field_workspace_size(pmsz.grid_of(f))
+    ws = torch.empty(n, dtype=torch.uint8, device=DEV)
+    h = ses.add(f, g, xi, ws)
+    done = False
+    while not done:
+        ses.step(1)
+        ses.sync()
+        st, done = ses.result(h)
+    ses.close()
+    assert [st[k] for k in KEYS] == [st_ref[k] for k in KEYS]
+    torch.cuda.synchronize()
+    assert np.array_equal(g.cpu().numpy().view(np.uint32), g_ref.view(np.uint32))
+
+
+def test_open_loop_server_results_match_alone():
+    """Poisson arrivals into the batching server: every served result equals
+    the alone result of the same input."""
+    cases = _cases()
+    alone = _alone(cases)
+    rng = np.random.default_rng(7)
+    t = np.cumsum(rng.exponential(1.0 / 400.0, size=12))
+    reqs = []
+    for i, ti in enumerate(t):
+        k = int(rng.integers(len(cases)))
+        f, fh, xi = cases[k]
+        r = serve.Request(i, f, fh, xi, float(ti))
+        r.stats = k
+        reqs.append(r)
+    which = {r.rid: r.stats for r in reqs}
+    bad = []
+
+    def check(r):
+        k = which[r.rid]
+        if not torch.equal(r.g, alone[k][0]):
+            bad.append(r.rid)
+
+    done = serve.run_open_loop("batched", reqs, DEV, hbm_budget=1 << 30, max_fields=4,
+                               rounds_per_step=2, check=check)
+    assert len(done) == len(reqs) and not bad
+    summary = serve.latency_summary(done)
+    assert summary["requests"] == len(reqs) and summary["p50_ms"] > 0
