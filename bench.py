@@ -199,7 +199,10 @@ def main():
         "detail": {"iterations": stats[0]["iterations"], "edits": stats[0]["steps_applied"],
                    "mismatch_initial": stats[0]["mismatch_initial"], "rounds": tm["rounds"],
                    "swept_vertices": tm["swept"], "tiles": tm["tiles"], "grid": tm["grid"],
-                   "engine_ms_per_step": round(avg_ms, 4)},
+                   "engine_ms_per_step": round(avg_ms, 4),
+                   "first_round_ms": round(tm["first_round_ms"], 4),
+                   "later_detect_ms": round(tm["detect_ms"], 4),
+                   "later_apply_ms": round(tm["apply_ms"], 4)},
     }
     del gs
     torch.cuda.empty_cache()

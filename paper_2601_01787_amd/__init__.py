@@ -71,7 +71,9 @@ class Report(ctypes.Structure):
 class Timing(ctypes.Structure):
     _fields_ = [("engine_ms", ctypes.c_double), ("rounds", ctypes.c_int64),
                 ("swept", ctypes.c_int64), ("edits", ctypes.c_int64), ("voxels", ctypes.c_int64),
-                ("tiles", ctypes.c_int64), ("grid", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("tiles", ctypes.c_int64), ("grid", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("first_round_ms", ctypes.c_double), ("detect_ms", ctypes.c_double),
+                ("apply_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

@@ -92,7 +92,7 @@ VerifyLayout verify_layout(const Geo& G) {
 // bytes is cleared by one kernel before the launch.
 // ---------------------------------------------------------------------------
 struct BatchPlan {
-  size_t ctl = 0, desc = 0, out = 0, fields = 0, dirs = 0, total = 0;
+  size_t ctl = 0, desc = 0, out = 0, trace = 0, fields = 0, dirs = 0, total = 0;
   int64_t total_tiles = 0, total_segs = 0;
   std::vector<FieldDesc> fd;
   std::vector<size_t> field_off, dirs_off;
@@ -140,7 +140,8 @@ int plan_batch(int32_t n, const pmsz_field* fields, const uint8_t* const* dirs_g
   P.ctl = 0;
   P.desc = align_up(sizeof(EngineCtl));
   P.out = P.desc + align_up(sizeof(FieldDesc) * (size_t)n);
-  P.fields = P.out + align_up(sizeof(FieldIter) * (size_t)n);
+  P.trace = P.out + align_up(sizeof(FieldIter) * (size_t)n);
+  P.fields = P.trace + align_up(kTraceBytes);
   P.dirs = P.fields + fbytes;
   P.total = P.dirs + dbytes;
   return PMSZ_OK;
@@ -209,7 +210,7 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
     d.dirs = d.dirs_given ? (uint8_t*)dirs_given[i] : (uint8_t*)(base + P.dirs + P.dirs_off[i]);
   }
   const size_t up = sizeof(FieldDesc) * (size_t)n;
-  const size_t down = sizeof(EngineCtl) + sizeof(FieldIter) * (size_t)n;
+  const size_t down = sizeof(EngineCtl) + kTraceBytes + sizeof(FieldIter) * (size_t)n;
   void* stage;
   int r = staging(t_stage, up > down ? up : down, &stage);
   if (r) return r;
@@ -227,6 +228,7 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
   a.total_tiles = P.total_tiles;
   a.total_segs = P.total_segs;
   a.max_rounds = -1;
+  a.trace = (unsigned long long*)(base + P.trace);
   Timing& tm = t_timing;
   if (!tm.ev[0])
     for (auto& e : tm.ev) HIP_TRY(hipEventCreate(&e));
@@ -237,11 +239,15 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
   // the staging buffer is reused for the results: the upload above is
   // stream-ordered before this copy, so it has been consumed
   HIP_TRY(hipMemcpyAsync(stage, ctl, sizeof(EngineCtl), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync((char*)stage + sizeof(EngineCtl), out, sizeof(FieldIter) * (size_t)n,
+  HIP_TRY(hipMemcpyAsync((char*)stage + sizeof(EngineCtl), a.trace, kTraceBytes,
                          hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync((char*)stage + sizeof(EngineCtl) + kTraceBytes, out,
+                         sizeof(FieldIter) * (size_t)n, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   const EngineCtl* hc = (const EngineCtl*)stage;
-  const FieldIter* hs = (const FieldIter*)((char*)stage + sizeof(EngineCtl));
+  const unsigned long long* tr = (const unsigned long long*)((char*)stage + sizeof(EngineCtl));
+  const FieldIter* hs =
+      (const FieldIter*)((char*)stage + sizeof(EngineCtl) + kTraceBytes);
   if (hc->error) return fail(PMSZ_ERR_DEVICE, "grid barrier timed out in the correction engine");
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, tm.ev[0], tm.ev[1]));
@@ -250,6 +256,20 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
   tm.last.rounds = (int64_t)hc->rounds;
   tm.last.tiles = P.total_tiles;
   tm.last.grid = grid;
+  {
+    const int64_t R = hc->rounds < (unsigned long long)kTraceRounds ? (int64_t)hc->rounds
+                                                                       : kTraceRounds;
+    for (int64_t r = 0; r < R; ++r) {
+      const double d = (double)(tr[3 * r + 1] - tr[3 * r]) * 1e-5;  // 100 MHz ticks -> ms
+      const double ap = (double)(tr[3 * r + 2] - tr[3 * r + 1]) * 1e-5;
+      if (r == 0) {
+        tm.last.first_round_ms = (double)(tr[2] - tr[kTraceRounds * 3]) * 1e-5;
+      } else {
+        tm.last.detect_ms += d;
+        tm.last.apply_ms += ap;
+      }
+    }
+  }
   int first = PMSZ_OK;
   for (int32_t i = 0; i < n; ++i) {
     if (!hs[i].done) return fail(PMSZ_ERR_DEVICE, "field %d did not finish", i);
@@ -597,6 +617,7 @@ int pmsz_session_step(pmsz_session* S, int64_t max_rounds) {
   a.total_tiles = tiles;
   a.total_segs = segs;
   a.max_rounds = max_rounds;
+  a.trace = nullptr;
   int grid = 0;
   HIP_TRY(engine_launch(S->dtype, a, S->stream, &grid));
   HIP_TRY(hipMemcpyAsync(down, S->ws, sizeof(EngineCtl), hipMemcpyDeviceToHost, S->stream));

@@ -52,6 +52,22 @@ template <> struct FP<double> {
   __device__ static __forceinline__ double from(U b) { return __longlong_as_double((long long)b); }
 };
 
+// x with the bits of `m` OR-ed into its top 32 bits: m = 0 keeps x, m =
+// 0x7fc00000 (binary32) / 0x7ff80000 (binary64 high word) makes it a quiet
+// NaN.  A bitwise blend instead of a select keeps the load of x unconditional.
+__device__ __forceinline__ float or_high(float x, uint32_t m) {
+  return __uint_as_float(__float_as_uint(x) | m);
+}
+__device__ __forceinline__ double or_high(double x, uint32_t m) {
+  return __longlong_as_double(__double_as_longlong(x) | ((long long)m << 32));
+}
+template <class T>
+__device__ __forceinline__ uint32_t nan_mask();
+template <>
+__device__ __forceinline__ uint32_t nan_mask<float>() { return 0x7fc00000u; }
+template <>
+__device__ __forceinline__ uint32_t nan_mask<double>() { return 0x7ff80000u; }
+
 // Next representable value toward +inf (x finite).
 template <class T>
 __device__ __forceinline__ T next_up(T x) {
@@ -96,6 +112,32 @@ __device__ __forceinline__ T halving_edit(T g, T lb) {
   T h = g - lb;
   T m = lb + T(0.5) * h;
   return (m < g) ? m : lb;
+}
+
+// ---------------------------------------------------------------------------
+// Global-address-space views of pointers that arrive as generic pointers (for
+// instance through a descriptor table).  Loads through them are global loads,
+// which count only in the vector-memory counter; generic (flat) loads also
+// count in the LDS counter, so every LDS barrier would wait for them.
+// ---------------------------------------------------------------------------
+template <class T>
+using gptr = T __attribute__((address_space(1)))*;
+
+template <class T>
+__device__ __forceinline__ gptr<T> as_global(T* p) {
+  return (gptr<T>)p;
+}
+
+// ---------------------------------------------------------------------------
+// Block barrier that orders LDS only.  A plain __syncthreads() also waits for
+// every outstanding global load of the wave (gfx9 counts loads and stores in
+// one counter), which would cancel the register prefetch of the tile marches;
+// this barrier leaves global loads in flight.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
 // ---------------------------------------------------------------------------

@@ -176,17 +176,104 @@ __device__ __forceinline__ void mark_box(const FieldDesc& d, const TileBox& b, u
       }
 }
 
+// Exclusive prefix sum over the block; *total receives the sum (all threads).
+__device__ __forceinline__ int block_scan(int v, int* sh, int* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const int y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) sh[wave] = x;
+  __syncthreads();
+  int before = 0, all = 0;
+  for (int w = 0; w < 4; ++w) {
+    if (w < wave) before += sh[w];
+    all += sh[w];
+  }
+  __syncthreads();
+  *total = all;
+  return before + x - v;
+}
+
+constexpr int kApplyCap = 2048;   // targets per compaction pass
+
+// Apply pass over bitmap words [w0, w1) of one field: the block reads the
+// segment in one sweep (16 words per thread), compacts the set bits into an
+// LDS list, and edits the listed targets with all threads at once.
+template <class T>
+__device__ __forceinline__ void apply_segment(const FieldDesc& d, int32_t w0, int32_t w1,
+                                              bool edit, uint8_t* nxt, uint32_t* list,
+                                              int* scan, unsigned long long& nflag,
+                                              unsigned long long& at_lb,
+                                              unsigned long long& edits) {
+  constexpr int kPer = 16;
+  const int tid = threadIdx.x;
+  const int32_t wb = w0 + kPer * tid;
+  uint32_t wv[kPer];
+  int cnt = 0;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    wv[k] = (wb + k < w1) ? d.bm[wb + k] : 0u;
+    cnt += __popc(wv[k]);
+  }
+#pragma unroll
+  for (int k = 0; k < kPer; ++k)
+    if (wv[k]) d.bm[wb + k] = 0u;
+  nflag += (unsigned)cnt;
+  int total = 0;
+  const int off = block_scan(cnt, scan, &total);
+  const T* f = (const T*)d.f;
+  T* g = (T*)d.g;
+  const T xi = (T)d.xi_t;
+  for (int base = 0; base < total; base += kApplyCap) {
+    int o = off;
+    if (o < base + kApplyCap && o + cnt > base) {
+#pragma unroll
+      for (int k = 0; k < kPer; ++k) {
+        uint32_t bits = wv[k];
+        while (bits) {
+          const int b = __ffs(bits) - 1;
+          bits &= bits - 1;
+          if (o >= base && o < base + kApplyCap) list[o - base] = (uint32_t)((wb + k) * 32 + b);
+          ++o;
+        }
+      }
+    }
+    lds_barrier();
+    const int n = total - base < kApplyCap ? total - base : kApplyCap;
+    for (int j = tid; j < n; j += 256) {
+      const int32_t t = (int32_t)list[j];
+      const T gt = g[t];
+      const T lb = lower_bound<T>(f[t], xi);
+      const bool above = gt > lb;
+      if (above && edit) g[t] = halving_edit<T>(gt, lb);
+      edits += (above && edit) ? 1u : 0u;
+      at_lb += above ? 0u : 1u;
+      if (edit) mark_box(d, box_of(d.geo, t), nxt);
+    }
+    lds_barrier();
+  }
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void k_engine(EngineArgs a) {
   __shared__ TileLds<T> sm;
   __shared__ unsigned long long red[4];
   __shared__ int sh_f, sh_kind;
+  __shared__ uint32_t s_list[kApplyCap];
+  __shared__ int s_scan[4];
   const unsigned G = gridDim.x;
   const int tid = threadIdx.x;
+  for (int k = tid; k < kFlagWords; k += 256) sm.flags[k] = 0u;
+  __syncthreads();
   EngineCtl* ctl = a.ctl;
   unsigned gen = relaxed_load(&ctl->bar_gen);
   const unsigned long long E0 = ctl->epoch;
   unsigned long long E = E0;
+  const bool tracer = a.trace && blockIdx.x == 0 && tid == 0;
+  if (tracer) a.trace[kTraceRounds * 3] = wall_clock64();
 
   // Fields that have not started: every tile is active in their first round.
   if (a.has_fresh) {
@@ -203,6 +290,7 @@ __global__ __launch_bounds__(256) void k_engine(EngineArgs a) {
     if (engine_failed(ctl)) break;
     const int p = (int)(E & 1);
     const int q = (int)(E % 3), qn = (int)((E + 1) % 3);
+    if (tracer && r < kTraceRounds) a.trace[3 * r] = wall_clock64();
 
     // ---- block 0: persist the state of round E, clear next-but-one counters
     if (blockIdx.x == 0) {
@@ -239,9 +327,9 @@ __global__ __launch_bounds__(256) void k_engine(EngineArgs a) {
         sh_f = fi;
         sh_kind = kind;
       }
-      __syncthreads();
+      lds_barrier();
       const int fi = sh_f, kind = sh_kind;
-      __syncthreads();
+      lds_barrier();
       if (fi < 0) continue;
       const FieldDesc& d = a.fd[fi];
       if (tid == 0 && fi != cur) {
@@ -291,6 +379,7 @@ __global__ __launch_bounds__(256) void k_engine(EngineArgs a) {
     }
     grid_sync(ctl, G, gen);
     if (engine_failed(ctl)) break;
+    if (tracer && r < kTraceRounds) a.trace[3 * r + 1] = wall_clock64();
 
     // ---- apply -------------------------------------------------------------
     for (int64_t sg = blockIdx.x; sg < a.total_segs; sg += G) {
@@ -303,42 +392,10 @@ __global__ __launch_bounds__(256) void k_engine(EngineArgs a) {
       const bool bad = !s.started && (relaxed_load(&cq->bad_nf) || relaxed_load(&cq->bad_b));
       if (s.done || bad || mism == 0) continue;
       const bool edit = (long long)s.k < d.max_iters;
-      const int64_t w0 = (sg - d.seg_base) * kSegWords;
-      const int64_t w1 = (w0 + kSegWords < d.words) ? w0 + kSegWords : d.words;
-      const T* f = (const T*)d.f;
-      T* g = (T*)d.g;
-      const T xi = (T)d.xi_t;
+      const int32_t w0 = (int32_t)((sg - d.seg_base) * kSegWords);
+      const int32_t w1 = (w0 + kSegWords < d.words) ? w0 + (int32_t)kSegWords : (int32_t)d.words;
       unsigned long long nflag = 0, at_lb = 0, edits = 0;
-      for (int32_t w = (int32_t)w0 + tid; w < (int32_t)w1; w += 256) {
-        uint32_t bits = d.bm[w];
-        if (!bits) continue;
-        d.bm[w] = 0u;
-        nflag += __popc(bits);
-        TileBox last = {-1, -1, -1, -1, -1, -1};
-        while (bits) {
-          const int b = __ffs(bits) - 1;
-          bits &= bits - 1;
-          const int32_t t = w * 32 + b;
-          const T gt = g[t];
-          const T lb = lower_bound<T>(f[t], xi);
-          if (gt > lb) {
-            if (edit) {
-              g[t] = halving_edit<T>(gt, lb);
-              ++edits;
-            }
-          } else {
-            ++at_lb;
-          }
-          if (edit) {
-            const TileBox bx = box_of(d.geo, t);
-            if (bx.x0 != last.x0 || bx.x1 != last.x1 || bx.y0 != last.y0 || bx.y1 != last.y1 ||
-                bx.z0 != last.z0 || bx.z1 != last.z1) {
-              mark_box(d, bx, nxt);
-              last = bx;
-            }
-          }
-        }
-      }
+      apply_segment<T>(d, w0, w1, edit, nxt, s_list, s_scan, nflag, at_lb, edits);
       nflag = block_sum(nflag, red);
       at_lb = block_sum(at_lb, red);
       edits = block_sum(edits, red);
@@ -350,6 +407,7 @@ __global__ __launch_bounds__(256) void k_engine(EngineArgs a) {
     }
     grid_sync(ctl, G, gen);
     if (engine_failed(ctl)) break;
+    if (tracer && r < kTraceRounds) a.trace[3 * r + 2] = wall_clock64();
     const unsigned long long edited = relaxed_load(&ctl->edits[q]);
     ++E;
     if (edited == 0) break;

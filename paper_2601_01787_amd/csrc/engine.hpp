@@ -11,7 +11,7 @@
 
 namespace pmsz {
 
-constexpr int64_t kSegWords = 2048;  // bitmap words per apply segment (64K vertices)
+constexpr int64_t kSegWords = 4096;  // bitmap words per apply segment (128K vertices)
 
 // Iteration state of one field at the start of a round.  Double-buffered by
 // round parity: during round E block 0 persists the state of round E while
@@ -70,7 +70,14 @@ struct EngineArgs {
   int64_t total_tiles;
   int64_t total_segs;
   int64_t max_rounds;    // < 0: until every field is done
+  unsigned long long* trace;  // nullable: per-round timestamps (kTraceRounds x 3)
 };
+
+// Round trace: block 0 stamps the 100 MHz wall clock at the start of a round,
+// after its detect barrier and after its apply barrier, for the first
+// kTraceRounds rounds of a launch; slot kTraceRounds*3 holds the launch start.
+constexpr int kTraceRounds = 64;
+constexpr size_t kTraceBytes = (kTraceRounds * 3 + 1) * 8;
 
 // Host side (engine.hip).
 hipError_t engine_launch(int dtype, const EngineArgs& a, hipStream_t s, int* grid_out);

@@ -94,31 +94,88 @@ __device__ __forceinline__ unsigned unpack3(unsigned long long v, int k) {
 }
 using TileCounts = unsigned long long;  // packed, valid in thread 0
 
+// Flag words of one tile in LDS: the targets of a tile's vertices lie in its
+// one-vertex halo, i.e. in (chunk + 2) x (TY + 2) rows of 66 vertices (3D) or
+// (chunk + 2) rows of 258 vertices (2D); a row of the flag bitmap then spans at
+// most 4 (3D) or 10 (2D) 32-bit words, counted from the word holding the
+// row's first halo vertex.
+constexpr int kMaxChunk = 16;
+constexpr int kFlagW3 = 4, kFlagW2 = 10;
+constexpr int kFlagWords = (kMaxChunk + 2) * (TY + 2) * kFlagW3 > (kMaxChunk + 2) * kFlagW2
+                               ? (kMaxChunk + 2) * (TY + 2) * kFlagW3
+                               : (kMaxChunk + 2) * kFlagW2;
+
 template <class T>
-union TileLds {
-  T p3[2][3][PLANE];  // [field g or h, field f][ring slot][haloed plane]
-  T r2[2][3][RW];
+struct TileLds {
+  union {
+    T p3[2][3][PLANE];  // [field g or h, field f][ring slot][haloed plane]
+    T r2[2][3][RW];
+  } ring;
+  uint32_t flags[kFlagWords];
 };
 
 // Flag the targets of one vertex's mismatches (Sec. IV-A):
 //   ascending mismatch  -> the vertex that is now n_max (the spurious
 //                          maximum; the vertex itself for a false maximum);
 //   descending mismatch -> the original n_min, to be lowered below the rival.
-// The atomicOr returns nothing, so the march never waits on it.
-__device__ __forceinline__ unsigned flag_targets(int32_t i, int ca, int cd, int fa, int fd,
-                                                 int32_t nx, int32_t sxy, uint32_t* bm) {
+// Targets go to the tile's LDS flag words (row r of the halo box, word
+// offset from the row's first word); the tile flushes them to the global
+// bitmap once at its end, so the march never waits on global atomics.
+struct FlagBox {
+  int32_t x0, y0, z0;   // tile origin
+  int32_t nrow_y;       // rows per plane in the LDS flag layout (TY + 2 in 3D, 1 in 2D)
+  int32_t words;        // words per row (kFlagW3 / kFlagW2)
+  int32_t span;         // halo vertices per row minus one (TX + 1 or RX + 1)
+};
+
+__device__ __forceinline__ void flag_lds(uint32_t* flags, const FlagBox& fb, const TileGeo& G,
+                                         int32_t tx, int32_t ty, int32_t tz) {
+  const int32_t row = (tz - (fb.z0 - 1)) * fb.nrow_y + (fb.nrow_y > 1 ? ty - (fb.y0 - 1) : 0);
+  const int32_t rbase = (G.ndim == 3 ? G.nx * ty + G.sxy * tz : G.nx * ty);
+  const int32_t first = (rbase + fb.x0 - 1) >> 5;  // arithmetic shift: floor
+  const int32_t gb = rbase + tx;
+  atomicOr(flags + row * fb.words + ((gb >> 5) - first), 1u << (gb & 31));
+}
+
+__device__ __forceinline__ unsigned flag_targets3(int32_t X, int32_t Y, int32_t Z, int ca, int cd,
+                                                  int fa, int fd, const FlagBox& fb,
+                                                  const TileGeo& G, uint32_t* flags) {
   unsigned cnt = 0;
   if (ca != fa) {
-    const int32_t t = i + code_delta32(ca, nx, sxy);
-    atomicOr(bm + (t >> 5), 1u << (t & 31));
+    const int m = ca & 7, sg = (ca & 8) ? -1 : 1;
+    flag_lds(flags, fb, G, X + sg * (m & 1), Y + sg * ((m >> 1) & 1), Z + sg * ((m >> 2) & 1));
     ++cnt;
   }
   if (cd != fd) {
-    const int32_t t = i + code_delta32(fd, nx, sxy);
-    atomicOr(bm + (t >> 5), 1u << (t & 31));
+    const int m = fd & 7, sg = (fd & 8) ? -1 : 1;
+    flag_lds(flags, fb, G, X + sg * (m & 1), Y + sg * ((m >> 1) & 1), Z + sg * ((m >> 2) & 1));
     ++cnt;
   }
   return cnt;
+}
+
+// Flush the tile's LDS flag words into the field's bitmap and clear them.
+// Must follow a barrier after the last flag_lds of the tile.
+__device__ __forceinline__ void flush_flags(uint32_t* flags, const FlagBox& fb, const TileGeo& G,
+                                            int32_t rows, gptr<uint32_t> bm) {
+  const int32_t nw = rows * fb.words;
+  for (int k = threadIdx.x; k < nw; k += 256) {
+    const uint32_t v = flags[k];
+    if (!v) continue;
+    flags[k] = 0u;
+    const int32_t row = k / fb.words, wo = k - row * fb.words;
+    int32_t ty, tz;
+    if (fb.nrow_y > 1) {
+      tz = fb.z0 - 1 + row / fb.nrow_y;
+      ty = fb.y0 - 1 + row % fb.nrow_y;
+    } else {
+      tz = 0;
+      ty = fb.y0 - 1 + row;
+    }
+    const int32_t rbase = (G.ndim == 3 ? G.nx * ty + G.sxy * tz : G.nx * ty);
+    const int32_t first = (rbase + fb.x0 - 1) >> 5;
+    __hip_atomic_fetch_or(bm + first + wo, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 // Validation of one vertex (problem statement of Sec. III-B): finite values
@@ -132,18 +189,28 @@ __device__ __forceinline__ int bound_class(T a, T b, T xi) {
 // One 3D tile.  h: field whose directions are evaluated (g, or f for
 // KIND_DIRS).  f: original field (its stencil in the first round, its value
 // for validation).  dirs: direction bytes of f, read (NEXT, FIRST_GIVEN) or
-// written (FIRST, DIRS).  Returns the packed counts in thread 0.
+// written (FIRST, DIRS).  bm: the field's flag bitmap.  Returns the packed
+// counts in thread 0.
 //
-// Software pipeline: while plane z is evaluated from the LDS ring, plane z+2
-// and the direction bytes of plane z+1 are already on their way into
-// registers, so the march does not wait on memory at every step.
+// Software pipeline: the march is unrolled by two over register sets A and
+// B.  While plane z is evaluated from the LDS ring, planes z+2 and z+3 (and
+// the direction bytes of the next two planes) are in flight in A and B.
+// Loads are unconditional (out-of-box lanes read a clamped in-box address
+// and substitute NaN), and the barriers order LDS only, so the waits before
+// each commit cover just the set being committed.
 template <class T, int KIND>
-__device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* __restrict__ h,
-                            const T* __restrict__ f, uint8_t* __restrict__ dirs,
-                            uint32_t* __restrict__ bm, T xi, const TileGeo& G, int64_t tile) {
+__device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_in,
+                            const T* f_in, uint8_t* dirs_in, uint32_t* bm_in, T xi,
+                            const TileGeo G, int64_t tile) {
+  const gptr<const T> h = as_global(h_in);
+  const gptr<const T> f = as_global(f_in);
+  const gptr<uint8_t> dirs = as_global(dirs_in);
+  const gptr<uint32_t> bm = as_global(bm_in);
   constexpr int PER = (PLANE + 255) / 256;
   constexpr bool kTwo = (KIND == KIND_FIRST);          // f stencil needed
   constexpr bool kReadDirs = (KIND == KIND_NEXT || KIND == KIND_FIRST_GIVEN);
+  constexpr bool kGivenF = (KIND == KIND_FIRST_GIVEN);
+  constexpr bool kFlags = (KIND != KIND_DIRS);
   const int tid = threadIdx.x, tx = tid & (TX - 1), ty = tid / TX;
   const int32_t t32 = (int32_t)tile;
   const int32_t bx = t32 % G.tiles_x, by = (t32 / G.tiles_x) % G.tiles_y,
@@ -151,110 +218,148 @@ __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* __
   const int32_t x0 = bx * TX, y0 = by * TY, z0 = bz * G.chunk;
   const int32_t z1 = (z0 + G.chunk < G.nz) ? z0 + G.chunk : G.nz;
 
-  // plane element e of this thread: (row, col) in the haloed plane
   int32_t off[PER];
-  bool inxy[PER];
+  uint32_t xymask[PER];  // NaN bits for halo positions outside the box
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
     const int e = tid + k * 256;
     const int r = e / PX, c = e - r * PX;
     const int32_t X = x0 + c - 1, Y = y0 + r - 1;
-    inxy[k] = e < PLANE && X >= 0 && X < G.nx && Y >= 0 && Y < G.ny;
-    off[k] = X + G.nx * Y;
+    const bool in = e < PLANE && X >= 0 && X < G.nx && Y >= 0 && Y < G.ny;
+    xymask[k] = in ? 0u : nan_mask<T>();
+    off[k] = in ? X + G.nx * Y : 0;
   }
-  T ph[PER], pf[PER];
-  auto fetch = [&](int32_t z) {
+  struct Set {
+    T h[PER], f[PER];  // raw loaded values; masked to NaN at commit
+    uint32_t zmask;    // NaN bits when the plane lies outside the box
+    int d;
+    T fv;
+  };
+  const int32_t X = x0 + tx, Y = y0 + ty;
+  const bool mine = X < G.nx && Y < G.ny;
+  const int32_t col = mine ? X + G.nx * Y : 0;
+  // plane z of the haloed values into a set (NaN outside the box)
+  auto fetch = [&](int32_t z, Set& S) {
     const bool zin = z >= 0 && z < G.nz;
+    const int32_t zb = zin ? G.sxy * z : 0;
+    S.zmask = zin ? 0u : nan_mask<T>();
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-      const bool in = zin && inxy[k];
-      ph[k] = in ? h[off[k] + G.sxy * z] : FP<T>::nan();
-      if (kTwo) pf[k] = in ? f[off[k] + G.sxy * z] : FP<T>::nan();
+      S.h[k] = h[off[k] + zb];
+      if (kTwo) S.f[k] = f[off[k] + zb];
     }
   };
-  auto commit = [&](int slot) {
+  // this thread's direction byte (and f value) of plane z (z < nz)
+  auto fetch_own = [&](int32_t z, Set& S) {
+    const int32_t i = col + G.sxy * (z < G.nz ? z : 0);
+    if (kReadDirs) S.d = dirs[i];
+    if (kGivenF) S.fv = f[i];
+  };
+  auto commit = [&](int slot, const Set& S) {
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
       const int e = tid + k * 256;
       if (e < PLANE) {
-        sm.p3[0][slot][e] = ph[k];
-        if (kTwo) sm.p3[1][slot][e] = pf[k];
+        sm.ring.p3[0][slot][e] = or_high(S.h[k], xymask[k] | S.zmask);
+        if (kTwo) sm.ring.p3[1][slot][e] = or_high(S.f[k], xymask[k] | S.zmask);
       }
     }
   };
 
-  const int32_t X = x0 + tx, Y = y0 + ty;
-  const bool mine = X < G.nx && Y < G.ny;
-  const int32_t col = X + G.nx * Y;
   const int c = (ty + 1) * PX + (tx + 1);
-  fetch(z0 - 1);
-  commit(0);
-  fetch(z0);
-  commit(1);
-  fetch(z0 + 1);
-  int d_next = 0;
-  T f_next = T(0);
-  if (kReadDirs && mine) d_next = dirs[col + G.sxy * z0];
-  if (KIND == KIND_FIRST_GIVEN && mine) f_next = f[col + G.sxy * z0];
-
+  FlagBox fbx{x0, y0, z0, TY + 2, kFlagW3, TX + 1};
   unsigned mism = 0, nf = 0, nb = 0;
-  for (int32_t z = z0; z < z1; ++z) {
-    const int s = z - z0;
-    commit((s + 2) % 3);
-    if (z + 1 < z1) fetch(z + 2);
-    const int d_cur = d_next;
-    const T f_cur = f_next;
-    if (z + 1 < z1 && mine) {
-      if (kReadDirs) d_next = dirs[col + G.sxy * (z + 1)];
-      if (KIND == KIND_FIRST_GIVEN) f_next = f[col + G.sxy * (z + 1)];
+  auto compute = [&](int32_t z, int s, int d_cur, T f_cur) {
+    if (!mine) return;
+    const int32_t i = col + G.sxy * z;
+    const T* L = sm.ring.p3[0][s % 3];
+    const T* C = sm.ring.p3[0][(s + 1) % 3];
+    const T* P = sm.ring.p3[0][(s + 2) % 3];
+    const T v[15] = {L[c - PX - 1], L[c - PX], L[c - 1], L[c],     C[c - PX - 1],
+                     C[c - PX],     C[c - 1],  C[c],     C[c + 1], C[c + PX],
+                     C[c + PX + 1], P[c],      P[c + 1], P[c + PX], P[c + PX + 1]};
+    int ca, cd;
+    extremes<T, 15>(v, kOrder3, ca, cd);
+    if (KIND == KIND_DIRS) {
+      dirs[i] = (uint8_t)(ca | (cd << 4));
+      return;
     }
-    __syncthreads();
-    if (mine) {
-      const int32_t i = col + G.sxy * z;
-      const T* L = sm.p3[0][s % 3];
-      const T* C = sm.p3[0][(s + 1) % 3];
-      const T* P = sm.p3[0][(s + 2) % 3];
-      const T v[15] = {L[c - PX - 1], L[c - PX], L[c - 1], L[c],     C[c - PX - 1],
-                       C[c - PX],     C[c - 1],  C[c],     C[c + 1], C[c + PX],
-                       C[c + PX + 1], P[c],      P[c + 1], P[c + PX], P[c + PX + 1]};
-      int ca, cd;
-      extremes<T, 15>(v, kOrder3, ca, cd);
-      if (KIND == KIND_DIRS) {
-        dirs[i] = (uint8_t)(ca | (cd << 4));
-      } else {
-        int fa, fd;
-        if (KIND == KIND_FIRST) {
-          const T* Lf = sm.p3[1][s % 3];
-          const T* Cf = sm.p3[1][(s + 1) % 3];
-          const T* Pf = sm.p3[1][(s + 2) % 3];
-          const T w[15] = {Lf[c - PX - 1], Lf[c - PX], Lf[c - 1], Lf[c],      Cf[c - PX - 1],
-                           Cf[c - PX],     Cf[c - 1],  Cf[c],     Cf[c + 1],  Cf[c + PX],
-                           Cf[c + PX + 1], Pf[c],      Pf[c + 1], Pf[c + PX], Pf[c + PX + 1]};
-          extremes<T, 15>(w, kOrder3, fa, fd);
-          dirs[i] = (uint8_t)(fa | (fd << 4));
-          { const int bc = bound_class<T>(Cf[c], C[c], xi); nf += bc == 1; nb += bc == 2; }
-        } else {
-          fa = d_cur & 15;
-          fd = d_cur >> 4;
-          if (KIND == KIND_FIRST_GIVEN) { const int bc = bound_class<T>(f_cur, C[c], xi); nf += bc == 1; nb += bc == 2; }
-        }
-        mism += flag_targets(i, ca, cd, fa, fd, G.nx, G.sxy, bm);
+    int fa, fd;
+    if (KIND == KIND_FIRST) {
+      const T* Lf = sm.ring.p3[1][s % 3];
+      const T* Cf = sm.ring.p3[1][(s + 1) % 3];
+      const T* Pf = sm.ring.p3[1][(s + 2) % 3];
+      const T w[15] = {Lf[c - PX - 1], Lf[c - PX], Lf[c - 1], Lf[c],      Cf[c - PX - 1],
+                       Cf[c - PX],     Cf[c - 1],  Cf[c],     Cf[c + 1],  Cf[c + PX],
+                       Cf[c + PX + 1], Pf[c],      Pf[c + 1], Pf[c + PX], Pf[c + PX + 1]};
+      extremes<T, 15>(w, kOrder3, fa, fd);
+      dirs[i] = (uint8_t)(fa | (fd << 4));
+      const int bc = bound_class<T>(Cf[c], C[c], xi);
+      nf += bc == 1;
+      nb += bc == 2;
+    } else {
+      fa = d_cur & 15;
+      fd = d_cur >> 4;
+      if (kGivenF) {
+        const int bc = bound_class<T>(f_cur, C[c], xi);
+        nf += bc == 1;
+        nb += bc == 2;
       }
     }
-    __syncthreads();
+    if (kFlags) mism += flag_targets3(X, Y, z, ca, cd, fa, fd, fbx, G, sm.flags);
+  };
+  // one step of the march using set S (holding plane z+1 and the own data of plane z)
+  // Every global load of a step is unconditional (planes past the tile
+  // read clamped addresses), so the number of loads in flight is the same
+  // on every path and each commit waits only for its own set.
+  auto step = [&](int32_t z, Set& S, bool valid) {
+    const int s = z - z0;
+    commit((s + 2) % 3, S);
+    const int d_cur = S.d;
+    const T f_cur = S.fv;
+    fetch(z + 3, S);
+    lds_barrier();
+    if (valid) compute(z, s, d_cur, f_cur);
+    // issued after the compute so the old own values are dead (no register
+    // copy of an in-flight load at the loop latch)
+    fetch_own(z + 2, S);
+    lds_barrier();
+  };
+
+  Set A, B;
+  A.d = B.d = 0;
+  A.fv = B.fv = T(0);
+  fetch(z0 - 1, A);
+  commit(0, A);
+  fetch(z0, A);
+  commit(1, A);
+  fetch(z0 + 1, A);
+  fetch_own(z0, A);
+  fetch(z0 + 2, B);
+  fetch_own(z0 + 1, B);
+  for (int32_t z = z0; z < z1; z += 2) {
+    step(z, A, true);
+    step(z + 1, B, z + 1 < z1);
   }
   if (KIND == KIND_DIRS) return 0;
+  flush_flags(sm.flags, fbx, G, (z1 - z0 + 2) * (TY + 2), bm);
   return block_sum(pack3(mism, nf, nb), red);
 }
 
 // One 2D tile (256-wide strip, `chunk` rows), pipelined like tile3.
 template <class T, int KIND>
-__device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* __restrict__ h,
-                            const T* __restrict__ f, uint8_t* __restrict__ dirs,
-                            uint32_t* __restrict__ bm, T xi, const TileGeo& G, int64_t tile) {
+__device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_in,
+                            const T* f_in, uint8_t* dirs_in, uint32_t* bm_in, T xi,
+                            const TileGeo G, int64_t tile) {
+  const gptr<const T> h = as_global(h_in);
+  const gptr<const T> f = as_global(f_in);
+  const gptr<uint8_t> dirs = as_global(dirs_in);
+  const gptr<uint32_t> bm = as_global(bm_in);
   constexpr int PER = (RW + 255) / 256;
   constexpr bool kTwo = (KIND == KIND_FIRST);
   constexpr bool kReadDirs = (KIND == KIND_NEXT || KIND == KIND_FIRST_GIVEN);
+  constexpr bool kGivenF = (KIND == KIND_FIRST_GIVEN);
+  constexpr bool kFlags = (KIND != KIND_DIRS);
   const int tid = threadIdx.x;
   const int32_t t32 = (int32_t)tile;
   const int32_t bx = t32 % G.tiles_x, by = t32 / G.tiles_x;
@@ -262,90 +367,137 @@ __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* __
   const int32_t y1 = (y0 + G.chunk < G.ny) ? y0 + G.chunk : G.ny;
 
   int32_t xs[PER];
-  bool inx[PER];
+  uint32_t xmask[PER];  // NaN bits for halo positions outside the box
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
     const int e = tid + k * 256;
-    xs[k] = x0 + e - 1;
-    inx[k] = e < RW && xs[k] >= 0 && xs[k] < G.nx;
+    const int32_t xx = x0 + e - 1;
+    const bool in = e < RW && xx >= 0 && xx < G.nx;
+    xmask[k] = in ? 0u : nan_mask<T>();
+    xs[k] = in ? xx : 0;
   }
-  T ph[PER], pf[PER];
-  auto fetch = [&](int32_t y) {
+  struct Set {
+    T h[PER], f[PER];  // raw loaded values; masked to NaN at commit
+    uint32_t zmask;    // NaN bits when the row lies outside the box
+    int d;
+    T fv;
+  };
+  const int32_t X = x0 + tid;
+  const bool mine = X < G.nx;
+  const int32_t xo = mine ? X : 0;
+  auto fetch = [&](int32_t y, Set& S) {
     const bool yin = y >= 0 && y < G.ny;
+    const int32_t yb = yin ? G.nx * y : 0;
+    S.zmask = yin ? 0u : nan_mask<T>();
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
-      const bool in = yin && inx[k];
-      ph[k] = in ? h[xs[k] + G.nx * y] : FP<T>::nan();
-      if (kTwo) pf[k] = in ? f[xs[k] + G.nx * y] : FP<T>::nan();
+      S.h[k] = h[xs[k] + yb];
+      if (kTwo) S.f[k] = f[xs[k] + yb];
     }
   };
-  auto commit = [&](int slot) {
+  auto fetch_own = [&](int32_t y, Set& S) {
+    const int32_t i = xo + G.nx * (y < G.ny ? y : 0);
+    if (kReadDirs) S.d = dirs[i];
+    if (kGivenF) S.fv = f[i];
+  };
+  auto commit = [&](int slot, const Set& S) {
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
       const int e = tid + k * 256;
       if (e < RW) {
-        sm.r2[0][slot][e] = ph[k];
-        if (kTwo) sm.r2[1][slot][e] = pf[k];
+        sm.ring.r2[0][slot][e] = or_high(S.h[k], xmask[k] | S.zmask);
+        if (kTwo) sm.ring.r2[1][slot][e] = or_high(S.f[k], xmask[k] | S.zmask);
       }
     }
   };
 
-  const int32_t X = x0 + tid;
-  const bool mine = X < G.nx;
   const int c = tid + 1;
-  fetch(y0 - 1);
-  commit(0);
-  fetch(y0);
-  commit(1);
-  fetch(y0 + 1);
-  int d_next = 0;
-  T f_next = T(0);
-  if (kReadDirs && mine) d_next = dirs[X + G.nx * y0];
-  if (KIND == KIND_FIRST_GIVEN && mine) f_next = f[X + G.nx * y0];
-
+  // 2D flag rows are indexed by y: the box's "z" origin is the first row
+  FlagBox fbx{x0, y0, y0, 1, kFlagW2, RX + 1};
   unsigned mism = 0, nf = 0, nb = 0;
-  for (int32_t y = y0; y < y1; ++y) {
-    const int s = y - y0;
-    commit((s + 2) % 3);
-    if (y + 1 < y1) fetch(y + 2);
-    const int d_cur = d_next;
-    const T f_cur = f_next;
-    if (y + 1 < y1 && mine) {
-      if (kReadDirs) d_next = dirs[X + G.nx * (y + 1)];
-      if (KIND == KIND_FIRST_GIVEN) f_next = f[X + G.nx * (y + 1)];
+  auto compute = [&](int32_t y, int s, int d_cur, T f_cur) {
+    if (!mine) return;
+    const int32_t i = X + G.nx * y;
+    const T* L = sm.ring.r2[0][s % 3];
+    const T* C = sm.ring.r2[0][(s + 1) % 3];
+    const T* P = sm.ring.r2[0][(s + 2) % 3];
+    const T v[7] = {L[c - 1], L[c], C[c - 1], C[c], C[c + 1], P[c], P[c + 1]};
+    int ca, cd;
+    extremes<T, 7>(v, kOrder2, ca, cd);
+    if (KIND == KIND_DIRS) {
+      dirs[i] = (uint8_t)(ca | (cd << 4));
+      return;
     }
-    __syncthreads();
-    if (mine) {
-      const int32_t i = X + G.nx * y;
-      const T* L = sm.r2[0][s % 3];
-      const T* C = sm.r2[0][(s + 1) % 3];
-      const T* P = sm.r2[0][(s + 2) % 3];
-      const T v[7] = {L[c - 1], L[c], C[c - 1], C[c], C[c + 1], P[c], P[c + 1]};
-      int ca, cd;
-      extremes<T, 7>(v, kOrder2, ca, cd);
-      if (KIND == KIND_DIRS) {
-        dirs[i] = (uint8_t)(ca | (cd << 4));
-      } else {
-        int fa, fd;
-        if (KIND == KIND_FIRST) {
-          const T* Lf = sm.r2[1][s % 3];
-          const T* Cf = sm.r2[1][(s + 1) % 3];
-          const T* Pf = sm.r2[1][(s + 2) % 3];
-          const T w[7] = {Lf[c - 1], Lf[c], Cf[c - 1], Cf[c], Cf[c + 1], Pf[c], Pf[c + 1]};
-          extremes<T, 7>(w, kOrder2, fa, fd);
-          dirs[i] = (uint8_t)(fa | (fd << 4));
-          { const int bc = bound_class<T>(Cf[c], C[c], xi); nf += bc == 1; nb += bc == 2; }
-        } else {
-          fa = d_cur & 15;
-          fd = d_cur >> 4;
-          if (KIND == KIND_FIRST_GIVEN) { const int bc = bound_class<T>(f_cur, C[c], xi); nf += bc == 1; nb += bc == 2; }
-        }
-        mism += flag_targets(i, ca, cd, fa, fd, G.nx, G.sxy, bm);
+    int fa, fd;
+    if (KIND == KIND_FIRST) {
+      const T* Lf = sm.ring.r2[1][s % 3];
+      const T* Cf = sm.ring.r2[1][(s + 1) % 3];
+      const T* Pf = sm.ring.r2[1][(s + 2) % 3];
+      const T w[7] = {Lf[c - 1], Lf[c], Cf[c - 1], Cf[c], Cf[c + 1], Pf[c], Pf[c + 1]};
+      extremes<T, 7>(w, kOrder2, fa, fd);
+      dirs[i] = (uint8_t)(fa | (fd << 4));
+      const int bc = bound_class<T>(Cf[c], C[c], xi);
+      nf += bc == 1;
+      nb += bc == 2;
+    } else {
+      fa = d_cur & 15;
+      fd = d_cur >> 4;
+      if (kGivenF) {
+        const int bc = bound_class<T>(f_cur, C[c], xi);
+        nf += bc == 1;
+        nb += bc == 2;
       }
     }
-    __syncthreads();
+    if (kFlags) {
+      // 2D codes only use the x and y bits; rows are indexed by y
+      if (ca != fa) {
+        const int m = ca & 7, sg = (ca & 8) ? -1 : 1;
+        const int32_t yy = y + sg * ((m >> 1) & 1);
+        flag_lds(sm.flags, fbx, G, X + sg * (m & 1), yy, yy);
+        ++mism;
+      }
+      if (cd != fd) {
+        const int m = fd & 7, sg = (fd & 8) ? -1 : 1;
+        const int32_t yy = y + sg * ((m >> 1) & 1);
+        flag_lds(sm.flags, fbx, G, X + sg * (m & 1), yy, yy);
+        ++mism;
+      }
+    }
+  };
+  // Every global load of a step is unconditional (planes past the tile
+  // read clamped addresses), so the number of loads in flight is the same
+  // on every path and each commit waits only for its own set.
+  auto step = [&](int32_t y, Set& S, bool valid) {
+    const int s = y - y0;
+    commit((s + 2) % 3, S);
+    const int d_cur = S.d;
+    const T f_cur = S.fv;
+    fetch(y + 3, S);
+    lds_barrier();
+    if (valid) compute(y, s, d_cur, f_cur);
+    // issued after the compute so the old own values are dead (no register
+    // copy of an in-flight load at the loop latch)
+    fetch_own(y + 2, S);
+    lds_barrier();
+  };
+
+  Set A, B;
+  A.d = B.d = 0;
+  A.fv = B.fv = T(0);
+  fetch(y0 - 1, A);
+  commit(0, A);
+  fetch(y0, A);
+  commit(1, A);
+  fetch(y0 + 1, A);
+  fetch_own(y0, A);
+  fetch(y0 + 2, B);
+  fetch_own(y0 + 1, B);
+  for (int32_t y = y0; y < y1; y += 2) {
+    step(y, A, true);
+    step(y + 1, B, y + 1 < y1);
   }
   if (KIND == KIND_DIRS) return 0;
+  flush_flags(sm.flags, fbx, G, y1 - y0 + 2, bm);
   return block_sum(pack3(mism, nf, nb), red);
 }
 
