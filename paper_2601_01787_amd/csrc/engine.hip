@@ -210,17 +210,21 @@ __device__ __forceinline__ void apply_segment(const FieldDesc& d, int32_t w0, in
                                               unsigned long long& edits) {
   constexpr int kPer = 16;
   const int tid = threadIdx.x;
-  const int32_t wb = w0 + kPer * tid;
+  // thread t owns words w0 + t + 256 k: each load instruction reads 256
+  // consecutive words across the block
+  const gptr<uint32_t> bm = as_global(d.bm);
   uint32_t wv[kPer];
   int cnt = 0;
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
-    wv[k] = (wb + k < w1) ? d.bm[wb + k] : 0u;
+    const int32_t w = w0 + tid + 256 * k;
+    wv[k] = bm[w < w1 ? w : w0];
+    if (w >= w1) wv[k] = 0u;
     cnt += __popc(wv[k]);
   }
 #pragma unroll
   for (int k = 0; k < kPer; ++k)
-    if (wv[k]) d.bm[wb + k] = 0u;
+    if (wv[k]) bm[w0 + tid + 256 * k] = 0u;
   nflag += (unsigned)cnt;
   int total = 0;
   const int off = block_scan(cnt, scan, &total);
@@ -236,7 +240,8 @@ __device__ __forceinline__ void apply_segment(const FieldDesc& d, int32_t w0, in
         while (bits) {
           const int b = __ffs(bits) - 1;
           bits &= bits - 1;
-          if (o >= base && o < base + kApplyCap) list[o - base] = (uint32_t)((wb + k) * 32 + b);
+          if (o >= base && o < base + kApplyCap)
+            list[o - base] = (uint32_t)((w0 + tid + 256 * k) * 32 + b);
           ++o;
         }
       }
@@ -396,13 +401,16 @@ __global__ __launch_bounds__(256) void k_engine(EngineArgs a) {
       const int32_t w1 = (w0 + kSegWords < d.words) ? w0 + (int32_t)kSegWords : (int32_t)d.words;
       unsigned long long nflag = 0, at_lb = 0, edits = 0;
       apply_segment<T>(d, w0, w1, edit, nxt, s_list, s_scan, nflag, at_lb, edits);
-      nflag = block_sum(nflag, red);
-      at_lb = block_sum(at_lb, red);
-      edits = block_sum(edits, red);
+      // a segment holds at most 128K vertices: the three counts pack into
+      // 21-bit fields of one word for a single block reduction
+      const unsigned long long tot =
+          block_sum(pack3((unsigned)nflag, (unsigned)at_lb, (unsigned)edits), red);
       if (tid == 0) {
-        if (nflag) atomicAdd(&cq->nflag, nflag);
-        if (at_lb) atomicAdd(&cq->at_lb, at_lb);
-        if (edits) atomicAdd(&ctl->edits[q], edits);
+        const unsigned long long nf_ = unpack3(tot, 0), al_ = unpack3(tot, 1),
+                                 ed_ = unpack3(tot, 2);
+        if (nf_) atomicAdd(&cq->nflag, nf_);
+        if (al_) atomicAdd(&cq->at_lb, al_);
+        if (ed_) atomicAdd(&ctl->edits[q], ed_);
       }
     }
     grid_sync(ctl, G, gen);

@@ -100,6 +100,10 @@ using TileCounts = unsigned long long;  // packed, valid in thread 0
 // most 4 (3D) or 10 (2D) 32-bit words, counted from the word holding the
 // row's first halo vertex.
 constexpr int kMaxChunk = 16;
+// Planes in flight per tile march: four binary32 sets fit the register
+// budget of four waves per SIMD; binary64 values take twice the registers.
+template <class T>
+constexpr int sets_for() { return sizeof(T) == 4 ? 4 : 2; }
 constexpr int kFlagW3 = 4, kFlagW2 = 10;
 constexpr int kFlagWords = (kMaxChunk + 2) * (TY + 2) * kFlagW3 > (kMaxChunk + 2) * kFlagW2
                                ? (kMaxChunk + 2) * (TY + 2) * kFlagW3
@@ -192,9 +196,9 @@ __device__ __forceinline__ int bound_class(T a, T b, T xi) {
 // written (FIRST, DIRS).  bm: the field's flag bitmap.  Returns the packed
 // counts in thread 0.
 //
-// Software pipeline: the march is unrolled by two over register sets A and
-// B.  While plane z is evaluated from the LDS ring, planes z+2 and z+3 (and
-// the direction bytes of the next two planes) are in flight in A and B.
+// Software pipeline: the march is unrolled over kSets register sets.  While
+// plane z is evaluated from the LDS ring, the next kSets planes (and the
+// direction bytes of the next planes) are in flight in the other sets.
 // Loads are unconditional (out-of-box lanes read a clamped in-box address
 // and substitute NaN), and the barriers order LDS only, so the waits before
 // each commit cover just the set being committed.
@@ -211,6 +215,7 @@ __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_
   constexpr bool kReadDirs = (KIND == KIND_NEXT || KIND == KIND_FIRST_GIVEN);
   constexpr bool kGivenF = (KIND == KIND_FIRST_GIVEN);
   constexpr bool kFlags = (KIND != KIND_DIRS);
+  constexpr int kSets = sets_for<T>();
   const int tid = threadIdx.x, tx = tid & (TX - 1), ty = tid / TX;
   const int32_t t32 = (int32_t)tile;
   const int32_t bx = t32 % G.tiles_x, by = (t32 / G.tiles_x) % G.tiles_y,
@@ -317,29 +322,33 @@ __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_
     commit((s + 2) % 3, S);
     const int d_cur = S.d;
     const T f_cur = S.fv;
-    fetch(z + 3, S);
+    fetch(z + 1 + kSets, S);
     lds_barrier();
     if (valid) compute(z, s, d_cur, f_cur);
     // issued after the compute so the old own values are dead (no register
     // copy of an in-flight load at the loop latch)
-    fetch_own(z + 2, S);
+    fetch_own(z + kSets, S);
     lds_barrier();
   };
 
-  Set A, B;
-  A.d = B.d = 0;
-  A.fv = B.fv = T(0);
-  fetch(z0 - 1, A);
-  commit(0, A);
-  fetch(z0, A);
-  commit(1, A);
-  fetch(z0 + 1, A);
-  fetch_own(z0, A);
-  fetch(z0 + 2, B);
-  fetch_own(z0 + 1, B);
-  for (int32_t z = z0; z < z1; z += 2) {
-    step(z, A, true);
-    step(z + 1, B, z + 1 < z1);
+  Set Q[kSets];
+#pragma unroll
+  for (int k = 0; k < kSets; ++k) {
+    Q[k].d = 0;
+    Q[k].fv = T(0);
+  }
+  fetch(z0 - 1, Q[0]);
+  commit(0, Q[0]);
+  fetch(z0, Q[0]);
+  commit(1, Q[0]);
+#pragma unroll
+  for (int k = 0; k < kSets; ++k) {
+    fetch(z0 + 1 + k, Q[k]);
+    fetch_own(z0 + k, Q[k]);
+  }
+  for (int32_t z = z0; z < z1; z += kSets) {
+#pragma unroll
+    for (int k = 0; k < kSets; ++k) step(z + k, Q[k], z + k < z1);
   }
   if (KIND == KIND_DIRS) return 0;
   flush_flags(sm.flags, fbx, G, (z1 - z0 + 2) * (TY + 2), bm);
@@ -360,6 +369,7 @@ __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_
   constexpr bool kReadDirs = (KIND == KIND_NEXT || KIND == KIND_FIRST_GIVEN);
   constexpr bool kGivenF = (KIND == KIND_FIRST_GIVEN);
   constexpr bool kFlags = (KIND != KIND_DIRS);
+  constexpr int kSets = sets_for<T>();
   const int tid = threadIdx.x;
   const int32_t t32 = (int32_t)tile;
   const int32_t bx = t32 % G.tiles_x, by = t32 / G.tiles_x;
@@ -472,29 +482,33 @@ __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_
     commit((s + 2) % 3, S);
     const int d_cur = S.d;
     const T f_cur = S.fv;
-    fetch(y + 3, S);
+    fetch(y + 1 + kSets, S);
     lds_barrier();
     if (valid) compute(y, s, d_cur, f_cur);
     // issued after the compute so the old own values are dead (no register
     // copy of an in-flight load at the loop latch)
-    fetch_own(y + 2, S);
+    fetch_own(y + kSets, S);
     lds_barrier();
   };
 
-  Set A, B;
-  A.d = B.d = 0;
-  A.fv = B.fv = T(0);
-  fetch(y0 - 1, A);
-  commit(0, A);
-  fetch(y0, A);
-  commit(1, A);
-  fetch(y0 + 1, A);
-  fetch_own(y0, A);
-  fetch(y0 + 2, B);
-  fetch_own(y0 + 1, B);
-  for (int32_t y = y0; y < y1; y += 2) {
-    step(y, A, true);
-    step(y + 1, B, y + 1 < y1);
+  Set Q[kSets];
+#pragma unroll
+  for (int k = 0; k < kSets; ++k) {
+    Q[k].d = 0;
+    Q[k].fv = T(0);
+  }
+  fetch(y0 - 1, Q[0]);
+  commit(0, Q[0]);
+  fetch(y0, Q[0]);
+  commit(1, Q[0]);
+#pragma unroll
+  for (int k = 0; k < kSets; ++k) {
+    fetch(y0 + 1 + k, Q[k]);
+    fetch_own(y0 + k, Q[k]);
+  }
+  for (int32_t y = y0; y < y1; y += kSets) {
+#pragma unroll
+    for (int k = 0; k < kSets; ++k) step(y + k, Q[k], y + k < y1);
   }
   if (KIND == KIND_DIRS) return 0;
   flush_flags(sm.flags, fbx, G, y1 - y0 + 2, bm);
