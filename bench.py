@@ -151,7 +151,7 @@ def main():
         src = torch.empty(args.copy_probe_mib << 18, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        torch.add(src, 1.0, out=dst)  # one elementwise kernel: reads and writes the size once
         torch.cuda.synchronize()
         log("copy probe: %d MiB read, %d MiB written" % (args.copy_probe_mib, args.copy_probe_mib))
         del src, dst

@@ -263,7 +263,7 @@ __device__ __forceinline__ void apply_segment(const FieldDesc& d, int32_t w0, in
 }
 
 template <class T>
-__global__ __launch_bounds__(256) void k_engine(EngineArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 3))) void k_engine(EngineArgs a) {
   __shared__ TileLds<T> sm;
   __shared__ unsigned long long red[4];
   __shared__ int sh_f, sh_kind;

@@ -1,18 +1,30 @@
 // tiles.hpp -- the steepest-direction stencil over one LDS tile (internal).
 //
 // Directions (Sec. IV-A, n_min / n_max): for every vertex, the highest and the
-// lowest vertex of {i} plus its Freudenthal neighbours, ties broken by index.
-// The 15 (3D) or 7 (2D) candidates are visited in ascending vertex index,
-// which is the order -7..-1, self, +1..+7 of the signed direction codes
-// (index delta = bx + by*nx + bz*nx*ny is a mixed-radix number), so the
-// tie-break costs nothing: ">=" keeps the last (largest-index) maximum and
-// "<" keeps the first (smallest-index) minimum.  Neighbours outside the box
-// are NaN in the tile, which fails both comparisons.
+// lowest vertex of {i} plus its Freudenthal neighbours, ties broken by index
+// (larger index wins the maximum, smaller the minimum).
 //
-// Tiles: a 3D tile is 64 x 4 columns marched along z through a ring of three
-// haloed planes (66 x 6) in LDS; a 2D tile is a 256-wide strip marched along
-// y through a ring of three haloed rows (258).  Row loads are 64-wide and
-// coalesced.  A block of 256 threads processes one tile at a time.
+// Separable evaluation.  The Freudenthal neighbourhood of i is the union of
+// two lattice boxes that share i: the upper box i + {0,1}^d and the lower box
+// i - {0,1}^d.  Each box is reduced in x, then y, then z pairs; in every pair
+// all vertices of the second half have larger indices than all of the first
+// (index = x + nx*y + nx*ny*z), so keeping the second half on a tie for the
+// maximum and the first half for the minimum is exactly the index
+// tie-break.  The two boxes are then merged the same way (every vertex of the
+// lower box has an index <= i <= every vertex of the upper box).  A thread
+// marching along z (rows along y in 2D) reduces the 2 x 2 squares of each
+// plane once and uses them for the vertex below and the vertex above, so a
+// vertex costs 9 pair merges per direction instead of 14 comparisons.
+//
+// Absent neighbours (outside the box) are NaN in the tile.  In the upper box
+// the first half of a pair is present whenever the second is, in the lower box
+// the second half is present whenever the first is, so one ordered comparison
+// per pair both keeps present values over NaN and applies the tie-break.
+//
+// Tiles: a 3D tile is 64 x 4 columns marched along z; a 2D tile is a
+// 256-wide strip marched along y.  Each step stages one haloed plane (66 x 6)
+// or row (258) in LDS, double-buffered, with one barrier per step; loads are
+// row-contiguous.  A block of 256 threads processes one tile at a time.
 #pragma once
 
 #include "common.hpp"
@@ -24,22 +36,43 @@ constexpr int PX = TX + 2, PY = TY + 2;   // haloed plane 66 x 6
 constexpr int PLANE = PX * PY;
 constexpr int RX = 256, RW = RX + 2;      // 2D strip width, haloed row
 
-// Codes of the candidates in ascending vertex index.
-__device__ constexpr int kOrder3[15] = {15, 14, 13, 12, 11, 10, 9, 0, 1, 2, 3, 4, 5, 6, 7};
-__device__ constexpr int kOrder2[7] = {11, 10, 9, 0, 1, 2, 3};
+// Extremes of a subset of the candidates: the highest and the lowest value
+// and their direction codes (low three bits: +x, +y, +z of the offset mask;
+// bit 3: negative offset; 0 = the vertex itself).
+template <class T>
+struct Ext {
+  T hi, lo;
+  int ca, cd;
+};
 
-template <class T, int NC>
-__device__ __forceinline__ void extremes(const T (&v)[NC], const int (&order)[NC], int& ca,
-                                         int& cd) {
-  T hi = -__builtin_inf(), lo = __builtin_inf();
-  ca = 0;
-  cd = 0;
-#pragma unroll
-  for (int p = 0; p < NC; ++p) {
-    const T x = v[p];
-    if (x >= hi) { hi = x; ca = order[p]; }
-    if (x < lo) { lo = x; cd = order[p]; }
-  }
+template <class T>
+__device__ __forceinline__ Ext<T> ext_of(T v, int code) {
+  return Ext<T>{v, v, code, code};
+}
+
+template <class T>
+__device__ __forceinline__ Ext<T> with_bits(Ext<T> e, int bits) {
+  e.ca |= bits;
+  e.cd |= bits;
+  return e;
+}
+
+// Merge of disjoint halves A and B, every vertex of B having a larger index
+// than every vertex of A; the maximum keeps B on a tie, the minimum keeps A.
+// merge_up: valid when B is absent (NaN) whenever A is (upper box pairs);
+// merge_dn: valid when A is absent whenever B is (lower box pairs).
+template <class T>
+__device__ __forceinline__ Ext<T> merge_up(const Ext<T>& A, const Ext<T>& B) {
+  const bool bh = B.hi >= A.hi;  // false when B is NaN
+  const bool bl = B.lo < A.lo;
+  return Ext<T>{bh ? B.hi : A.hi, bl ? B.lo : A.lo, bh ? B.ca : A.ca, bl ? B.cd : A.cd};
+}
+
+template <class T>
+__device__ __forceinline__ Ext<T> merge_dn(const Ext<T>& A, const Ext<T>& B) {
+  const bool bh = !(A.hi > B.hi);  // true when A is NaN
+  const bool bl = !(A.lo <= B.lo);
+  return Ext<T>{bh ? B.hi : A.hi, bl ? B.lo : A.lo, bh ? B.ca : A.ca, bl ? B.cd : A.cd};
 }
 
 // Shape of one field as the tile code sees it.
@@ -101,9 +134,10 @@ using TileCounts = unsigned long long;  // packed, valid in thread 0
 // row's first halo vertex.
 constexpr int kMaxChunk = 16;
 // Planes in flight per tile march: four binary32 sets fit the register
-// budget of four waves per SIMD; binary64 values take twice the registers.
-template <class T>
-constexpr int sets_for() { return sizeof(T) == 4 ? 4 : 2; }
+// budget of four waves per SIMD; binary64 values, and the first round (which
+// loads two fields per plane), take twice the registers per set.
+template <class T, int KIND>
+constexpr int sets_for() { return (sizeof(T) == 4 && KIND != KIND_FIRST) ? 4 : 2; }
 constexpr int kFlagW3 = 4, kFlagW2 = 10;
 constexpr int kFlagWords = (kMaxChunk + 2) * (TY + 2) * kFlagW3 > (kMaxChunk + 2) * kFlagW2
                                ? (kMaxChunk + 2) * (TY + 2) * kFlagW3
@@ -112,8 +146,8 @@ constexpr int kFlagWords = (kMaxChunk + 2) * (TY + 2) * kFlagW3 > (kMaxChunk + 2
 template <class T>
 struct TileLds {
   union {
-    T p3[2][3][PLANE];  // [field g or h, field f][ring slot][haloed plane]
-    T r2[2][3][RW];
+    T p3[2][2][PLANE];  // [field g or h, field f][buffer][haloed plane]
+    T r2[2][2][RW];
   } ring;
   uint32_t flags[kFlagWords];
 };
@@ -196,12 +230,18 @@ __device__ __forceinline__ int bound_class(T a, T b, T xi) {
 // written (FIRST, DIRS).  bm: the field's flag bitmap.  Returns the packed
 // counts in thread 0.
 //
-// Software pipeline: the march is unrolled over kSets register sets.  While
-// plane z is evaluated from the LDS ring, the next kSets planes (and the
-// direction bytes of the next planes) are in flight in the other sets.
-// Loads are unconditional (out-of-box lanes read a clamped in-box address
-// and substitute NaN), and the barriers order LDS only, so the waits before
-// each commit cover just the set being committed.
+// The march visits planes p = z0-1 .. z1 (z1 = end of the tile).  Step p
+// stages plane p in LDS, reduces the thread's upper square (x..x+1, y..y+1)
+// and lower square (x-1..x, y-1..y) of plane p, completes the upper box of
+// vertex p-1 and the lower box of vertex p, and finishes vertex p-1.
+//
+// Software pipeline: the march is unrolled over kSets register sets; while
+// plane p is reduced, planes p+1 .. p+kSets-1 (and the direction bytes of
+// the matching vertices) are in flight in the other sets.  Loads are
+// unconditional (out-of-box lanes read a clamped in-box address and
+// substitute NaN at commit), and the barriers order LDS only, so the wait
+// before each commit covers just the set being committed.  Two LDS buffers
+// with one barrier per step suffice: a step reads only its own plane.
 template <class T, int KIND>
 __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_in,
                             const T* f_in, uint8_t* dirs_in, uint32_t* bm_in, T xi,
@@ -214,8 +254,7 @@ __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_
   constexpr bool kTwo = (KIND == KIND_FIRST);          // f stencil needed
   constexpr bool kReadDirs = (KIND == KIND_NEXT || KIND == KIND_FIRST_GIVEN);
   constexpr bool kGivenF = (KIND == KIND_FIRST_GIVEN);
-  constexpr bool kFlags = (KIND != KIND_DIRS);
-  constexpr int kSets = sets_for<T>();
+  constexpr int kSets = sets_for<T, KIND>();
   const int tid = threadIdx.x, tx = tid & (TX - 1), ty = tid / TX;
   const int32_t t32 = (int32_t)tile;
   const int32_t bx = t32 % G.tiles_x, by = (t32 / G.tiles_x) % G.tiles_y,
@@ -235,15 +274,14 @@ __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_
     off[k] = in ? X + G.nx * Y : 0;
   }
   struct Set {
-    T h[PER], f[PER];  // raw loaded values; masked to NaN at commit
+    T h[PER], f[PER];  // raw loaded values of one plane; masked to NaN at commit
     uint32_t zmask;    // NaN bits when the plane lies outside the box
-    int d;
-    T fv;
+    int d;             // direction byte of f at this column, one plane lower
+    T fv;              // value of f there (given directions)
   };
   const int32_t X = x0 + tx, Y = y0 + ty;
   const bool mine = X < G.nx && Y < G.ny;
   const int32_t col = mine ? X + G.nx * Y : 0;
-  // plane z of the haloed values into a set (NaN outside the box)
   auto fetch = [&](int32_t z, Set& S) {
     const bool zin = z >= 0 && z < G.nz;
     const int32_t zb = zin ? G.sxy * z : 0;
@@ -254,81 +292,95 @@ __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_
       if (kTwo) S.f[k] = f[off[k] + zb];
     }
   };
-  // this thread's direction byte (and f value) of plane z (z < nz)
-  auto fetch_own = [&](int32_t z, Set& S) {
-    const int32_t i = col + G.sxy * (z < G.nz ? z : 0);
+  auto fetch_own = [&](int32_t v, Set& S) {
+    const int32_t i = col + G.sxy * (v >= 0 && v < G.nz ? v : 0);
     if (kReadDirs) S.d = dirs[i];
     if (kGivenF) S.fv = f[i];
   };
-  auto commit = [&](int slot, const Set& S) {
+  auto commit = [&](int buf, const Set& S) {
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
       const int e = tid + k * 256;
       if (e < PLANE) {
-        sm.ring.p3[0][slot][e] = or_high(S.h[k], xymask[k] | S.zmask);
-        if (kTwo) sm.ring.p3[1][slot][e] = or_high(S.f[k], xymask[k] | S.zmask);
+        sm.ring.p3[0][buf][e] = or_high(S.h[k], xymask[k] | S.zmask);
+        if (kTwo) sm.ring.p3[1][buf][e] = or_high(S.f[k], xymask[k] | S.zmask);
       }
     }
   };
 
   const int c = (ty + 1) * PX + (tx + 1);
+  // upper and lower 2 x 2 squares of the plane in LDS around this column
+  auto squares = [&](const T* P, Ext<T>& up, Ext<T>& dn) {
+    const Ext<T> r0 = merge_up(ext_of(P[c], 0), ext_of(P[c + 1], 1));
+    const Ext<T> r1 = merge_up(ext_of(P[c + PX], 2), ext_of(P[c + PX + 1], 3));
+    up = merge_up(r0, r1);
+    const Ext<T> q0 = merge_dn(ext_of(P[c - PX - 1], 11), ext_of(P[c - PX], 10));
+    const Ext<T> q1 = merge_dn(ext_of(P[c - 1], 9), ext_of(P[c], 0));
+    dn = merge_dn(q0, q1);
+  };
   FlagBox fbx{x0, y0, z0, TY + 2, kFlagW3, TX + 1};
   unsigned mism = 0, nf = 0, nb = 0;
-  auto compute = [&](int32_t z, int s, int d_cur, T f_cur) {
-    if (!mine) return;
-    const int32_t i = col + G.sxy * z;
-    const T* L = sm.ring.p3[0][s % 3];
-    const T* C = sm.ring.p3[0][(s + 1) % 3];
-    const T* P = sm.ring.p3[0][(s + 2) % 3];
-    const T v[15] = {L[c - PX - 1], L[c - PX], L[c - 1], L[c],     C[c - PX - 1],
-                     C[c - PX],     C[c - 1],  C[c],     C[c + 1], C[c + PX],
-                     C[c + PX + 1], P[c],      P[c + 1], P[c + PX], P[c + PX + 1]};
-    int ca, cd;
-    extremes<T, 15>(v, kOrder3, ca, cd);
-    if (KIND == KIND_DIRS) {
-      dirs[i] = (uint8_t)(ca | (cd << 4));
-      return;
-    }
-    int fa, fd;
-    if (KIND == KIND_FIRST) {
-      const T* Lf = sm.ring.p3[1][s % 3];
-      const T* Cf = sm.ring.p3[1][(s + 1) % 3];
-      const T* Pf = sm.ring.p3[1][(s + 2) % 3];
-      const T w[15] = {Lf[c - PX - 1], Lf[c - PX], Lf[c - 1], Lf[c],      Cf[c - PX - 1],
-                       Cf[c - PX],     Cf[c - 1],  Cf[c],     Cf[c + 1],  Cf[c + PX],
-                       Cf[c + PX + 1], Pf[c],      Pf[c + 1], Pf[c + PX], Pf[c + PX + 1]};
-      extremes<T, 15>(w, kOrder3, fa, fd);
-      dirs[i] = (uint8_t)(fa | (fd << 4));
-      const int bc = bound_class<T>(Cf[c], C[c], xi);
-      nf += bc == 1;
-      nb += bc == 2;
-    } else {
-      fa = d_cur & 15;
-      fd = d_cur >> 4;
-      if (kGivenF) {
-        const int bc = bound_class<T>(f_cur, C[c], xi);
-        nf += bc == 1;
-        nb += bc == 2;
-      }
-    }
-    if (kFlags) mism += flag_targets3(X, Y, z, ca, cd, fa, fd, fbx, G, sm.flags);
-  };
-  // one step of the march using set S (holding plane z+1 and the own data of plane z)
-  // Every global load of a step is unconditional (planes past the tile
-  // read clamped addresses), so the number of loads in flight is the same
-  // on every path and each commit waits only for its own set.
-  auto step = [&](int32_t z, Set& S, bool valid) {
-    const int s = z - z0;
-    commit((s + 2) % 3, S);
+  // carried from plane p-1: its squares, the lower box of vertex p-1 and the
+  // centre values (for validation)
+  Ext<T> gu{}, gl{}, gbox{}, fu{}, fl{}, fbox{};
+  T gc = T(0), fc = T(0);
+  auto step = [&](int32_t p, Set& S, bool out) {
+    const int buf = (p - z0 + 1) & 1;
+    commit(buf, S);
     const int d_cur = S.d;
     const T f_cur = S.fv;
-    fetch(z + 1 + kSets, S);
+    fetch(p + kSets, S);
     lds_barrier();
-    if (valid) compute(z, s, d_cur, f_cur);
-    // issued after the compute so the old own values are dead (no register
-    // copy of an in-flight load at the loop latch)
-    fetch_own(z + kSets, S);
-    lds_barrier();
+    Ext<T> su, sd;
+    squares(sm.ring.p3[0][buf], su, sd);
+    const Ext<T> glo = merge_dn(with_bits(gl, 12), sd);  // lower box of vertex p
+    Ext<T> fsu, fsd, flo;
+    if (kTwo) {
+      squares(sm.ring.p3[1][buf], fsu, fsd);
+      flo = merge_dn(with_bits(fl, 12), fsd);
+    }
+    if (out && mine) {
+      const int32_t v = p - 1;
+      const int32_t i = col + G.sxy * v;
+      const Ext<T> e = merge_up(gbox, merge_up(gu, with_bits(su, 4)));
+      const int ca = e.ca, cd = e.cd;
+      if (KIND == KIND_DIRS) {
+        dirs[i] = (uint8_t)(ca | (cd << 4));
+      } else {
+        int fa, fd;
+        if (KIND == KIND_FIRST) {
+          const Ext<T> ef = merge_up(fbox, merge_up(fu, with_bits(fsu, 4)));
+          fa = ef.ca;
+          fd = ef.cd;
+          dirs[i] = (uint8_t)(fa | (fd << 4));
+          const int bc = bound_class<T>(fc, gc, xi);
+          nf += bc == 1;
+          nb += bc == 2;
+        } else {
+          fa = d_cur & 15;
+          fd = d_cur >> 4;
+          if (kGivenF) {
+            const int bc = bound_class<T>(f_cur, gc, xi);
+            nf += bc == 1;
+            nb += bc == 2;
+          }
+        }
+        mism += flag_targets3(X, Y, v, ca, cd, fa, fd, fbx, G, sm.flags);
+      }
+    }
+    gu = su;
+    gl = sd;
+    gbox = glo;
+    gc = sm.ring.p3[0][buf][c];
+    if (kTwo) {
+      fu = fsu;
+      fl = fsd;
+      fbox = flo;
+      fc = sm.ring.p3[1][buf][c];
+    }
+    // issued after the evaluation so the old own values are dead (no
+    // register copy of an in-flight load at the loop latch)
+    fetch_own(p + kSets - 1, S);
   };
 
   Set Q[kSets];
@@ -336,26 +388,24 @@ __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_
   for (int k = 0; k < kSets; ++k) {
     Q[k].d = 0;
     Q[k].fv = T(0);
+    fetch(z0 - 1 + k, Q[k]);
+    fetch_own(z0 - 2 + k, Q[k]);
   }
-  fetch(z0 - 1, Q[0]);
-  commit(0, Q[0]);
-  fetch(z0, Q[0]);
-  commit(1, Q[0]);
+  step(z0 - 1, Q[0], false);
+  step(z0, Q[1 % kSets], false);
+  for (int32_t p = z0 + 1; p <= z1; p += kSets) {
 #pragma unroll
-  for (int k = 0; k < kSets; ++k) {
-    fetch(z0 + 1 + k, Q[k]);
-    fetch_own(z0 + k, Q[k]);
-  }
-  for (int32_t z = z0; z < z1; z += kSets) {
-#pragma unroll
-    for (int k = 0; k < kSets; ++k) step(z + k, Q[k], z + k < z1);
+    for (int k = 0; k < kSets; ++k) step(p + k, Q[(k + 2) % kSets], p + k <= z1);
   }
   if (KIND == KIND_DIRS) return 0;
+  lds_barrier();
   flush_flags(sm.flags, fbx, G, (z1 - z0 + 2) * (TY + 2), bm);
   return block_sum(pack3(mism, nf, nb), red);
 }
 
-// One 2D tile (256-wide strip, `chunk` rows), pipelined like tile3.
+// One 2D tile (256-wide strip, `chunk` rows), marched along y like tile3:
+// step r stages row r, reduces the thread's upper pair (x..x+1) and lower
+// pair (x-1..x) and finishes vertex r-1.
 template <class T, int KIND>
 __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_in,
                             const T* f_in, uint8_t* dirs_in, uint32_t* bm_in, T xi,
@@ -368,8 +418,7 @@ __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_
   constexpr bool kTwo = (KIND == KIND_FIRST);
   constexpr bool kReadDirs = (KIND == KIND_NEXT || KIND == KIND_FIRST_GIVEN);
   constexpr bool kGivenF = (KIND == KIND_FIRST_GIVEN);
-  constexpr bool kFlags = (KIND != KIND_DIRS);
-  constexpr int kSets = sets_for<T>();
+  constexpr int kSets = sets_for<T, KIND>();
   const int tid = threadIdx.x;
   const int32_t t32 = (int32_t)tile;
   const int32_t bx = t32 % G.tiles_x, by = t32 / G.tiles_x;
@@ -387,8 +436,8 @@ __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_
     xs[k] = in ? xx : 0;
   }
   struct Set {
-    T h[PER], f[PER];  // raw loaded values; masked to NaN at commit
-    uint32_t zmask;    // NaN bits when the row lies outside the box
+    T h[PER], f[PER];
+    uint32_t zmask;
     int d;
     T fv;
   };
@@ -405,90 +454,100 @@ __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_
       if (kTwo) S.f[k] = f[xs[k] + yb];
     }
   };
-  auto fetch_own = [&](int32_t y, Set& S) {
-    const int32_t i = xo + G.nx * (y < G.ny ? y : 0);
+  auto fetch_own = [&](int32_t v, Set& S) {
+    const int32_t i = xo + G.nx * (v >= 0 && v < G.ny ? v : 0);
     if (kReadDirs) S.d = dirs[i];
     if (kGivenF) S.fv = f[i];
   };
-  auto commit = [&](int slot, const Set& S) {
+  auto commit = [&](int buf, const Set& S) {
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
       const int e = tid + k * 256;
       if (e < RW) {
-        sm.ring.r2[0][slot][e] = or_high(S.h[k], xmask[k] | S.zmask);
-        if (kTwo) sm.ring.r2[1][slot][e] = or_high(S.f[k], xmask[k] | S.zmask);
+        sm.ring.r2[0][buf][e] = or_high(S.h[k], xmask[k] | S.zmask);
+        if (kTwo) sm.ring.r2[1][buf][e] = or_high(S.f[k], xmask[k] | S.zmask);
       }
     }
   };
 
   const int c = tid + 1;
+  auto pairs = [&](const T* R, Ext<T>& up, Ext<T>& dn) {
+    up = merge_up(ext_of(R[c], 0), ext_of(R[c + 1], 1));
+    dn = merge_dn(ext_of(R[c - 1], 9), ext_of(R[c], 0));
+  };
   // 2D flag rows are indexed by y: the box's "z" origin is the first row
   FlagBox fbx{x0, y0, y0, 1, kFlagW2, RX + 1};
   unsigned mism = 0, nf = 0, nb = 0;
-  auto compute = [&](int32_t y, int s, int d_cur, T f_cur) {
-    if (!mine) return;
-    const int32_t i = X + G.nx * y;
-    const T* L = sm.ring.r2[0][s % 3];
-    const T* C = sm.ring.r2[0][(s + 1) % 3];
-    const T* P = sm.ring.r2[0][(s + 2) % 3];
-    const T v[7] = {L[c - 1], L[c], C[c - 1], C[c], C[c + 1], P[c], P[c + 1]};
-    int ca, cd;
-    extremes<T, 7>(v, kOrder2, ca, cd);
-    if (KIND == KIND_DIRS) {
-      dirs[i] = (uint8_t)(ca | (cd << 4));
-      return;
-    }
-    int fa, fd;
-    if (KIND == KIND_FIRST) {
-      const T* Lf = sm.ring.r2[1][s % 3];
-      const T* Cf = sm.ring.r2[1][(s + 1) % 3];
-      const T* Pf = sm.ring.r2[1][(s + 2) % 3];
-      const T w[7] = {Lf[c - 1], Lf[c], Cf[c - 1], Cf[c], Cf[c + 1], Pf[c], Pf[c + 1]};
-      extremes<T, 7>(w, kOrder2, fa, fd);
-      dirs[i] = (uint8_t)(fa | (fd << 4));
-      const int bc = bound_class<T>(Cf[c], C[c], xi);
-      nf += bc == 1;
-      nb += bc == 2;
-    } else {
-      fa = d_cur & 15;
-      fd = d_cur >> 4;
-      if (kGivenF) {
-        const int bc = bound_class<T>(f_cur, C[c], xi);
-        nf += bc == 1;
-        nb += bc == 2;
-      }
-    }
-    if (kFlags) {
-      // 2D codes only use the x and y bits; rows are indexed by y
-      if (ca != fa) {
-        const int m = ca & 7, sg = (ca & 8) ? -1 : 1;
-        const int32_t yy = y + sg * ((m >> 1) & 1);
-        flag_lds(sm.flags, fbx, G, X + sg * (m & 1), yy, yy);
-        ++mism;
-      }
-      if (cd != fd) {
-        const int m = fd & 7, sg = (fd & 8) ? -1 : 1;
-        const int32_t yy = y + sg * ((m >> 1) & 1);
-        flag_lds(sm.flags, fbx, G, X + sg * (m & 1), yy, yy);
-        ++mism;
-      }
-    }
+  Ext<T> gu{}, gl{}, gbox{}, fu{}, fl{}, fbox{};
+  T gc = T(0), fc = T(0);
+  auto flag2 = [&](int32_t y, int code) {
+    const int m = code & 7, sg = (code & 8) ? -1 : 1;
+    const int32_t yy = y + sg * ((m >> 1) & 1);
+    flag_lds(sm.flags, fbx, G, X + sg * (m & 1), yy, yy);
   };
-  // Every global load of a step is unconditional (planes past the tile
-  // read clamped addresses), so the number of loads in flight is the same
-  // on every path and each commit waits only for its own set.
-  auto step = [&](int32_t y, Set& S, bool valid) {
-    const int s = y - y0;
-    commit((s + 2) % 3, S);
+  auto step = [&](int32_t r, Set& S, bool out) {
+    const int buf = (r - y0 + 1) & 1;
+    commit(buf, S);
     const int d_cur = S.d;
     const T f_cur = S.fv;
-    fetch(y + 1 + kSets, S);
+    fetch(r + kSets, S);
     lds_barrier();
-    if (valid) compute(y, s, d_cur, f_cur);
-    // issued after the compute so the old own values are dead (no register
-    // copy of an in-flight load at the loop latch)
-    fetch_own(y + kSets, S);
-    lds_barrier();
+    Ext<T> su, sd;
+    pairs(sm.ring.r2[0][buf], su, sd);
+    const Ext<T> glo = merge_dn(with_bits(gl, 10), sd);  // lower box of vertex r
+    Ext<T> fsu, fsd, flo;
+    if (kTwo) {
+      pairs(sm.ring.r2[1][buf], fsu, fsd);
+      flo = merge_dn(with_bits(fl, 10), fsd);
+    }
+    if (out && mine) {
+      const int32_t v = r - 1;
+      const int32_t i = X + G.nx * v;
+      const Ext<T> e = merge_up(gbox, merge_up(gu, with_bits(su, 2)));
+      const int ca = e.ca, cd = e.cd;
+      if (KIND == KIND_DIRS) {
+        dirs[i] = (uint8_t)(ca | (cd << 4));
+      } else {
+        int fa, fd;
+        if (KIND == KIND_FIRST) {
+          const Ext<T> ef = merge_up(fbox, merge_up(fu, with_bits(fsu, 2)));
+          fa = ef.ca;
+          fd = ef.cd;
+          dirs[i] = (uint8_t)(fa | (fd << 4));
+          const int bc = bound_class<T>(fc, gc, xi);
+          nf += bc == 1;
+          nb += bc == 2;
+        } else {
+          fa = d_cur & 15;
+          fd = d_cur >> 4;
+          if (kGivenF) {
+            const int bc = bound_class<T>(f_cur, gc, xi);
+            nf += bc == 1;
+            nb += bc == 2;
+          }
+        }
+        // 2D codes only use the x and y bits; rows are indexed by y
+        if (ca != fa) {
+          flag2(v, ca);
+          ++mism;
+        }
+        if (cd != fd) {
+          flag2(v, fd);
+          ++mism;
+        }
+      }
+    }
+    gu = su;
+    gl = sd;
+    gbox = glo;
+    gc = sm.ring.r2[0][buf][c];
+    if (kTwo) {
+      fu = fsu;
+      fl = fsd;
+      fbox = flo;
+      fc = sm.ring.r2[1][buf][c];
+    }
+    fetch_own(r + kSets - 1, S);
   };
 
   Set Q[kSets];
@@ -496,21 +555,17 @@ __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_
   for (int k = 0; k < kSets; ++k) {
     Q[k].d = 0;
     Q[k].fv = T(0);
+    fetch(y0 - 1 + k, Q[k]);
+    fetch_own(y0 - 2 + k, Q[k]);
   }
-  fetch(y0 - 1, Q[0]);
-  commit(0, Q[0]);
-  fetch(y0, Q[0]);
-  commit(1, Q[0]);
+  step(y0 - 1, Q[0], false);
+  step(y0, Q[1 % kSets], false);
+  for (int32_t r = y0 + 1; r <= y1; r += kSets) {
 #pragma unroll
-  for (int k = 0; k < kSets; ++k) {
-    fetch(y0 + 1 + k, Q[k]);
-    fetch_own(y0 + k, Q[k]);
-  }
-  for (int32_t y = y0; y < y1; y += kSets) {
-#pragma unroll
-    for (int k = 0; k < kSets; ++k) step(y + k, Q[k], y + k < y1);
+    for (int k = 0; k < kSets; ++k) step(r + k, Q[(k + 2) % kSets], r + k <= y1);
   }
   if (KIND == KIND_DIRS) return 0;
+  lds_barrier();
   flush_flags(sm.flags, fbx, G, y1 - y0 + 2, bm);
   return block_sum(pack3(mism, nf, nb), red);
 }
