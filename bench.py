@@ -114,6 +114,61 @@ def bench_batched(dev, n_fields, seed):
             "max_iterations": max(s["iterations"] for s in st_batch)}
 
 
+def bench_serving(dev, rates, n_requests, pool_per_class, seed):
+    """Open-loop serving: Poisson arrivals at each rate; requests drawn from a
+    pre-generated pool (generation stays out of the loop) over five classes
+    (128^3, 256^3, 512^3 Perlin; 1024^2, 4096^2 Gaussian peaks; binary32) with
+    relative bounds from {1e-2, 1e-3, 1e-4}.  The continuous-batching server
+    and a FIFO server of plain per-request launches replay the same arrival
+    sequence; every served result is compared with the request's alone result."""
+    import numpy as np
+    import torch
+
+    import paper_2601_01787_amd as pmsz
+    import synth
+    from paper_2601_01787_amd import serve
+    rng = np.random.default_rng(seed)
+    pool = []
+    for cls in ("perlin128", "perlin256", "perlin512", "peaks1024", "peaks4096"):
+        for j in range(pool_per_class):
+            rel = float(rng.choice([1e-2, 1e-3, 1e-4]))
+            s = int(rng.integers(1 << 30))
+            if cls.startswith("perlin"):
+                n = int(cls[6:])
+                f, fhat, xi = synth.perlin_case(n, 6, 8, rel, s, device=dev)
+            else:
+                n = int(cls[5:])
+                f, fhat, xi = synth.make_2d_case(n, n, rel, s, device=dev)
+            g, _ = pmsz.correct(f, fhat, xi)
+            pool.append({"cls": cls, "f": f, "fhat": fhat, "xi": xi, "g": g})
+    torch.cuda.synchronize()
+    out = []
+    for rate in rates:
+        arr = np.cumsum(rng.exponential(1.0 / rate, size=n_requests))
+        pick = rng.integers(len(pool), size=n_requests)
+        row = {"rate_req_s": rate, "requests": n_requests}
+        for kind in ("batched", "fifo"):
+            reqs = []
+            for i, (t, k) in enumerate(zip(arr, pick)):
+                p = pool[int(k)]
+                r = serve.Request(i, p["f"], p["fhat"], p["xi"], float(t))
+                reqs.append(r)
+            bad = []
+            which = {i: int(k) for i, k in enumerate(pick)}
+
+            def check(r):
+                if not torch.equal(r.g, pool[which[r.rid]]["g"]):
+                    bad.append(r.rid)
+
+            done = serve.run_open_loop(kind, reqs, dev, hbm_budget=96 << 30, max_fields=64,
+                                       rounds_per_step=4, check=check)
+            s = serve.latency_summary(done)
+            s["identical"] = not bad and len(done) == n_requests
+            row[kind] = s
+        out.append(row)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,6 +178,11 @@ def main():
     ap.add_argument("--cpu-planes", type=int, default=512)
     ap.add_argument("--batch-fields", type=int, default=256,
                     help="fields of the uneven 2D batch (0 skips the batched comparison)")
+    ap.add_argument("--serve-rates", default="50,200,500",
+                    help="Poisson arrival rates (req/s) of the serving comparison ('' skips it)")
+    ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-pool", type=int, default=4,
+                    help="pre-generated fields per request class")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -168,6 +228,7 @@ def main():
     for i in range(K):
         _, st = pmsz.correct(f, gs[W + i], xi, inplace=True, ws=ws)
         tm = pmsz.last_timing()
+        per_round = pmsz.last_rounds()
         eng_ms.append(tm["engine_ms"])
         tims.append(tm)
         stats.append(st)
@@ -202,13 +263,23 @@ def main():
                    "engine_ms_per_step": round(avg_ms, 4),
                    "first_round_ms": round(tm["first_round_ms"], 4),
                    "later_detect_ms": round(tm["detect_ms"], 4),
-                   "later_apply_ms": round(tm["apply_ms"], 4)},
+                   "later_apply_ms": round(tm["apply_ms"], 4),
+                   "per_round": {"detect_ms": [round(r["detect_ms"], 4) for r in per_round],
+                                 "apply_ms": [round(r["apply_ms"], 4) for r in per_round],
+                                 "swept": [r["swept"] for r in per_round],
+                                 "flagged": [r["flagged"] for r in per_round],
+                                 "edits": [r["edits"] for r in per_round]}},
     }
     del gs
     torch.cuda.empty_cache()
     if args.batch_fields:
         log("batched vs plain on", args.batch_fields, "2D fields")
         out["batched"] = bench_batched(dev, args.batch_fields, 256)
+        torch.cuda.empty_cache()
+    if args.serve_rates:
+        rates = [float(x) for x in args.serve_rates.split(",") if x]
+        log("serving: rates", rates, "x", args.serve_requests, "requests")
+        out["serving"] = bench_serving(dev, rates, args.serve_requests, args.serve_pool, 7)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) on", args.cpu_planes, "planes")

@@ -228,6 +228,24 @@ typedef struct {
 } pmsz_timing;
 int pmsz_last_timing(pmsz_timing* out);
 
+/* Per-round record of the last pmsz_correct / pmsz_correct_batched on this
+ * thread, for the first 64 rounds of the launch (diagnostics of the loop of
+ * Sec. IV-A).  Times are block 0's view on the device clock; the counts are
+ * totals over every field of the launch.  Round 0's detect_ms runs from the
+ * launch start. */
+typedef struct {
+  double detect_ms;  /* start of the round to the end of its detect pass   */
+  double apply_ms;   /* end of detect to the end of the apply pass          */
+  int64_t swept;     /* vertices examined by the detect pass                */
+  int64_t flagged;   /* |F|: distinct flagged vertices                      */
+  int64_t edits;     /* values changed by the apply pass                    */
+} pmsz_round;
+
+/* Copies min(cap, rounds recorded) records into out[] (host) and stores the
+ * number recorded (<= 64) in *n.  Returns PMSZ_ERR_INVALID_ARG if n is NULL,
+ * or if out is NULL while cap > 0. */
+int pmsz_last_rounds(pmsz_round* out, int64_t cap, int64_t* n);
+
 /* Name of a status code (static string). */
 const char* pmsz_status_string(int status);
 

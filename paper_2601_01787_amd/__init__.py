@@ -26,7 +26,7 @@ DEFAULT_MAX_ITERS = 1 << 40
 
 EXPORTS = ("pmsz_workspace_size", "pmsz_directions", "pmsz_correct",
            "pmsz_batched_workspace_size", "pmsz_correct_batched", "pmsz_labels",
-           "pmsz_verify", "pmsz_last_timing", "pmsz_session_workspace_size",
+           "pmsz_verify", "pmsz_last_timing", "pmsz_last_rounds", "pmsz_session_workspace_size",
            "pmsz_field_workspace_size", "pmsz_session_create", "pmsz_session_add",
            "pmsz_session_step", "pmsz_session_sync", "pmsz_session_result",
            "pmsz_session_remove", "pmsz_session_destroy", "pmsz_status_string",
@@ -79,6 +79,14 @@ class Timing(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
 
 
+class Round(ctypes.Structure):
+    _fields_ = [("detect_ms", ctypes.c_double), ("apply_ms", ctypes.c_double),
+                ("swept", ctypes.c_int64), ("flagged", ctypes.c_int64), ("edits", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class Field(ctypes.Structure):
     _fields_ = [("grid", Grid), ("f", ctypes.c_void_p), ("g", ctypes.c_void_p),
                 ("xi", ctypes.c_double)]
@@ -108,6 +116,8 @@ def load():
     L.pmsz_labels.argtypes = [G, vp, vp, vp, vp, sz, vp]
     L.pmsz_verify.argtypes = [G, vp, vp, vp, dbl, vp, sz, ctypes.POINTER(Report), vp]
     L.pmsz_last_timing.argtypes = [ctypes.POINTER(Timing)]
+    L.pmsz_last_rounds.argtypes = [ctypes.POINTER(Round), ctypes.c_int64,
+                                   ctypes.POINTER(ctypes.c_int64)]
     L.pmsz_session_workspace_size.argtypes = [i32, ctypes.POINTER(sz)]
     L.pmsz_field_workspace_size.argtypes = [G, ctypes.POINTER(sz)]
     L.pmsz_session_create.argtypes = [i32, i32, vp, sz, vp, ctypes.POINTER(vp)]
@@ -240,6 +250,15 @@ def last_timing():
     t = Timing()
     _raise_if(load().pmsz_last_timing(ctypes.byref(t)))
     return t.as_dict()
+
+
+def last_rounds():
+    """Per-round records (detect and apply time, vertices examined, |F|,
+    edits) of the last correction made on this thread."""
+    buf = (Round * 64)()
+    n = ctypes.c_int64()
+    _raise_if(load().pmsz_last_rounds(buf, 64, ctypes.byref(n)))
+    return [buf[i].as_dict() for i in range(min(n.value, 64))]
 
 
 def field_workspace_size(grid):

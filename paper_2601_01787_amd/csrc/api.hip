@@ -174,6 +174,8 @@ int staging(Staging& s, size_t bytes, void** out) {
 struct Timing {
   hipEvent_t ev[2] = {nullptr, nullptr};
   pmsz_timing last;
+  pmsz_round rounds[kTraceRounds];
+  int64_t nrounds = 0;
   ~Timing() {
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
@@ -207,6 +209,8 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
     d.st = (FieldState*)(fb + L.state);
     d.act = (uint8_t*)(fb + L.act);
     d.bm = (uint32_t*)(fb + L.bm);
+    d.list = (uint32_t*)(fb + L.list);
+    d.list_cap = list_capacity(d.geo);
     d.dirs = d.dirs_given ? (uint8_t*)dirs_given[i] : (uint8_t*)(base + P.dirs + P.dirs_off[i]);
   }
   const size_t up = sizeof(FieldDesc) * (size_t)n;
@@ -259,14 +263,21 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
   {
     const int64_t R = hc->rounds < (unsigned long long)kTraceRounds ? (int64_t)hc->rounds
                                                                        : kTraceRounds;
+    tm.nrounds = R;
     for (int64_t r = 0; r < R; ++r) {
-      const double d = (double)(tr[3 * r + 1] - tr[3 * r]) * 1e-5;  // 100 MHz ticks -> ms
-      const double ap = (double)(tr[3 * r + 2] - tr[3 * r + 1]) * 1e-5;
+      const unsigned long long* t = tr + kTraceSlots * r;
+      const double start = (double)(r == 0 ? tr[kTraceRounds * kTraceSlots] : t[0]);
+      pmsz_round& o = tm.rounds[r];
+      o.detect_ms = ((double)t[1] - start) * 1e-5;  // 100 MHz ticks -> ms
+      o.apply_ms = (double)(t[2] - t[1]) * 1e-5;
+      o.swept = (int64_t)t[3];
+      o.flagged = (int64_t)t[4];
+      o.edits = (int64_t)t[5];
       if (r == 0) {
-        tm.last.first_round_ms = (double)(tr[2] - tr[kTraceRounds * 3]) * 1e-5;
+        tm.last.first_round_ms = o.detect_ms + o.apply_ms;
       } else {
-        tm.last.detect_ms += d;
-        tm.last.apply_ms += ap;
+        tm.last.detect_ms += o.detect_ms;
+        tm.last.apply_ms += o.apply_ms;
       }
     }
   }
@@ -369,6 +380,14 @@ const char* pmsz_last_error(void) { return g_last_error.c_str(); }
 int pmsz_last_timing(pmsz_timing* out) {
   if (!out) return fail(PMSZ_ERR_INVALID_ARG, "NULL argument");
   *out = t_timing.last;
+  return PMSZ_OK;
+}
+
+int pmsz_last_rounds(pmsz_round* out, int64_t cap, int64_t* n) {
+  if (!n || (cap > 0 && !out)) return fail(PMSZ_ERR_INVALID_ARG, "NULL argument");
+  const int64_t m = t_timing.nrounds < cap ? t_timing.nrounds : (cap > 0 ? cap : 0);
+  for (int64_t r = 0; r < m; ++r) out[r] = t_timing.rounds[r];
+  *n = t_timing.nrounds;
   return PMSZ_OK;
 }
 
@@ -568,6 +587,8 @@ int pmsz_session_add(pmsz_session* S, const pmsz_field* field, int64_t max_iters
   e.d.st = (FieldState*)(fb + L.state);
   e.d.act = (uint8_t*)(fb + L.act);
   e.d.bm = (uint32_t*)(fb + L.bm);
+  e.d.list = (uint32_t*)(fb + L.list);
+  e.d.list_cap = list_capacity(e.d.geo);
   e.d.dirs = (uint8_t*)(fb + L.dirs);
   HIP_TRY(engine_zero(fb, L.dirs, S->stream));
   memset(&e.st, 0, sizeof(e.st));

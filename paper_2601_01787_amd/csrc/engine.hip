@@ -28,12 +28,16 @@ namespace pmsz {
 
 // ---------------------------------------------------------------------------
 // Grid barrier for a cooperative launch.  Each block's thread 0 releases its
-// writes (one L2 write-back at agent scope), arrives on a device-scope
-// counter, polls the generation word with relaxed loads (which read the
-// coherent copy without touching the caches), and acquires once at the end
-// (one cache invalidate), so that the next phase sees every block's writes.
-// The spin is bounded: after ~4 s the block records an error and the launch
-// winds down instead of hanging.
+// writes (one L2 write-back at agent scope) and arrives on one of kBarGroups
+// group counters; the last arrival of a group resets it and arrives on the
+// top counter, and the last arrival there resets that and publishes the next
+// generation with a release store.  The other blocks poll the generation
+// word, which no arrival touches, with relaxed loads (they read the coherent
+// copy without touching the caches) and acquire once at the end (one cache
+// invalidate), so the next phase sees every block's writes.  Spreading the
+// arrivals keeps them from serialising on one address.  The spin is bounded:
+// after ~4 s the block records an error and the launch winds down instead of
+// hanging.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ unsigned relaxed_load(const unsigned* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -47,14 +51,28 @@ __device__ __forceinline__ void grid_sync(EngineCtl* ctl, unsigned nblocks, unsi
   if (threadIdx.x == 0) {
     const unsigned target = gen + 1;
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    const unsigned groups = nblocks < (unsigned)kBarGroups ? nblocks : (unsigned)kBarGroups;
+    const unsigned grp = blockIdx.x % groups;
+    const unsigned members = nblocks / groups + (grp < nblocks % groups ? 1u : 0u);
+    bool last = false;
     const unsigned arrived =
-        __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (arrived == nblocks - 1) {
-      __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&ctl->bar_gen, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    } else {
+        __hip_atomic_fetch_add(&ctl->bar[grp].v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == members - 1) {
+      __hip_atomic_store(&ctl->bar[grp].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      // acq_rel: the reset is ordered before this group's arrival, and the
+      // final arrival orders every group's reset before its release below
+      const unsigned top = __hip_atomic_fetch_add(&ctl->bar[kBarGroups].v, 1u, __ATOMIC_ACQ_REL,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+      if (top == groups - 1) {
+        __hip_atomic_store(&ctl->bar[kBarGroups].v, 0u, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ctl->bar_gen.v, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        last = true;
+      }
+    }
+    if (!last) {
       const unsigned long long t0 = wall_clock64();
-      while (relaxed_load(&ctl->bar_gen) != target) {
+      while (relaxed_load(&ctl->bar_gen.v) != target) {
         __builtin_amdgcn_s_sleep(1);
         if (wall_clock64() - t0 > 400000000ull) {  // 100 MHz counter: 4 s
           __hip_atomic_store(&ctl->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -197,6 +215,133 @@ __device__ __forceinline__ int block_scan(int v, int* sh, int* total) {
   return before + x - v;
 }
 
+// ---------------------------------------------------------------------------
+// Sparse rounds.  A vertex whose mismatch set is non-empty in round E+1 is a
+// Freudenthal neighbour of some vertex flagged in round E: either one of its
+// neighbours was edited, or nothing around it changed and it flags the same
+// target as before, which lies in its own neighbourhood.  So when round E
+// flagged few vertices, examining the neighbours of exactly those (the apply
+// pass lists them) gives the same flag set as any sweep that covers them.
+// Duplicated examinations only repeat idempotent flag writes; the mismatch
+// count is then an over-count, which is only ever tested against zero after
+// a field's first round.
+// ---------------------------------------------------------------------------
+
+// Examinations needed by round E of a field in a sparse round, or -1 when the
+// round sweeps its active tiles (first round, or too many targets listed).
+__device__ __forceinline__ long long sparse_items(const FieldDesc& d, const FieldIter& s,
+                                                  unsigned long long E) {
+  if (!s.started || s.done) return -1;
+  const unsigned long long n = relaxed_load(&d.st->c[(E + 2) % 3].nlist);
+  if (n > (unsigned long long)d.list_cap) return -1;
+  return (long long)n * (d.geo.ndim == 3 ? 15 : 7);
+}
+
+// Signed vertex offset of a direction code.
+__device__ __forceinline__ int32_t code_offset(const TileGeo& G, int code) {
+  const int m = code & 7;
+  const int32_t o = (m & 1) + ((m >> 1) & 1) * G.nx + ((m >> 2) & 1) * G.sxy;
+  return (code & 8) ? -o : o;
+}
+
+// Directions of g at vertex v from gathered values: the same upper / lower
+// box pair merges, in the same order, as the tile marches.
+template <class T>
+__device__ __forceinline__ void gather_dirs(const TileGeo& G, gptr<const T> g, int32_t v, int& ca,
+                                            int& cd) {
+  const T nan = T(__builtin_nan(""));
+  const int32_t x = v % G.nx;
+  const bool xm = x > 0, xp = x + 1 < G.nx;
+  if (G.ndim == 3) {
+    const int32_t yz = v / G.nx, y = yz % G.ny, z = yz / G.ny;
+    const bool ym = y > 0, yp = y + 1 < G.ny, zm = z > 0, zp = z + 1 < G.nz;
+    auto up = [&](int bx, int by, int bz) {
+      const bool ok = (!bx || xp) && (!by || yp) && (!bz || zp);
+      const T val = ok ? g[v + bx + by * G.nx + bz * G.sxy] : nan;
+      return ext_of(val, bx | (by << 1) | (bz << 2));
+    };
+    auto dn = [&](int bx, int by, int bz) {  // vertex v - (1-bx, 1-by, 1-bz)
+      const int mx = 1 - bx, my = 1 - by, mz = 1 - bz, m = mx | (my << 1) | (mz << 2);
+      const bool ok = (!mx || xm) && (!my || ym) && (!mz || zm);
+      const T val = ok ? g[v - mx - my * G.nx - mz * G.sxy] : nan;
+      return ext_of(val, m ? (8 | m) : 0);
+    };
+    const Ext<T> U = merge_up(merge_up(merge_up(up(0, 0, 0), up(1, 0, 0)),
+                                       merge_up(up(0, 1, 0), up(1, 1, 0))),
+                              merge_up(merge_up(up(0, 0, 1), up(1, 0, 1)),
+                                       merge_up(up(0, 1, 1), up(1, 1, 1))));
+    const Ext<T> L = merge_dn(merge_dn(merge_dn(dn(0, 0, 0), dn(1, 0, 0)),
+                                       merge_dn(dn(0, 1, 0), dn(1, 1, 0))),
+                              merge_dn(merge_dn(dn(0, 0, 1), dn(1, 0, 1)),
+                                       merge_dn(dn(0, 1, 1), dn(1, 1, 1))));
+    const Ext<T> e = merge_up(L, U);
+    ca = e.ca;
+    cd = e.cd;
+  } else {
+    const int32_t y = v / G.nx;
+    const bool ym = y > 0, yp = y + 1 < G.ny;
+    auto up = [&](int bx, int by) {
+      const bool ok = (!bx || xp) && (!by || yp);
+      return ext_of(ok ? g[v + bx + by * G.nx] : nan, bx | (by << 1));
+    };
+    auto dn = [&](int bx, int by) {
+      const int mx = 1 - bx, my = 1 - by, m = mx | (my << 1);
+      const bool ok = (!mx || xm) && (!my || ym);
+      return ext_of(ok ? g[v - mx - my * G.nx] : nan, m ? (8 | m) : 0);
+    };
+    const Ext<T> U = merge_up(merge_up(up(0, 0), up(1, 0)), merge_up(up(0, 1), up(1, 1)));
+    const Ext<T> L = merge_dn(merge_dn(dn(0, 0), dn(1, 0)), merge_dn(dn(0, 1), dn(1, 1)));
+    const Ext<T> e = merge_up(L, U);
+    ca = e.ca;
+    cd = e.cd;
+  }
+}
+
+// Examination m of a sparse round: neighbour m % per of listed target m / per.
+// Returns the number of mismatches found (0, 1 or 2).
+template <class T>
+__device__ __forceinline__ unsigned sparse_examine(const FieldDesc& d, uint32_t m) {
+  const TileGeo& G = d.geo;
+  const bool three = G.ndim == 3;
+  const uint32_t per = three ? 15u : 7u;
+  const uint32_t k = m / per, j = m - k * per;
+  const int32_t t = (int32_t)d.list[k];
+  // the vertex itself, then its neighbours: 3D codes 1..7, 9..15; 2D 1..3, 9..11
+  const int code = three ? (j < 8 ? (int)j : (int)j + 1) : (j < 4 ? (int)j : (int)j + 5);
+  // is the neighbour inside the box?
+  const int mm = code & 7;
+  const int sg = (code & 8) ? -1 : 1;
+  const int32_t x = t % G.nx;
+  const int32_t y = three ? (t / G.nx) % G.ny : t / G.nx;
+  const int32_t z = three ? t / G.sxy : 0;
+  const int32_t X = x + sg * (mm & 1), Y = y + sg * ((mm >> 1) & 1), Z = z + sg * ((mm >> 2) & 1);
+  if (X < 0 || X >= G.nx || Y < 0 || Y >= G.ny || Z < 0 || Z >= G.nz) return 0;
+  const int32_t v = t + code_offset(G, code);
+  int ca, cd;
+  gather_dirs<T>(G, as_global((const T*)d.g), v, ca, cd);
+  const int d8 = as_global(d.dirs)[v];
+  const int fa = d8 & 15, fd = d8 >> 4;
+  const gptr<uint32_t> bm = as_global(d.bm);
+  unsigned n = 0;
+  // targets are neighbours of v, inside the box for directions made by the
+  // direction pass; the range check only guards the bitmap
+  if (ca != fa) {
+    const int32_t tt = v + code_offset(G, ca);
+    if ((uint32_t)tt < (uint32_t)G.n)
+      __hip_atomic_fetch_or(bm + (tt >> 5), 1u << (tt & 31), __ATOMIC_RELAXED,
+                            __HIP_MEMORY_SCOPE_AGENT);
+    ++n;
+  }
+  if (cd != fd) {
+    const int32_t tt = v + code_offset(G, fd);
+    if ((uint32_t)tt < (uint32_t)G.n)
+      __hip_atomic_fetch_or(bm + (tt >> 5), 1u << (tt & 31), __ATOMIC_RELAXED,
+                            __HIP_MEMORY_SCOPE_AGENT);
+    ++n;
+  }
+  return n;
+}
+
 constexpr int kApplyCap = 2048;   // targets per compaction pass
 
 // Apply pass over bitmap words [w0, w1) of one field: the block reads the
@@ -205,7 +350,8 @@ constexpr int kApplyCap = 2048;   // targets per compaction pass
 template <class T>
 __device__ __forceinline__ void apply_segment(const FieldDesc& d, int32_t w0, int32_t w1,
                                               bool edit, uint8_t* nxt, uint32_t* list,
-                                              int* scan, unsigned long long& nflag,
+                                              int* scan, long long* lbase_sh, FieldCtr* cq,
+                                              unsigned long long& nflag,
                                               unsigned long long& at_lb,
                                               unsigned long long& edits) {
   constexpr int kPer = 16;
@@ -246,8 +392,14 @@ __device__ __forceinline__ void apply_segment(const FieldDesc& d, int32_t w0, in
         }
       }
     }
-    lds_barrier();
     const int n = total - base < kApplyCap ? total - base : kApplyCap;
+    // room in the field's target list for this pass (next round's sparse
+    // examination); entries past the capacity are dropped, and the count
+    // then sends the next round to a tile sweep
+    if (edit && tid == 0)
+      *lbase_sh = (long long)atomicAdd(&cq->nlist, (unsigned long long)n);
+    lds_barrier();
+    const long long lbase = edit ? *lbase_sh : 0;
     for (int j = tid; j < n; j += 256) {
       const int32_t t = (int32_t)list[j];
       const T gt = g[t];
@@ -256,7 +408,10 @@ __device__ __forceinline__ void apply_segment(const FieldDesc& d, int32_t w0, in
       if (above && edit) g[t] = halving_edit<T>(gt, lb);
       edits += (above && edit) ? 1u : 0u;
       at_lb += above ? 0u : 1u;
-      if (edit) mark_box(d, box_of(d.geo, t), nxt);
+      if (edit) {
+        mark_box(d, box_of(d.geo, t), nxt);
+        if (lbase + j < d.list_cap) d.list[lbase + j] = (uint32_t)t;
+      }
     }
     lds_barrier();
   }
@@ -266,7 +421,9 @@ template <class T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 3))) void k_engine(EngineArgs a) {
   __shared__ TileLds<T> sm;
   __shared__ unsigned long long red[4];
-  __shared__ int sh_f, sh_kind;
+  __shared__ uint16_t s_tiles[256];
+  __shared__ long long s_pre[256];
+  __shared__ long long s_lbase;
   __shared__ uint32_t s_list[kApplyCap];
   __shared__ int s_scan[4];
   const unsigned G = gridDim.x;
@@ -274,11 +431,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
   for (int k = tid; k < kFlagWords; k += 256) sm.flags[k] = 0u;
   __syncthreads();
   EngineCtl* ctl = a.ctl;
-  unsigned gen = relaxed_load(&ctl->bar_gen);
+  unsigned gen = relaxed_load(&ctl->bar_gen.v);
   const unsigned long long E0 = ctl->epoch;
   unsigned long long E = E0;
   const bool tracer = a.trace && blockIdx.x == 0 && tid == 0;
-  if (tracer) a.trace[kTraceRounds * 3] = wall_clock64();
+  if (tracer) a.trace[kTraceRounds * kTraceSlots] = wall_clock64();
 
   // Fields that have not started: every tile is active in their first round.
   if (a.has_fresh) {
@@ -295,7 +452,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     if (engine_failed(ctl)) break;
     const int p = (int)(E & 1);
     const int q = (int)(E % 3), qn = (int)((E + 1) % 3);
-    if (tracer && r < kTraceRounds) a.trace[3 * r] = wall_clock64();
+    if (tracer && r < kTraceRounds) a.trace[kTraceSlots * r] = wall_clock64();
 
     // ---- block 0: persist the state of round E, clear next-but-one counters
     if (blockIdx.x == 0) {
@@ -304,87 +461,140 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
         if (E > E0) d.st->s[p] = state_at(d, E, E0);
         d.st->c[qn] = FieldCtr{0, 0, 0, 0, 0, 0};
       }
-      if (tid == 0) ctl->edits[qn] = 0;
+      if (tid == 0) {
+        ctl->edits[qn] = 0;
+        ctl->swept[qn] = 0;
+        ctl->flagged[qn] = 0;
+      }
     }
 
     // ---- detect ------------------------------------------------------------
     unsigned long long acc_m = 0, acc_nf = 0, acc_nb = 0, acc_sw = 0;
     int cur = -1, cached = -1, cached_kind = -1;
-    for (int64_t tt = blockIdx.x; tt < a.total_tiles; tt += G) {
-      if (tid == 0) {
-        int fi = field_of_tile(a.fd, a.nf, tt), kind = 0;
-        const FieldDesc& d = a.fd[fi];
-        uint8_t* flag = d.act + p * tile_count(d.geo) + (tt - d.tile_base);
+    // The block's tiles are base + j*G; their activity bytes are read and
+    // cleared 256 at a time, one per thread, and the active ones listed.
+    for (int64_t base = blockIdx.x; base < a.total_tiles; base += (int64_t)G * 256) {
+      const int64_t mine = base + (int64_t)tid * G;
+      int take = 0;
+      if (mine < a.total_tiles) {
+        const FieldDesc& d = a.fd[field_of_tile(a.fd, a.nf, mine)];
+        uint8_t* flag = d.act + p * tile_count(d.geo) + (mine - d.tile_base);
         if (*flag) {
           *flag = 0;
-          if (fi != cached) {
-            const FieldIter s = state_at(d, E, E0);
-            cached = fi;
-            cached_kind = s.done ? -1
-                        : s.started ? KIND_NEXT
-                        : (a.fd[fi].dirs_given ? KIND_FIRST_GIVEN : KIND_FIRST);
+          take = 1;
+        }
+      }
+      int n_act = 0;
+      const int pos = block_scan(take, s_scan, &n_act);
+      if (take) s_tiles[pos] = (uint16_t)tid;
+      __syncthreads();
+      for (int j = 0; j < n_act; ++j) {
+        const int64_t tt = base + (int64_t)s_tiles[j] * G;
+        const int fi = field_of_tile(a.fd, a.nf, tt);
+        if (fi != cached) {
+          const FieldIter s = state_at(a.fd[fi], E, E0);
+          cached = fi;
+          cached_kind = (s.done || sparse_items(a.fd[fi], s, E) >= 0) ? -1
+                      : s.started ? KIND_NEXT
+                      : (a.fd[fi].dirs_given ? KIND_FIRST_GIVEN : KIND_FIRST);
+        }
+        const int kind = cached_kind;
+        if (kind < 0) continue;
+        const FieldDesc& d = a.fd[fi];
+        if (tid == 0 && fi != cur) {
+          if (cur >= 0) {
+            FieldCtr* c = &a.fd[cur].st->c[q];
+            if (acc_m) atomicAdd(&c->mism, acc_m);
+            if (acc_nf) atomicAdd(&c->bad_nf, acc_nf);
+            if (acc_nb) atomicAdd(&c->bad_b, acc_nb);
+            if (acc_sw) {
+              atomicAdd(&c->swept, acc_sw);
+              atomicAdd(&ctl->swept[q], acc_sw);
+            }
           }
-          kind = cached_kind;
-          if (kind < 0) fi = -1;
+          acc_m = acc_nf = acc_nb = acc_sw = 0;
+          cur = fi;
+        }
+        const int64_t tile = tt - d.tile_base;
+        const T* g = (const T*)d.g;
+        const T* f = (const T*)d.f;
+        const T xi = (T)d.xi_t;
+        TileCounts tc;
+        if (d.geo.ndim == 3) {
+          if (kind == KIND_NEXT)
+            tc = tile3<T, KIND_NEXT>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile);
+          else if (kind == KIND_FIRST_GIVEN)
+            tc = tile3<T, KIND_FIRST_GIVEN>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile);
+          else
+            tc = tile3<T, KIND_FIRST>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile);
         } else {
-          fi = -1;
+          if (kind == KIND_NEXT)
+            tc = tile2<T, KIND_NEXT>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile);
+          else if (kind == KIND_FIRST_GIVEN)
+            tc = tile2<T, KIND_FIRST_GIVEN>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile);
+          else
+            tc = tile2<T, KIND_FIRST>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile);
         }
-        sh_f = fi;
-        sh_kind = kind;
-      }
-      lds_barrier();
-      const int fi = sh_f, kind = sh_kind;
-      lds_barrier();
-      if (fi < 0) continue;
-      const FieldDesc& d = a.fd[fi];
-      if (tid == 0 && fi != cur) {
-        if (cur >= 0) {
-          FieldCtr* c = &a.fd[cur].st->c[q];
-          if (acc_m) atomicAdd(&c->mism, acc_m);
-          if (acc_nf) atomicAdd(&c->bad_nf, acc_nf);
-          if (acc_nb) atomicAdd(&c->bad_b, acc_nb);
-          if (acc_sw) atomicAdd(&c->swept, acc_sw);
+        if (tid == 0) {
+          acc_m += unpack3(tc, 0);
+          acc_nf += unpack3(tc, 1);
+          acc_nb += unpack3(tc, 2);
+          acc_sw += (unsigned long long)tile_voxels(d.geo, tile);
         }
-        acc_m = acc_nf = acc_nb = acc_sw = 0;
-        cur = fi;
       }
-      const int64_t tile = tt - d.tile_base;
-      const T* g = (const T*)d.g;
-      const T* f = (const T*)d.f;
-      const T xi = (T)d.xi_t;
-      TileCounts tc;
-      if (d.geo.ndim == 3) {
-        if (kind == KIND_NEXT)
-          tc = tile3<T, KIND_NEXT>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile);
-        else if (kind == KIND_FIRST_GIVEN)
-          tc = tile3<T, KIND_FIRST_GIVEN>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile);
-        else
-          tc = tile3<T, KIND_FIRST>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile);
-      } else {
-        if (kind == KIND_NEXT)
-          tc = tile2<T, KIND_NEXT>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile);
-        else if (kind == KIND_FIRST_GIVEN)
-          tc = tile2<T, KIND_FIRST_GIVEN>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile);
-        else
-          tc = tile2<T, KIND_FIRST>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile);
-      }
-      if (tid == 0) {
-        acc_m += unpack3(tc, 0);
-        acc_nf += unpack3(tc, 1);
-        acc_nb += unpack3(tc, 2);
-        acc_sw += (unsigned long long)tile_voxels(d.geo, tile);
-      }
+      __syncthreads();  // s_tiles is rewritten by the next batch
     }
     if (tid == 0 && cur >= 0) {
       FieldCtr* c = &a.fd[cur].st->c[q];
       if (acc_m) atomicAdd(&c->mism, acc_m);
       if (acc_nf) atomicAdd(&c->bad_nf, acc_nf);
       if (acc_nb) atomicAdd(&c->bad_b, acc_nb);
-      if (acc_sw) atomicAdd(&c->swept, acc_sw);
+      if (acc_sw) {
+        atomicAdd(&c->swept, acc_sw);
+        atomicAdd(&ctl->swept[q], acc_sw);
+      }
+    }
+    // Sparse rounds: the examinations of up to 256 fields at a time form one
+    // index space (prefix sums in LDS) that the grid strides over.
+    for (int f0 = 0; f0 < a.nf; f0 += 256) {
+      const int fi = f0 + tid;
+      long long items = 0;
+      if (fi < a.nf) {
+        const FieldDesc& d = a.fd[fi];
+        items = sparse_items(d, state_at(d, E, E0), E);
+        if (items < 0) items = 0;
+        if (items > 0 && blockIdx.x == 0) {
+          FieldCtr* c = &d.st->c[q];
+          atomicAdd(&c->swept, (unsigned long long)items);
+          atomicAdd(&ctl->swept[q], (unsigned long long)items);
+        }
+      }
+      s_pre[tid] = items;
+      __syncthreads();
+      for (int o = 1; o < 256; o <<= 1) {  // inclusive prefix sum
+        const long long v = tid >= o ? s_pre[tid - o] : 0;
+        __syncthreads();
+        s_pre[tid] += v;
+        __syncthreads();
+      }
+      const long long total = s_pre[255];
+      const int nfc = a.nf - f0 < 256 ? a.nf - f0 : 256;
+      for (long long m = (long long)blockIdx.x * 256 + tid; m < total; m += (long long)G * 256) {
+        int lo = 0, hi = nfc - 1;  // first field whose inclusive sum exceeds m
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (s_pre[mid] > m) hi = mid; else lo = mid + 1;
+        }
+        const long long start = lo ? s_pre[lo - 1] : 0;
+        const FieldDesc& d = a.fd[f0 + lo];
+        const unsigned n = sparse_examine<T>(d, (uint32_t)(m - start));
+        if (n) atomicAdd(&d.st->c[q].mism, (unsigned long long)n);
+      }
+      __syncthreads();  // s_pre is rewritten by the next group
     }
     grid_sync(ctl, G, gen);
     if (engine_failed(ctl)) break;
-    if (tracer && r < kTraceRounds) a.trace[3 * r + 1] = wall_clock64();
+    if (tracer && r < kTraceRounds) a.trace[kTraceSlots * r + 1] = wall_clock64();
 
     // ---- apply -------------------------------------------------------------
     for (int64_t sg = blockIdx.x; sg < a.total_segs; sg += G) {
@@ -400,7 +610,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
       const int32_t w0 = (int32_t)((sg - d.seg_base) * kSegWords);
       const int32_t w1 = (w0 + kSegWords < d.words) ? w0 + (int32_t)kSegWords : (int32_t)d.words;
       unsigned long long nflag = 0, at_lb = 0, edits = 0;
-      apply_segment<T>(d, w0, w1, edit, nxt, s_list, s_scan, nflag, at_lb, edits);
+      apply_segment<T>(d, w0, w1, edit, nxt, s_list, s_scan, &s_lbase, cq, nflag, at_lb, edits);
       // a segment holds at most 128K vertices: the three counts pack into
       // 21-bit fields of one word for a single block reduction
       const unsigned long long tot =
@@ -408,14 +618,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
       if (tid == 0) {
         const unsigned long long nf_ = unpack3(tot, 0), al_ = unpack3(tot, 1),
                                  ed_ = unpack3(tot, 2);
-        if (nf_) atomicAdd(&cq->nflag, nf_);
+        if (nf_) {
+          atomicAdd(&cq->nflag, nf_);
+          atomicAdd(&ctl->flagged[q], nf_);
+        }
         if (al_) atomicAdd(&cq->at_lb, al_);
         if (ed_) atomicAdd(&ctl->edits[q], ed_);
       }
     }
     grid_sync(ctl, G, gen);
     if (engine_failed(ctl)) break;
-    if (tracer && r < kTraceRounds) a.trace[3 * r + 2] = wall_clock64();
+    if (tracer && r < kTraceRounds) {
+      unsigned long long* t = a.trace + kTraceSlots * r;
+      t[2] = wall_clock64();
+      t[3] = relaxed_load(&ctl->swept[q]);
+      t[4] = relaxed_load(&ctl->flagged[q]);
+      t[5] = relaxed_load(&ctl->edits[q]);
+    }
     const unsigned long long edited = relaxed_load(&ctl->edits[q]);
     ++E;
     if (edited == 0) break;

@@ -25,6 +25,7 @@ struct FieldIter {
 // to c[E%3], reads c[(E-1)%3], and clears c[(E+1)%3].
 struct FieldCtr {
   unsigned long long mism, nflag, at_lb, bad_nf, bad_b, swept;
+  unsigned long long nlist;  // targets appended to the field's target list
 };
 
 struct FieldState {
@@ -41,6 +42,7 @@ struct FieldDesc {
   FieldState* st;     // iteration state and counters of this field
   uint8_t* act;       // per tile and round parity: examine in that round
                       // (act[p * tiles + tile])
+  uint32_t* list;     // targets of the last apply pass (list_cap entries)
   TileGeo geo;
   double xi_t;        // xi in the field type, <= xi
   int64_t max_iters;
@@ -48,15 +50,26 @@ struct FieldDesc {
   int64_t seg_base;   // first global apply segment
   int64_t words;      // bitmap words
   int32_t dirs_given; // caller supplied the directions of f
-  int32_t pad;
+  int32_t list_cap;   // capacity of the target list
+};
+
+// Grid barrier words, each on its own 256-byte line: arrivals are spread over
+// kBarGroups group counters whose last arrivals meet at a top counter, and
+// the waiting blocks poll a generation word that no arrival touches.
+constexpr int kBarGroups = 32;
+struct alignas(256) BarWord {
+  unsigned v;
+  unsigned pad[63];
 };
 
 struct EngineCtl {
-  unsigned bar_count;
-  unsigned bar_gen;
+  BarWord bar_gen;
+  BarWord bar[kBarGroups + 1];  // group counters, then the top counter
   unsigned long long epoch;     // rounds run since the workspace was initialised
   unsigned long long rounds;    // rounds run by the last launch
   unsigned long long edits[3];  // value changes per round (mod 3), all fields
+  unsigned long long swept[3];  // vertices examined per round (mod 3), all fields
+  unsigned long long flagged[3];  // flagged vertices per round (mod 3), all fields
   int error;                    // a grid barrier timed out
   int pad;
 };
@@ -70,14 +83,17 @@ struct EngineArgs {
   int64_t total_tiles;
   int64_t total_segs;
   int64_t max_rounds;    // < 0: until every field is done
-  unsigned long long* trace;  // nullable: per-round timestamps (kTraceRounds x 3)
+  unsigned long long* trace;  // nullable: per-round record (kTraceRounds x kTraceSlots)
 };
 
-// Round trace: block 0 stamps the 100 MHz wall clock at the start of a round,
-// after its detect barrier and after its apply barrier, for the first
-// kTraceRounds rounds of a launch; slot kTraceRounds*3 holds the launch start.
+// Round trace, for the first kTraceRounds rounds of a launch: block 0 stamps
+// the 100 MHz wall clock at the start of a round, after its detect barrier
+// and after its apply barrier, then copies the round's totals (vertices
+// examined, flagged vertices, edits); slot kTraceRounds*kTraceSlots holds the
+// launch start.
 constexpr int kTraceRounds = 64;
-constexpr size_t kTraceBytes = (kTraceRounds * 3 + 1) * 8;
+constexpr int kTraceSlots = 6;
+constexpr size_t kTraceBytes = (kTraceRounds * kTraceSlots + 1) * 8;
 
 // Host side (engine.hip).
 hipError_t engine_launch(int dtype, const EngineArgs& a, hipStream_t s, int* grid_out);
@@ -85,9 +101,15 @@ hipError_t engine_launch(int dtype, const EngineArgs& a, hipStream_t s, int* gri
 // the call can sit inside a captured graph.
 hipError_t engine_zero(void* p, size_t bytes, hipStream_t s);
 
-// Per-field workspace: [FieldState][activity bytes x 2][bitmap][directions].
+// Target list: when a round flags at most this many vertices, the next
+// round examines the Freudenthal neighbours of exactly those vertices
+// instead of sweeping tiles.
+inline int32_t list_capacity(const TileGeo& G) { return G.n / 256 + 1024; }
+
+// Per-field workspace: [FieldState][activity bytes x 2][bitmap][target list]
+// [directions].
 struct FieldLayout {
-  size_t state, act, bm, dirs, total;
+  size_t state, act, bm, list, dirs, total;
 };
 inline size_t ws_align(size_t v) { return (v + 255) / 256 * 256; }
 inline FieldLayout field_layout(const TileGeo& G, bool dirs_given) {
@@ -95,7 +117,8 @@ inline FieldLayout field_layout(const TileGeo& G, bool dirs_given) {
   L.state = 0;
   L.act = ws_align(sizeof(FieldState));
   L.bm = L.act + ws_align(2 * (size_t)tile_count(G));
-  L.dirs = L.bm + ws_align(((size_t)G.n + 31) / 32 * 4);
+  L.list = L.bm + ws_align(((size_t)G.n + 31) / 32 * 4);
+  L.dirs = L.list + ws_align((size_t)list_capacity(G) * 4);
   L.total = L.dirs + (dirs_given ? 0 : ws_align((size_t)G.n));
   return L;
 }

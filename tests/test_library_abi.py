@@ -41,8 +41,10 @@ def test_host_only_calls():
     g = pmsz.Grid(3, pmsz.F32, 512, 512, 512)
     n = pmsz.workspace_size(g, pmsz.WS_CORRECT)
     N = 512 ** 3
-    # bitmap (N/8) + direction bytes (N) + three 4-byte words per tile of >= 2048 vertices
-    assert N + N // 8 <= n <= N + N // 8 + 12 * (N // 2048) + 8192
+    # bitmap (N/8) + direction bytes (N) + target list (4 bytes for N/256 + 1024
+    # entries) + a few bytes per tile of >= 2048 vertices + fixed control blocks
+    lst = 4 * (N // 256 + 1024)
+    assert N + N // 8 + lst <= n <= N + N // 8 + lst + 12 * (N // 2048) + 65536
     with pytest.raises(pmsz.PmszError) as e:
         pmsz.workspace_size(pmsz.Grid(2, pmsz.F32, 4, 4, 3), pmsz.WS_CORRECT)
     assert e.value.status == 1
