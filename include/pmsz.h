@@ -222,9 +222,11 @@ typedef struct {
   int64_t tiles;     /* tiles of the batch                                    */
   int32_t grid;      /* blocks of the cooperative launch                      */
   int32_t reserved;
-  double first_round_ms; /* first round: directions of f, validation, detect, apply */
+  double first_round_ms; /* first round: validation, detect, apply            */
   double detect_ms;  /* detect phases of the later rounds (block 0's clock)    */
   double apply_ms;   /* apply phases of the later rounds                       */
+  double dirs_ms;    /* directions of f, computed before the correction kernel
+                        (0 when the caller gave them)                           */
 } pmsz_timing;
 int pmsz_last_timing(pmsz_timing* out);
 

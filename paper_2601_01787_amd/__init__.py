@@ -73,7 +73,7 @@ class Timing(ctypes.Structure):
                 ("swept", ctypes.c_int64), ("edits", ctypes.c_int64), ("voxels", ctypes.c_int64),
                 ("tiles", ctypes.c_int64), ("grid", ctypes.c_int32), ("reserved", ctypes.c_int32),
                 ("first_round_ms", ctypes.c_double), ("detect_ms", ctypes.c_double),
-                ("apply_ms", ctypes.c_double)]
+                ("apply_ms", ctypes.c_double), ("dirs_ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}

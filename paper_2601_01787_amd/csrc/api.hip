@@ -172,7 +172,7 @@ int staging(Staging& s, size_t bytes, void** out) {
 
 // Events around the engine launch and the figures of the last run.
 struct Timing {
-  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // engine start, engine end, dirs start
   pmsz_timing last;
   pmsz_round rounds[kTraceRounds];
   int64_t nrounds = 0;
@@ -237,6 +237,10 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
   if (!tm.ev[0])
     for (auto& e : tm.ev) HIP_TRY(hipEventCreate(&e));
   int grid = 0;
+  bool need_dirs = false;
+  for (int32_t i = 0; i < n; ++i) need_dirs |= !P.fd[i].dirs_given;
+  HIP_TRY(hipEventRecord(tm.ev[2], s));
+  if (need_dirs) HIP_TRY(engine_dirs(dtype, a.fd, n, P.total_tiles, s));
   HIP_TRY(hipEventRecord(tm.ev[0], s));
   HIP_TRY(engine_launch(dtype, a, s, &grid));
   HIP_TRY(hipEventRecord(tm.ev[1], s));
@@ -253,10 +257,12 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
   const FieldIter* hs =
       (const FieldIter*)((char*)stage + sizeof(EngineCtl) + kTraceBytes);
   if (hc->error) return fail(PMSZ_ERR_DEVICE, "grid barrier timed out in the correction engine");
-  float ms = 0.f;
+  float ms = 0.f, dms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, tm.ev[0], tm.ev[1]));
+  HIP_TRY(hipEventElapsedTime(&dms, tm.ev[2], tm.ev[0]));
   memset(&tm.last, 0, sizeof(tm.last));
   tm.last.engine_ms = ms;
+  tm.last.dirs_ms = dms;
   tm.last.rounds = (int64_t)hc->rounds;
   tm.last.tiles = P.total_tiles;
   tm.last.grid = grid;
@@ -591,6 +597,10 @@ int pmsz_session_add(pmsz_session* S, const pmsz_field* field, int64_t max_iters
   e.d.list_cap = list_capacity(e.d.geo);
   e.d.dirs = (uint8_t*)(fb + L.dirs);
   HIP_TRY(engine_zero(fb, L.dirs, S->stream));
+  // directions of f now, at the stencil's own occupancy; the engine then
+  // starts the field from them
+  HIP_TRY(launch_dirs(field->grid.dtype, field->f, make_geo(field->grid), e.d.dirs, S->stream));
+  e.d.dirs_given = 1;
   memset(&e.st, 0, sizeof(e.st));
   const int32_t h = S->next_handle++;
   S->fields[h] = e;

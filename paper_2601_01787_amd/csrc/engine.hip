@@ -247,13 +247,11 @@ __device__ __forceinline__ int32_t code_offset(const TileGeo& G, int code) {
 // Directions of g at vertex v from gathered values: the same upper / lower
 // box pair merges, in the same order, as the tile marches.
 template <class T>
-__device__ __forceinline__ void gather_dirs(const TileGeo& G, gptr<const T> g, int32_t v, int& ca,
-                                            int& cd) {
+__device__ __forceinline__ void gather_dirs(const TileGeo& G, gptr<const T> g, int32_t v,
+                                            int32_t x, int32_t y, int32_t z, int& ca, int& cd) {
   const T nan = T(__builtin_nan(""));
-  const int32_t x = v % G.nx;
   const bool xm = x > 0, xp = x + 1 < G.nx;
   if (G.ndim == 3) {
-    const int32_t yz = v / G.nx, y = yz % G.ny, z = yz / G.ny;
     const bool ym = y > 0, yp = y + 1 < G.ny, zm = z > 0, zp = z + 1 < G.nz;
     auto up = [&](int bx, int by, int bz) {
       const bool ok = (!bx || xp) && (!by || yp) && (!bz || zp);
@@ -278,7 +276,6 @@ __device__ __forceinline__ void gather_dirs(const TileGeo& G, gptr<const T> g, i
     ca = e.ca;
     cd = e.cd;
   } else {
-    const int32_t y = v / G.nx;
     const bool ym = y > 0, yp = y + 1 < G.ny;
     auto up = [&](int bx, int by) {
       const bool ok = (!bx || xp) && (!by || yp);
@@ -303,8 +300,8 @@ template <class T>
 __device__ __forceinline__ unsigned sparse_examine(const FieldDesc& d, uint32_t m) {
   const TileGeo& G = d.geo;
   const bool three = G.ndim == 3;
-  const uint32_t per = three ? 15u : 7u;
-  const uint32_t k = m / per, j = m - k * per;
+  const uint32_t k = three ? m / 15u : m / 7u;
+  const uint32_t j = m - k * (three ? 15u : 7u);
   const int32_t t = (int32_t)d.list[k];
   // the vertex itself, then its neighbours: 3D codes 1..7, 9..15; 2D 1..3, 9..11
   const int code = three ? (j < 8 ? (int)j : (int)j + 1) : (j < 4 ? (int)j : (int)j + 5);
@@ -318,7 +315,7 @@ __device__ __forceinline__ unsigned sparse_examine(const FieldDesc& d, uint32_t 
   if (X < 0 || X >= G.nx || Y < 0 || Y >= G.ny || Z < 0 || Z >= G.nz) return 0;
   const int32_t v = t + code_offset(G, code);
   int ca, cd;
-  gather_dirs<T>(G, as_global((const T*)d.g), v, ca, cd);
+  gather_dirs<T>(G, as_global((const T*)d.g), v, X, Y, Z, ca, cd);
   const int d8 = as_global(d.dirs)[v];
   const int fa = d8 & 15, fd = d8 >> 4;
   const gptr<uint32_t> bm = as_global(d.bm);
@@ -495,8 +492,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
           const FieldIter s = state_at(a.fd[fi], E, E0);
           cached = fi;
           cached_kind = (s.done || sparse_items(a.fd[fi], s, E) >= 0) ? -1
-                      : s.started ? KIND_NEXT
-                      : (a.fd[fi].dirs_given ? KIND_FIRST_GIVEN : KIND_FIRST);
+                      : s.started ? KIND_NEXT : KIND_FIRST_GIVEN;
         }
         const int kind = cached_kind;
         if (kind < 0) continue;
@@ -523,17 +519,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
         if (d.geo.ndim == 3) {
           if (kind == KIND_NEXT)
             tc = tile3<T, KIND_NEXT>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile);
-          else if (kind == KIND_FIRST_GIVEN)
-            tc = tile3<T, KIND_FIRST_GIVEN>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile);
           else
-            tc = tile3<T, KIND_FIRST>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile);
+            tc = tile3<T, KIND_FIRST_GIVEN>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile);
         } else {
           if (kind == KIND_NEXT)
             tc = tile2<T, KIND_NEXT>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile);
-          else if (kind == KIND_FIRST_GIVEN)
-            tc = tile2<T, KIND_FIRST_GIVEN>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile);
           else
-            tc = tile2<T, KIND_FIRST>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile);
+            tc = tile2<T, KIND_FIRST_GIVEN>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile);
         }
         if (tid == 0) {
           acc_m += unpack3(tc, 0);
@@ -579,6 +571,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
       }
       const long long total = s_pre[255];
       const int nfc = a.nf - f0 < 256 ? a.nf - f0 : 256;
+      // Mismatches are only tested against zero in these rounds: each thread
+      // keeps one count for its current field and a wave adds them with a
+      // single atomic when its lanes agree on the field, so the counter does
+      // not serialise thousands of atomics.
+      int pend_f = -1;
+      unsigned pend_n = 0;
       for (long long m = (long long)blockIdx.x * 256 + tid; m < total; m += (long long)G * 256) {
         int lo = 0, hi = nfc - 1;  // first field whose inclusive sum exceeds m
         while (lo < hi) {
@@ -586,9 +584,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
           if (s_pre[mid] > m) hi = mid; else lo = mid + 1;
         }
         const long long start = lo ? s_pre[lo - 1] : 0;
-        const FieldDesc& d = a.fd[f0 + lo];
-        const unsigned n = sparse_examine<T>(d, (uint32_t)(m - start));
-        if (n) atomicAdd(&d.st->c[q].mism, (unsigned long long)n);
+        const int fi = f0 + lo;
+        if (fi != pend_f) {
+          if (pend_n) atomicAdd(&a.fd[pend_f].st->c[q].mism, (unsigned long long)pend_n);
+          pend_f = fi;
+          pend_n = 0;
+        }
+        pend_n += sparse_examine<T>(a.fd[fi], (uint32_t)(m - start));
+      }
+      const int f_lane0 = __shfl(pend_f, 0, 64);
+      if (__all(pend_f == f_lane0 || pend_n == 0)) {
+        const unsigned w = wave_sum(pend_n);
+        if ((tid & 63) == 0 && w) atomicAdd(&a.fd[f_lane0].st->c[q].mism, (unsigned long long)w);
+      } else if (pend_n) {
+        atomicAdd(&a.fd[pend_f].st->c[q].mism, (unsigned long long)pend_n);
       }
       __syncthreads();  // s_pre is rewritten by the next group
     }
@@ -652,6 +661,37 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
       ctl->rounds = E - E0;
     }
   }
+}
+
+// Directions of f for every field of a batch whose caller gave none, before
+// the engine runs: a plain (non-cooperative) grid over the tiles of all
+// fields, at the stencil's own occupancy.
+template <class T>
+__global__ __launch_bounds__(256) void k_dirs_fields(const FieldDesc* fd, int nf,
+                                                     int64_t total_tiles) {
+  __shared__ TileLds<T> sm;
+  for (int64_t tt = blockIdx.x; tt < total_tiles; tt += gridDim.x) {
+    const FieldDesc& d = fd[field_of_tile(fd, nf, tt)];
+    if (d.dirs_given) continue;
+    const T* f = (const T*)d.f;
+    if (d.geo.ndim == 3)
+      tile3<T, KIND_DIRS>(sm, nullptr, f, f, d.dirs, nullptr, T(0), d.geo, tt - d.tile_base);
+    else
+      tile2<T, KIND_DIRS>(sm, nullptr, f, f, d.dirs, nullptr, T(0), d.geo, tt - d.tile_base);
+  }
+}
+
+hipError_t engine_dirs(int dtype, const FieldDesc* fd, int nf, int64_t total_tiles,
+                       hipStream_t s) {
+  int64_t grid = total_tiles < 65536 ? total_tiles : 65536;
+  if (grid < 1) grid = 1;
+  if (dtype == PMSZ_F32)
+    hipLaunchKernelGGL(k_dirs_fields<float>, dim3((unsigned)grid), dim3(256), 0, s, fd, nf,
+                       total_tiles);
+  else
+    hipLaunchKernelGGL(k_dirs_fields<double>, dim3((unsigned)grid), dim3(256), 0, s, fd, nf,
+                       total_tiles);
+  return hipGetLastError();
 }
 
 __global__ __launch_bounds__(256) void k_zero(uint32_t* p, int64_t words) {

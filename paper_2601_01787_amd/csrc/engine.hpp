@@ -97,6 +97,11 @@ constexpr size_t kTraceBytes = (kTraceRounds * kTraceSlots + 1) * 8;
 
 // Host side (engine.hip).
 hipError_t engine_launch(int dtype, const EngineArgs& a, hipStream_t s, int* grid_out);
+// Directions of f, before the engine, for every field of the device table fd
+// whose dirs_given is 0 (into its dirs); the engine then starts every field
+// from given directions.
+hipError_t engine_dirs(int dtype, const FieldDesc* fd, int nf, int64_t total_tiles,
+                       hipStream_t s);
 // Zero `bytes` bytes (multiple of 4, 4-byte aligned) with a kernel, so that
 // the call can sit inside a captured graph.
 hipError_t engine_zero(void* p, size_t bytes, hipStream_t s);

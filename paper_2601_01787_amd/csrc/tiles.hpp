@@ -397,8 +397,8 @@ __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_
 #pragma unroll
     for (int k = 0; k < kSets; ++k) step(p + k, Q[(k + 2) % kSets], p + k <= z1);
   }
+  lds_barrier();  // the next tile of this block reuses the LDS buffers
   if (KIND == KIND_DIRS) return 0;
-  lds_barrier();
   flush_flags(sm.flags, fbx, G, (z1 - z0 + 2) * (TY + 2), bm);
   return block_sum(pack3(mism, nf, nb), red);
 }
@@ -564,8 +564,8 @@ __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_
 #pragma unroll
     for (int k = 0; k < kSets; ++k) step(r + k, Q[(k + 2) % kSets], r + k <= y1);
   }
+  lds_barrier();  // the next tile of this block reuses the LDS buffers
   if (KIND == KIND_DIRS) return 0;
-  lds_barrier();
   flush_flags(sm.flags, fbx, G, y1 - y0 + 2, bm);
   return block_sum(pack3(mism, nf, nb), red);
 }

@@ -239,3 +239,13 @@ def small_perlin_case(device="cpu"):
 def large_perlin_case(device="cpu"):
     """512^3 float32, 6 octaves, 8 cells, eps = 1e-4 (range 1), seed 512."""
     return perlin_case(512, 6, 8, 1e-4, 512, device=device)
+
+
+def grf_case(shape=(768, 1024, 1024), rel_eps=1e-5, seed=1024, device="cpu"):
+    """(f, fhat, xi) for a binary64 Gaussian random field with power spectrum
+    k^-3, normalised to [0, 1]; xi = rel_eps * (max f - min f).  The default
+    is the 1024 x 1024 x 768 large-field workload."""
+    f = grf3d(shape, seed, device=device)
+    xi = rel_eps * (float(f.max()) - float(f.min()))
+    fhat = quantise_proxy(f, xi, seed)
+    return f, fhat, xi
