@@ -18,7 +18,8 @@
  *   cube into six tetrahedra around its (0,0,0)-(1,1,1) diagonal.  The
  *   neighbours of a vertex are the 6 (2D) or 14 (3D) offsets +-b where b is a
  *   non-zero 0/1 vector; there is no periodic wrap.  nx*ny*nz must be below
- *   2^31 (vertex ids are int32).
+ *   2^31 (vertex ids are int32); a 3D grid also needs (5*nx + 65) times the
+ *   value size below 2^32 (nx < 214M for binary32, 107M for binary64).
  * Order.  Vertex a is above vertex b iff h_a > h_b, or h_a == h_b and a > b
  *   (ties broken by index).  n_max(i) / n_min(i) are the highest / lowest
  *   vertex of {i} plus its neighbours (Sec. IV-A); i is a maximum iff

@@ -54,6 +54,11 @@ int check_grid(const pmsz_grid* g) {
   const int64_t lim = 2147483647LL;
   if (g->nx > lim || g->ny > lim || g->nz > lim || g->nx * g->ny > lim / g->nz)
     return fail(PMSZ_ERR_INVALID_ARG, "nx*ny*nz must be below 2^31");
+  // 3D tiles address six rows of a plane from one base with 32-bit offsets
+  const int64_t size = g->dtype == PMSZ_F64 ? 8 : 4;
+  if (g->ndim == 3 && (5 * g->nx + 65) * size > 4294967295LL)
+    return fail(PMSZ_ERR_INVALID_ARG, "3D grids need nx below %lld for this value type",
+                (long long)((4294967295LL / size - 65) / 5 + 1));
   return PMSZ_OK;
 }
 

@@ -1,20 +1,22 @@
 // engine.hip -- the persistent correction kernel (gfx950).
 //
 // One cooperative launch runs the correction loop of Sec. IV-A for one or many
-// fields.  Round E (p = E & 1, q = E % 3), for every field still running:
-//   detect  over the tiles marked active for round E: directions of g^k,
-//           comparison with the directions of f, targets set in the flag
-//           bitmap with fire-and-forget atomicOr (Sec. IV-A ascending and
-//           descending rules, Sec. III-B FPmax rule).  In a field's first
-//           round the same pass computes the directions of f and validates
-//           fhat.
+// fields, whose directions of f were computed beforehand (k_dirs_fields, or
+// the caller).  Round E (p = E & 1, q = E % 3), for every field still running:
+//   detect  directions of g^k, compared with the directions of f; targets are
+//           set in the flag bitmap (Sec. IV-A ascending and descending rules,
+//           Sec. III-B FPmax rule).  A field's first round sweeps all its
+//           tiles and validates fhat; later rounds sweep only the tiles
+//           within one vertex of last round's targets, or, when last round
+//           flagged few vertices, examine exactly the Freudenthal neighbours
+//           of those targets (sparse rounds).
 //   barrier
 //   apply   for fields with mismatches: count the flagged vertices (|F|) and
 //           those already at their bound; unless the field is out of rounds,
-//           give every flagged vertex above its bound one halving edit (Eq. 1)
-//           and mark the tiles within one vertex of it active for round E+1.
-//           Only those tiles can see a different neighbourhood next round, so
-//           examining them alone gives exactly the full-sweep result.
+//           give every flagged vertex above its bound one halving edit (Eq. 1),
+//           list it for a sparse next round and mark the tiles within one
+//           vertex of it active.  Either way only vertices whose mismatch can
+//           be non-empty are examined, so the result is that of a full sweep.
 //   barrier
 // The decision of Sec. IV-A's loop (converged, stalled, out of rounds,
 // continue) is a pure function of the state at the start of a round and that

@@ -129,13 +129,13 @@ inline FieldLayout field_layout(const TileGeo& G, bool dirs_given) {
 }
 
 // Tile rows per tile for the engine: enough tiles to spread a small field over
-// the chip, 16 planes / rows otherwise.
+// the chip, 32 planes / rows otherwise.
 inline int engine_chunk(int ndim, int64_t nx, int64_t ny, int64_t nz) {
   const int64_t cols = ndim == 3 ? ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY) : (nx + RX - 1) / RX;
   const int64_t depth = ndim == 3 ? nz : ny;
   int64_t c = depth * cols / 2048;
   if (c < 2) c = 2;
-  if (c > 16) c = 16;
+  if (c > 32) c = 32;
   return (int)c;
 }
 

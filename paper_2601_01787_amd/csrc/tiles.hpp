@@ -111,9 +111,8 @@ inline TileGeo make_tile_geo(int ndim, int64_t nx, int64_t ny, int64_t nz, int c
 // What a tile pass does with the directions it computes.
 enum TileKind {
   KIND_DIRS = 0,        // write the direction bytes of h
-  KIND_FIRST = 1,       // first round: directions of f (written), validation of g
-                        // against f, mismatch detection of g
-  KIND_FIRST_GIVEN = 2, // first round with the caller's directions of f
+  KIND_FIRST_GIVEN = 2, // first round: validation of g against f, mismatch
+                        // detection of g against the given directions of f
   KIND_NEXT = 3         // later rounds: mismatch detection of g
 };
 
@@ -132,12 +131,11 @@ using TileCounts = unsigned long long;  // packed, valid in thread 0
 // (chunk + 2) rows of 258 vertices (2D); a row of the flag bitmap then spans at
 // most 4 (3D) or 10 (2D) 32-bit words, counted from the word holding the
 // row's first halo vertex.
-constexpr int kMaxChunk = 16;
+constexpr int kMaxChunk = 32;
 // Planes in flight per tile march: four binary32 sets fit the register
-// budget of four waves per SIMD; binary64 values, and the first round (which
-// loads two fields per plane), take twice the registers per set.
+// budget of four waves per SIMD; binary64 values take twice the registers.
 template <class T, int KIND>
-constexpr int sets_for() { return (sizeof(T) == 4 && KIND != KIND_FIRST) ? 4 : 2; }
+constexpr int sets_for() { return sizeof(T) == 4 ? 4 : 2; }
 constexpr int kFlagW3 = 4, kFlagW2 = 10;
 constexpr int kFlagWords = (kMaxChunk + 2) * (TY + 2) * kFlagW3 > (kMaxChunk + 2) * kFlagW2
                                ? (kMaxChunk + 2) * (TY + 2) * kFlagW3
@@ -146,8 +144,8 @@ constexpr int kFlagWords = (kMaxChunk + 2) * (TY + 2) * kFlagW3 > (kMaxChunk + 2
 template <class T>
 struct TileLds {
   union {
-    T p3[2][2][PLANE];  // [field g or h, field f][buffer][haloed plane]
-    T r2[2][2][RW];
+    T p3[2][PLANE];  // [buffer][haloed plane]
+    T r2[2][RW];
   } ring;
   uint32_t flags[kFlagWords];
 };
@@ -218,17 +216,27 @@ __device__ __forceinline__ void flush_flags(uint32_t* flags, const FlagBox& fb, 
 
 // Validation of one vertex (problem statement of Sec. III-B): finite values
 // and lb <= g <= ub.  Returns 0 (valid), 1 (non-finite) or 2 (out of bound).
+// With a - xi = s1 + e1 and a + xi = s2 + e2 exactly (TwoSum), a value b lies
+// at or above the smallest value >= a - xi iff b > s1, or b == s1 and
+// e1 <= 0 (no value lies strictly between s1 and the next one up), and at or
+// below the largest value <= a + xi iff b < s2, or b == s2 and e2 >= 0; an
+// overflowed sum (infinite s) admits every finite b.
 template <class T>
 __device__ __forceinline__ int bound_class(T a, T b, T xi) {
   if (!__builtin_isfinite(a) || !__builtin_isfinite(b)) return 1;
-  return (b < lower_bound<T>(a, xi) || b > upper_bound<T>(a, xi)) ? 2 : 0;
+  T s1, e1, s2, e2;
+  two_sum<T>(a, -xi, s1, e1);
+  two_sum<T>(a, xi, s2, e2);
+  const bool lo_ok = b > s1 || (b == s1 && e1 <= T(0));
+  const bool hi_ok = b < s2 || (b == s2 && e2 >= T(0));
+  return (lo_ok && hi_ok) ? 0 : 2;
 }
 
 // One 3D tile.  h: field whose directions are evaluated (g, or f for
-// KIND_DIRS).  f: original field (its stencil in the first round, its value
-// for validation).  dirs: direction bytes of f, read (NEXT, FIRST_GIVEN) or
-// written (FIRST, DIRS).  bm: the field's flag bitmap.  Returns the packed
-// counts in thread 0.
+// KIND_DIRS).  f: original field (its values for the first round's
+// validation).  dirs: direction bytes of f, read (NEXT, FIRST_GIVEN) or
+// written (DIRS).  bm: the field's flag bitmap.  Returns the packed counts in
+// thread 0.
 //
 // The march visits planes p = z0-1 .. z1 (z1 = end of the tile).  Step p
 // stages plane p in LDS, reduces the thread's upper square (x..x+1, y..y+1)
@@ -251,7 +259,6 @@ __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_
   const gptr<uint8_t> dirs = as_global(dirs_in);
   const gptr<uint32_t> bm = as_global(bm_in);
   constexpr int PER = (PLANE + 255) / 256;
-  constexpr bool kTwo = (KIND == KIND_FIRST);          // f stencil needed
   constexpr bool kReadDirs = (KIND == KIND_NEXT || KIND == KIND_FIRST_GIVEN);
   constexpr bool kGivenF = (KIND == KIND_FIRST_GIVEN);
   constexpr int kSets = sets_for<T, KIND>();
@@ -262,7 +269,15 @@ __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_
   const int32_t x0 = bx * TX, y0 = by * TY, z0 = bz * G.chunk;
   const int32_t z1 = (z0 + G.chunk < G.nz) ? z0 + G.chunk : G.nz;
 
-  int32_t off[PER];
+  // Addressing: a uniform base per plane, at the tile's halo corner
+  // (x0-1, y0-1), plus a 32-bit per-lane byte offset fixed for the tile, so
+  // every load is a scalar-base load with no per-step address arithmetic.
+  // The corner itself may lie outside the array; lanes outside the box read
+  // the tile's first vertex instead.  Offsets stay below 6 * nx * sizeof(T),
+  // which the host keeps under 2^32.
+  const int64_t corner = (int64_t)(x0 - 1) + (int64_t)G.nx * (y0 - 1);
+  const uint32_t safe = (uint32_t)G.nx + 1u;  // (x0, y0) from the corner
+  uint32_t offb[PER];
   uint32_t xymask[PER];  // NaN bits for halo positions outside the box
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
@@ -271,39 +286,38 @@ __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_
     const int32_t X = x0 + c - 1, Y = y0 + r - 1;
     const bool in = e < PLANE && X >= 0 && X < G.nx && Y >= 0 && Y < G.ny;
     xymask[k] = in ? 0u : nan_mask<T>();
-    off[k] = in ? X + G.nx * Y : 0;
+    offb[k] = (in ? (uint32_t)r * (uint32_t)G.nx + (uint32_t)c : safe) * (uint32_t)sizeof(T);
   }
   struct Set {
-    T h[PER], f[PER];  // raw loaded values of one plane; masked to NaN at commit
+    T h[PER];          // raw loaded values of one plane; masked to NaN at commit
     uint32_t zmask;    // NaN bits when the plane lies outside the box
     int d;             // direction byte of f at this column, one plane lower
     T fv;              // value of f there (given directions)
   };
   const int32_t X = x0 + tx, Y = y0 + ty;
   const bool mine = X < G.nx && Y < G.ny;
-  const int32_t col = mine ? X + G.nx * Y : 0;
+  // this column from the corner (the tile's first vertex for idle lanes)
+  const uint32_t rel = mine ? (uint32_t)(ty + 1) * (uint32_t)G.nx + (uint32_t)(tx + 1) : safe;
   auto fetch = [&](int32_t z, Set& S) {
     const bool zin = z >= 0 && z < G.nz;
-    const int32_t zb = zin ? G.sxy * z : 0;
+    const int64_t zb = zin ? (int64_t)G.sxy * z : 0;
     S.zmask = zin ? 0u : nan_mask<T>();
+    const gptr<const char> pb = (gptr<const char>)(h + (zb + corner));
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      S.h[k] = h[off[k] + zb];
-      if (kTwo) S.f[k] = f[off[k] + zb];
-    }
+    for (int k = 0; k < PER; ++k) S.h[k] = *(gptr<const T>)(pb + offb[k]);
   };
   auto fetch_own = [&](int32_t v, Set& S) {
-    const int32_t i = col + G.sxy * (v >= 0 && v < G.nz ? v : 0);
-    if (kReadDirs) S.d = dirs[i];
-    if (kGivenF) S.fv = f[i];
+    const int64_t pl = (int64_t)G.sxy * (v >= 0 && v < G.nz ? v : 0) + corner;
+    if (kReadDirs) S.d = (dirs + pl)[rel];
+    if (kGivenF)
+      S.fv = *(gptr<const T>)((gptr<const char>)(f + pl) + rel * (uint32_t)sizeof(T));
   };
   auto commit = [&](int buf, const Set& S) {
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
       const int e = tid + k * 256;
       if (e < PLANE) {
-        sm.ring.p3[0][buf][e] = or_high(S.h[k], xymask[k] | S.zmask);
-        if (kTwo) sm.ring.p3[1][buf][e] = or_high(S.f[k], xymask[k] | S.zmask);
+        sm.ring.p3[buf][e] = or_high(S.h[k], xymask[k] | S.zmask);
       }
     }
   };
@@ -322,8 +336,8 @@ __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_
   unsigned mism = 0, nf = 0, nb = 0;
   // carried from plane p-1: its squares, the lower box of vertex p-1 and the
   // centre values (for validation)
-  Ext<T> gu{}, gl{}, gbox{}, fu{}, fl{}, fbox{};
-  T gc = T(0), fc = T(0);
+  Ext<T> gu{}, gl{}, gbox{};
+  T gc = T(0);
   auto step = [&](int32_t p, Set& S, bool out) {
     const int buf = (p - z0 + 1) & 1;
     commit(buf, S);
@@ -332,38 +346,20 @@ __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_
     fetch(p + kSets, S);
     lds_barrier();
     Ext<T> su, sd;
-    squares(sm.ring.p3[0][buf], su, sd);
+    squares(sm.ring.p3[buf], su, sd);
     const Ext<T> glo = merge_dn(with_bits(gl, 12), sd);  // lower box of vertex p
-    Ext<T> fsu, fsd, flo;
-    if (kTwo) {
-      squares(sm.ring.p3[1][buf], fsu, fsd);
-      flo = merge_dn(with_bits(fl, 12), fsd);
-    }
     if (out && mine) {
       const int32_t v = p - 1;
-      const int32_t i = col + G.sxy * v;
       const Ext<T> e = merge_up(gbox, merge_up(gu, with_bits(su, 4)));
       const int ca = e.ca, cd = e.cd;
       if (KIND == KIND_DIRS) {
-        dirs[i] = (uint8_t)(ca | (cd << 4));
+        (dirs + ((int64_t)G.sxy * v + corner))[rel] = (uint8_t)(ca | (cd << 4));
       } else {
-        int fa, fd;
-        if (KIND == KIND_FIRST) {
-          const Ext<T> ef = merge_up(fbox, merge_up(fu, with_bits(fsu, 4)));
-          fa = ef.ca;
-          fd = ef.cd;
-          dirs[i] = (uint8_t)(fa | (fd << 4));
-          const int bc = bound_class<T>(fc, gc, xi);
+        const int fa = d_cur & 15, fd = d_cur >> 4;
+        if (kGivenF) {
+          const int bc = bound_class<T>(f_cur, gc, xi);
           nf += bc == 1;
           nb += bc == 2;
-        } else {
-          fa = d_cur & 15;
-          fd = d_cur >> 4;
-          if (kGivenF) {
-            const int bc = bound_class<T>(f_cur, gc, xi);
-            nf += bc == 1;
-            nb += bc == 2;
-          }
         }
         mism += flag_targets3(X, Y, v, ca, cd, fa, fd, fbx, G, sm.flags);
       }
@@ -371,13 +367,7 @@ __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_
     gu = su;
     gl = sd;
     gbox = glo;
-    gc = sm.ring.p3[0][buf][c];
-    if (kTwo) {
-      fu = fsu;
-      fl = fsd;
-      fbox = flo;
-      fc = sm.ring.p3[1][buf][c];
-    }
+    gc = sm.ring.p3[buf][c];
     // issued after the evaluation so the old own values are dead (no
     // register copy of an in-flight load at the loop latch)
     fetch_own(p + kSets - 1, S);
@@ -415,7 +405,6 @@ __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_
   const gptr<uint8_t> dirs = as_global(dirs_in);
   const gptr<uint32_t> bm = as_global(bm_in);
   constexpr int PER = (RW + 255) / 256;
-  constexpr bool kTwo = (KIND == KIND_FIRST);
   constexpr bool kReadDirs = (KIND == KIND_NEXT || KIND == KIND_FIRST_GIVEN);
   constexpr bool kGivenF = (KIND == KIND_FIRST_GIVEN);
   constexpr int kSets = sets_for<T, KIND>();
@@ -425,7 +414,8 @@ __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_
   const int32_t x0 = bx * RX, y0 = by * G.chunk;
   const int32_t y1 = (y0 + G.chunk < G.ny) ? y0 + G.chunk : G.ny;
 
-  int32_t xs[PER];
+  // uniform base per row at the strip's halo corner x0-1, 32-bit lane offsets
+  uint32_t offb[PER];
   uint32_t xmask[PER];  // NaN bits for halo positions outside the box
 #pragma unroll
   for (int k = 0; k < PER; ++k) {
@@ -433,39 +423,38 @@ __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_
     const int32_t xx = x0 + e - 1;
     const bool in = e < RW && xx >= 0 && xx < G.nx;
     xmask[k] = in ? 0u : nan_mask<T>();
-    xs[k] = in ? xx : 0;
+    offb[k] = (in ? (uint32_t)e : 1u) * (uint32_t)sizeof(T);
   }
   struct Set {
-    T h[PER], f[PER];
+    T h[PER];
     uint32_t zmask;
     int d;
     T fv;
   };
   const int32_t X = x0 + tid;
   const bool mine = X < G.nx;
-  const int32_t xo = mine ? X : 0;
+  const uint32_t rel = mine ? (uint32_t)tid + 1u : 1u;  // from the corner x0-1
+  const int64_t corner = (int64_t)x0 - 1;
   auto fetch = [&](int32_t y, Set& S) {
     const bool yin = y >= 0 && y < G.ny;
-    const int32_t yb = yin ? G.nx * y : 0;
+    const int64_t yb = yin ? (int64_t)G.nx * y : 0;
     S.zmask = yin ? 0u : nan_mask<T>();
+    const gptr<const char> pb = (gptr<const char>)(h + (yb + corner));
 #pragma unroll
-    for (int k = 0; k < PER; ++k) {
-      S.h[k] = h[xs[k] + yb];
-      if (kTwo) S.f[k] = f[xs[k] + yb];
-    }
+    for (int k = 0; k < PER; ++k) S.h[k] = *(gptr<const T>)(pb + offb[k]);
   };
   auto fetch_own = [&](int32_t v, Set& S) {
-    const int32_t i = xo + G.nx * (v >= 0 && v < G.ny ? v : 0);
-    if (kReadDirs) S.d = dirs[i];
-    if (kGivenF) S.fv = f[i];
+    const int64_t pl = (int64_t)G.nx * (v >= 0 && v < G.ny ? v : 0) + corner;
+    if (kReadDirs) S.d = (dirs + pl)[rel];
+    if (kGivenF)
+      S.fv = *(gptr<const T>)((gptr<const char>)(f + pl) + rel * (uint32_t)sizeof(T));
   };
   auto commit = [&](int buf, const Set& S) {
 #pragma unroll
     for (int k = 0; k < PER; ++k) {
       const int e = tid + k * 256;
       if (e < RW) {
-        sm.ring.r2[0][buf][e] = or_high(S.h[k], xmask[k] | S.zmask);
-        if (kTwo) sm.ring.r2[1][buf][e] = or_high(S.f[k], xmask[k] | S.zmask);
+        sm.ring.r2[buf][e] = or_high(S.h[k], xmask[k] | S.zmask);
       }
     }
   };
@@ -478,8 +467,8 @@ __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_
   // 2D flag rows are indexed by y: the box's "z" origin is the first row
   FlagBox fbx{x0, y0, y0, 1, kFlagW2, RX + 1};
   unsigned mism = 0, nf = 0, nb = 0;
-  Ext<T> gu{}, gl{}, gbox{}, fu{}, fl{}, fbox{};
-  T gc = T(0), fc = T(0);
+  Ext<T> gu{}, gl{}, gbox{};
+  T gc = T(0);
   auto flag2 = [&](int32_t y, int code) {
     const int m = code & 7, sg = (code & 8) ? -1 : 1;
     const int32_t yy = y + sg * ((m >> 1) & 1);
@@ -493,38 +482,20 @@ __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_
     fetch(r + kSets, S);
     lds_barrier();
     Ext<T> su, sd;
-    pairs(sm.ring.r2[0][buf], su, sd);
+    pairs(sm.ring.r2[buf], su, sd);
     const Ext<T> glo = merge_dn(with_bits(gl, 10), sd);  // lower box of vertex r
-    Ext<T> fsu, fsd, flo;
-    if (kTwo) {
-      pairs(sm.ring.r2[1][buf], fsu, fsd);
-      flo = merge_dn(with_bits(fl, 10), fsd);
-    }
     if (out && mine) {
       const int32_t v = r - 1;
-      const int32_t i = X + G.nx * v;
       const Ext<T> e = merge_up(gbox, merge_up(gu, with_bits(su, 2)));
       const int ca = e.ca, cd = e.cd;
       if (KIND == KIND_DIRS) {
-        dirs[i] = (uint8_t)(ca | (cd << 4));
+        (dirs + ((int64_t)G.nx * v + corner))[rel] = (uint8_t)(ca | (cd << 4));
       } else {
-        int fa, fd;
-        if (KIND == KIND_FIRST) {
-          const Ext<T> ef = merge_up(fbox, merge_up(fu, with_bits(fsu, 2)));
-          fa = ef.ca;
-          fd = ef.cd;
-          dirs[i] = (uint8_t)(fa | (fd << 4));
-          const int bc = bound_class<T>(fc, gc, xi);
+        const int fa = d_cur & 15, fd = d_cur >> 4;
+        if (kGivenF) {
+          const int bc = bound_class<T>(f_cur, gc, xi);
           nf += bc == 1;
           nb += bc == 2;
-        } else {
-          fa = d_cur & 15;
-          fd = d_cur >> 4;
-          if (kGivenF) {
-            const int bc = bound_class<T>(f_cur, gc, xi);
-            nf += bc == 1;
-            nb += bc == 2;
-          }
         }
         // 2D codes only use the x and y bits; rows are indexed by y
         if (ca != fa) {
@@ -540,13 +511,7 @@ __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_
     gu = su;
     gl = sd;
     gbox = glo;
-    gc = sm.ring.r2[0][buf][c];
-    if (kTwo) {
-      fu = fsu;
-      fl = fsd;
-      fbox = flo;
-      fc = sm.ring.r2[1][buf][c];
-    }
+    gc = sm.ring.r2[buf][c];
     fetch_own(r + kSets - 1, S);
   };
 
