@@ -67,10 +67,15 @@ def lib():
         L.orc_flags.argtypes = grid + [i32, vp, vp, vp]
         L.orc_flags.restype = i64
         L.orc_correct.argtypes = grid + [i32, vp, vp, dbl, vp, i64, ctypes.POINTER(Stats)]
+        L.orc_correct_mode.argtypes = grid + [i32, vp, vp, dbl, vp, i64, i32,
+                                              ctypes.POINTER(Stats)]
+        L.orc_flags_targeted.argtypes = grid + [i32, vp, vp, vp, vp]
+        L.orc_flags_targeted.restype = i64
         L.orc_labels.argtypes = grid + [vp, vp, vp]
         L.orc_labels_at.argtypes = grid + [i32, vp, vp, i64, vp, vp]
         L.orc_verify.argtypes = grid + [i32, vp, vp, vp, dbl, ctypes.POINTER(Report)]
         for name in ("orc_directions", "orc_directions_at", "orc_validate", "orc_correct",
+                     "orc_correct_mode",
                      "orc_labels", "orc_labels_at", "orc_verify"):
             getattr(L, name).restype = i32
         _lib = L
@@ -166,17 +171,33 @@ def flags(g, dirs_f):
     return out, int(m)
 
 
-def correct(f, fhat, xi, max_iters=1 << 40, dirs_f=None):
-    """Run the correction on a copy of fhat; returns (g, stats dict)."""
+EDIT_MODES = {"halving": 0, "targeted": 1}
+
+
+def correct(f, fhat, xi, max_iters=1 << 40, dirs_f=None, mode="halving"):
+    """Run the correction on a copy of fhat; returns (g, stats dict).
+    mode: "halving" (Eq. 1 with half the gap to the bound) or "targeted"
+    (each target lowered just below its rival, never below the bound)."""
     f = _c(f)
     g = np.array(fhat, dtype=f.dtype, copy=True, order="C")
     st = Stats()
-    lib().orc_correct(*grid_of(f), _dtype_code(f), _ptr(f), _ptr(g), float(xi),
-                      _ptr(dirs_f) if dirs_f is not None else None, int(max_iters),
-                      ctypes.byref(st))
+    lib().orc_correct_mode(*grid_of(f), _dtype_code(f), _ptr(f), _ptr(g), float(xi),
+                           _ptr(dirs_f) if dirs_f is not None else None, int(max_iters),
+                           EDIT_MODES[mode], ctypes.byref(st))
     d = st.as_dict()
     d["status"] = STATUS[d["status"]]
     return g, d
+
+
+def flags_targeted(g, dirs_f):
+    """Flag set of one iteration with the targeted proposals: returns
+    (flags uint8, proposals float64 (+inf where none), mismatches)."""
+    g, dirs_f = _c(g), _c(dirs_f)
+    out = np.empty(g.shape, dtype=np.uint8)
+    prop = np.empty(g.shape, dtype=np.float64)
+    m = lib().orc_flags_targeted(*grid_of(g), _dtype_code(g), _ptr(g), _ptr(dirs_f), _ptr(out),
+                                 _ptr(prop))
+    return out, prop, int(m)
 
 
 def labels(dirs):

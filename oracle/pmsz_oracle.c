@@ -372,6 +372,65 @@ int64_t orc_flags(int ndim, int64_t nx, int64_t ny, int64_t nz, int dtype, const
   return mism;
 }
 
+/* Targeted edit (the variant of Sec. IV-A's worked examples, where a spurious
+ * maximum is lowered to its rival's value "or slightly below" instead of by a
+ * fixed step).  Every flag carries a proposed value for its target: the
+ * largest value at which the target no longer beats its rival in the (value,
+ * index) order --
+ *   ascending rule  (n_max under g is t, under f it is c != t): rival c;
+ *   descending rule (n_min under f is t, under g it is r != t): rival r;
+ *   proposal = g[rival] when t < rival (the tie then goes to the rival), else
+ *   the next value below g[rival]; a zero proposal is +0.
+ * prop[t] receives the smallest proposal for t (+inf where none); flags and
+ * the return value are those of orc_flags. */
+static double next_below(int dtype, double v) {
+  return dtype == ORC_F32 ? (double)nextafterf((float)v, -INFINITY) : nextafter(v, -INFINITY);
+}
+
+int64_t orc_flags_targeted(int ndim, int64_t nx, int64_t ny, int64_t nz, int dtype,
+                           const void* g, const uint8_t* dirs_f, uint8_t* flags, double* prop) {
+  grid_t G = {ndim, nx, ny, nz};
+  int64_t n = nverts(&G);
+  int32_t* ag = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  int32_t* dg = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+  if (!ag || !dg) { free(ag); free(dg); return -1; }
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    int a, d;
+    steepest(&G, g, dtype, i, &a, &d);
+    ag[i] = (int32_t)follow(&G, i, a);
+    dg[i] = (int32_t)follow(&G, i, d);
+  }
+  memset(flags, 0, (size_t)n);
+  for (int64_t t = 0; t < n; ++t) prop[t] = INFINITY;
+  int64_t mism = 0;
+  for (int64_t i = 0; i < n; ++i) {
+    int64_t af = follow(&G, i, dirs_f[i] & 15);
+    int64_t df = follow(&G, i, dirs_f[i] >> 4);
+    int64_t t = -1, rival = -1;
+    for (int rule = 0; rule < 2; ++rule) {
+      if (rule == 0) {
+        if (ag[i] == af) continue;
+        t = ag[i];
+        rival = af;
+      } else {
+        if (dg[i] == df) continue;
+        t = df;
+        rival = dg[i];
+      }
+      mism++;
+      flags[t] = 1;
+      double rv = val(g, dtype, rival);
+      double p = t < rival ? rv : next_below(dtype, rv);
+      if (p == 0.0) p = 0.0; /* +0 */
+      if (p < prop[t]) prop[t] = p;
+    }
+  }
+  free(ag);
+  free(dg);
+  return mism;
+}
+
 /* The correction loop.  g holds fhat on entry and the last iterate on exit.
  *   k = 0
  *   repeat: F = flags(g^k)
@@ -380,9 +439,9 @@ int64_t orc_flags(int ndim, int64_t nx, int64_t ny, int64_t nz, int dtype, const
  *           k == max_iters            -> NOT_CONVERGED
  *           g_t <- edit(g_t) for t in F, simultaneously; k += 1
  * dirs_f may be NULL (then computed here). */
-int orc_correct(int ndim, int64_t nx, int64_t ny, int64_t nz, int dtype, const void* f,
-                void* g, double xi, const uint8_t* dirs_f_in, int64_t max_iters,
-                orc_stats* st) {
+int orc_correct_mode(int ndim, int64_t nx, int64_t ny, int64_t nz, int dtype, const void* f,
+                     void* g, double xi, const uint8_t* dirs_f_in, int64_t max_iters,
+                     int mode, orc_stats* st) {
   memset(st, 0, sizeof(*st));
   int s = orc_validate(ndim, nx, ny, nz, dtype, f, g, xi);
   if (s == ORC_OK && max_iters < 0) s = ORC_INVALID;
@@ -399,11 +458,19 @@ int orc_correct(int ndim, int64_t nx, int64_t ny, int64_t nz, int dtype, const v
     dirs_f = own;
   }
   uint8_t* flags = (uint8_t*)malloc((size_t)n);
-  if (!flags) { free(own); st->status = ORC_OOM; return ORC_OOM; }
+  double* prop = mode ? (double*)malloc(sizeof(double) * (size_t)n) : NULL;
+  if (!flags || (mode && !prop)) {
+    free(flags);
+    free(prop);
+    free(own);
+    st->status = ORC_OOM;
+    return ORC_OOM;
+  }
   int64_t k = 0;
   int status;
   for (;;) {
-    int64_t mism = orc_flags(ndim, nx, ny, nz, dtype, g, dirs_f, flags);
+    int64_t mism = mode ? orc_flags_targeted(ndim, nx, ny, nz, dtype, g, dirs_f, flags, prop)
+                        : orc_flags(ndim, nx, ny, nz, dtype, g, dirs_f, flags);
     if (mism < 0) { status = ORC_OOM; break; }
     if (k == 0) st->mismatch_initial = mism;
     int64_t nflag = 0, at_lb = 0;
@@ -430,12 +497,14 @@ int orc_correct(int ndim, int64_t nx, int64_t ny, int64_t nz, int dtype, const v
       if (!flags[t]) continue;
       if (dtype == ORC_F32) {
         float* gt = (float*)g + t;
-        float nv = edit_f(*gt, lower_f(((const float*)f)[t], (float)xt));
+        float lb = lower_f(((const float*)f)[t], (float)xt);
+        float nv = mode ? ((float)prop[t] > lb ? (float)prop[t] : lb) : edit_f(*gt, lb);
         if (nv != *gt) changed++;
         *gt = nv;
       } else {
         double* gt = (double*)g + t;
-        double nv = edit_d(*gt, lower_d(((const double*)f)[t], xt));
+        double lb = lower_d(((const double*)f)[t], xt);
+        double nv = mode ? (prop[t] > lb ? prop[t] : lb) : edit_d(*gt, lb);
         if (nv != *gt) changed++;
         *gt = nv;
       }
@@ -446,8 +515,16 @@ int orc_correct(int ndim, int64_t nx, int64_t ny, int64_t nz, int dtype, const v
   st->iterations = k;
   st->status = status;
   free(flags);
+  free(prop);
   free(own);
   return status;
+}
+
+/* The correction with the halving edit of Eq. 1 (mode 0). */
+int orc_correct(int ndim, int64_t nx, int64_t ny, int64_t nz, int dtype, const void* f,
+                void* g, double xi, const uint8_t* dirs_f_in, int64_t max_iters,
+                orc_stats* st) {
+  return orc_correct_mode(ndim, nx, ny, nz, dtype, f, g, xi, dirs_f_in, max_iters, 0, st);
 }
 
 /* Label of vertex i: walk the steepest direction (low nibble = ascending, high

@@ -100,9 +100,18 @@ def exact_upper(f, xi_t, dtype):
             return t
 
 
-def slow_correct(f, fhat, xi_t, adj, max_iters=10 ** 6):
+def beats(vals, a, b):
+    """(value, index) order: a above b."""
+    return vals[a] > vals[b] or (vals[a] == vals[b] and a > b)
+
+
+def slow_correct(f, fhat, xi_t, adj, max_iters=10 ** 6, mode="halving"):
     """Reference correction loop written from the rules of Sec. IV-A, in the
-    field's own numpy scalar type.  Returns (g, iterations, status)."""
+    field's own numpy scalar type.  Returns (g, iterations, status).
+    mode "targeted": each target is lowered to the highest value at which it
+    no longer beats its rival (found here by stepping down value by value from
+    the rival's value), the smallest such value over its flaggers, never below
+    its bound."""
     dt = f.dtype.type
     fl = f.reshape(-1)
     g = fhat.reshape(-1).copy()
@@ -125,9 +134,33 @@ def slow_correct(f, fhat, xi_t, adj, max_iters=10 ** 6):
         if k == max_iters:
             return g.reshape(f.shape), k, "NOT_CONVERGED"
         new = g.copy()
-        for t in targets:
-            half = dt(0.5) * (g[t] - lb[t])
-            m = lb[t] + half
-            new[t] = m if m < g[t] else lb[t]
+        if mode == "targeted":
+            best = {}
+            for i in range(n):
+                up, down = steepest(g, adj, i)
+                pairs = []
+                if up != dir_f[i][0]:
+                    pairs.append((up, dir_f[i][0]))
+                if down != dir_f[i][1]:
+                    pairs.append((dir_f[i][1], down))
+                for t, rival in pairs:
+                    # highest candidate value v with (v, t) below (g[rival], rival)
+                    v = g[rival]
+                    trial = g.copy()
+                    trial[t] = v
+                    while beats(trial, t, rival):
+                        v = np.nextafter(v, dt(-np.inf))
+                        trial[t] = v
+                    if v == 0:
+                        v = dt(0.0)
+                    if t not in best or v < best[t]:
+                        best[t] = v
+            for t in targets:
+                new[t] = best[t] if best[t] > lb[t] else lb[t]
+        else:
+            for t in targets:
+                half = dt(0.5) * (g[t] - lb[t])
+                m = lb[t] + half
+                new[t] = m if m < g[t] else lb[t]
         g = new
         k += 1

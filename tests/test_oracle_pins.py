@@ -439,3 +439,73 @@ def test_special_cases():
     assert st0["status"] == "NOT_CONVERGED" and np.array_equal(g0, fhat2)
     # a negative error bound is invalid
     assert oracle.validate(f, f, -1.0) == "INVALID_ARG"
+
+
+# ---------------------------------------------- targeted-edit variant --------
+# Each flagged vertex is lowered to the highest value at which it no longer
+# beats its rival (the worked examples of Sec. IV-A lower a spurious maximum to
+# its rival's value "or slightly below"), the smallest such value over its
+# flaggers, never below its bound.
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_targeted_ascending_example(dtype):
+    """f = [0, 1, 0.5], fhat = [0, 0.75, 1.0], xi = 0.5: vertex 2 is a spurious
+    maximum; it drops to the value just below its rival's 0.75 (index 2 > 1,
+    so an equal value would still win) in one iteration."""
+    f = np.array([[0, 1, 0.5]], dtype)
+    fh = np.array([[0, 0.75, 1.0]], dtype)
+    g, st = oracle.correct(f, fh, 0.5, mode="targeted")
+    assert st["status"] == "OK" and st["iterations"] == 1 and st["steps_applied"] == 1
+    assert g[0, 2] == np.nextafter(dtype(0.75), dtype(-np.inf))
+    assert g[0, 0] == 0 and g[0, 1] == dtype(0.75)
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_targeted_tie_goes_to_the_rival(dtype):
+    """f = [0, 0.25, 1], fhat = [0.375, 0.125, 1], xi = 0.5: vertex 0 is both a
+    false maximum (rival 1) and the original minimum pushed above vertex 1;
+    index 0 < 1, so the rival's own value 0.125 already settles both ties."""
+    f = np.array([[0, 0.25, 1]], dtype)
+    fh = np.array([[0.375, 0.125, 1]], dtype)
+    flags, prop, m = oracle.flags_targeted(fh, oracle.directions(f))
+    assert np.flatnonzero(flags).tolist() == [0] and prop[0, 0] == 0.125
+    g, st = oracle.correct(f, fh, 0.5, mode="targeted")
+    assert st["status"] == "OK" and st["iterations"] == 1
+    assert g.reshape(-1).tolist() == [0.125, 0.125, 1.0]
+    assert np.array_equal(oracle.directions(g), oracle.directions(f))
+
+
+@pytest.mark.parametrize("seed", range(10))
+@pytest.mark.parametrize("ndim", [2, 3])
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_targeted_oracle_matches_slow_correction(seed, ndim, dtype):
+    f, fhat, xi = _tiny_case(100 + seed, ndim, dtype, ties=seed % 2 == 0)
+    adj = brute.adjacency(*grid_args(f.shape))
+    g_slow, k_slow, st_slow = brute.slow_correct(f, fhat, oracle.xi_t(dtype, xi), adj,
+                                                 mode="targeted")
+    g, st = oracle.correct(f, fhat, xi, mode="targeted")
+    assert st["status"] == st_slow
+    assert st["iterations"] == k_slow
+    assert np.array_equal(g.view(np.uint8), g_slow.view(np.uint8))
+
+
+@pytest.mark.parametrize("ndim", [2, 3])
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_targeted_invariants(ndim, dtype):
+    """Monotone, within bounds, edits only at flagged vertices, directions of f
+    restored at convergence; and on this input no more iterations than the
+    halving edit needs."""
+    f, fhat, xi, lb, ub = _invariant_case(ndim, dtype, 9)
+    g_final, st = oracle.correct(f, fhat, xi, mode="targeted")
+    assert st["status"] == "OK"
+    prev = fhat
+    dirs_f = oracle.directions(f)
+    for k in range(1, st["iterations"] + 1):
+        gk, _ = oracle.correct(f, fhat, xi, max_iters=k, mode="targeted")
+        assert np.all(gk <= prev) and np.all(gk >= lb) and np.all(gk <= ub)
+        flags, _ = oracle.flags(prev, dirs_f)
+        assert np.all(flags.astype(bool) | (gk == prev))
+        prev = gk
+    assert np.array_equal(oracle.directions(g_final), dirs_f)
+    _, st_half = oracle.correct(f, fhat, xi)
+    assert st["iterations"] <= st_half["iterations"]
