@@ -21,7 +21,6 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Gvoxels/s corrected at 512^3 fp32 ε=1e-4; batched vs plain; serve p50/p99 ms"
 HBM_PEAK_GBS = 8000.0
-ENGINE_KERNEL = "k_engine<float>"
 ENGINE_SOURCES = ["engine.hip", "engine.hpp", "tiles.hpp", "common.hpp"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "engine_perlin512_f32_traffic.json")
 
@@ -46,16 +45,30 @@ def algorithmic_bytes(voxels, swept, edits, s):
     return voxels * (2 * s + 1) + max(swept - voxels, 0) * (s + 1.125) + edits * 3 * s
 
 
-def measured_traffic():
-    """HBM bytes per launch from the committed rocprofv3 counter runs, if they
-    were taken on the current engine source."""
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    runs, if they were taken on the current source."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     with open(TRAFFIC_FILE) as fh:
         t = json.load(fh)
     if t.get("source_hash") != source_hash():
         return None
-    return t.get("bytes_per_launch")
+    return t.get("bytes_per_launch", {}).get(kernel)
+
+
+def kernel_split(tm, rounds, s):
+    """Per kernel of one correction: (total ms, launches, algorithmic bytes).
+    The directions kernel reads f and writes the direction bytes (s + 1 per
+    vertex).  The engine's first round reads fhat, f and the direction bytes
+    (2s + 1 per vertex); a later round reads g and the direction bytes and
+    writes flag bits (s + 1.125) per vertex examined, in tiles or by sparse
+    examination; an edit reads f and g and writes g (3s)."""
+    swept = [r["swept"] for r in rounds]
+    engine_bytes = (swept[0] * (2 * s + 1) if swept else 0) + \
+        sum(swept[1:]) * (s + 1.125) + tm["edits"] * 3 * s
+    return {"k_dirs_fields": (tm["dirs_ms"], 1, tm["voxels"] * (s + 1)),
+            "k_engine": (tm["engine_ms"], 1, engine_bytes)}
 
 
 def cpu_baseline(f, fhat, xi, planes):
@@ -138,14 +151,49 @@ def bench_large(dev, steps):
         tm = pmsz.last_timing()
     ms_step = sum(ms) / len(ms)
     alg = algorithmic_bytes(tm["voxels"], tm["swept"], tm["edits"], 8)
+    dev_ms = tm["dirs_ms"] + tm["engine_ms"]
     return {"workload": "grf k^-3 1024x1024x768 f64, rel eps 1e-5, seed 1024",
             "voxels": f.numel(), "steps": steps, "ms_per_step": round(ms_step, 3),
             "gvox_s": round(f.numel() / ms_step / 1e6, 3),
+            "device_ms": round(dev_ms, 3), "dirs_ms": round(tm["dirs_ms"], 3),
             "engine_ms": round(tm["engine_ms"], 3),
-            "hbm_frac": round(alg / (tm["engine_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "hbm_frac": round(alg / (dev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "iterations": st["iterations"], "edits": st["steps_applied"],
             "mismatch_initial": st["mismatch_initial"], "rounds": tm["rounds"],
             "swept_vertices": tm["swept"], "status": st["status"]}
+
+
+def bench_targeted(f, fhat, xi, steps, g_halving):
+    """The targeted-edit variant on the same resident workload: time, rounds,
+    edits and the edit ratio (vertices whose value changed / all vertices,
+    the paper's edit-ratio measure), beside the halving edit's."""
+    import torch
+
+    import paper_2601_01787_amd as pmsz
+    ws = pmsz.workspace(pmsz.grid_of(f), pmsz.WS_CORRECT_TARGETED, f.device)
+    g = fhat.clone()
+    _, st = pmsz.correct(f, g, xi, inplace=True, ws=ws, mode="targeted")  # warm-up
+    ms = []
+    for _ in range(steps):
+        g.copy_(fhat)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = pmsz.correct(f, g, xi, inplace=True, ws=ws, mode="targeted")
+        torch.cuda.synchronize()
+        ms.append((time.perf_counter() - t0) * 1e3)
+    rep_t = pmsz.verify(f, g, fhat, xi)
+    rep_h = pmsz.verify(f, g_halving, fhat, xi)
+    n = f.numel()
+    ms_step = sum(ms) / len(ms)
+    return {"ms_per_step": round(ms_step, 4), "gvox_s": round(n / ms_step / 1e6, 3),
+            "status": st["status"], "iterations": st["iterations"],
+            "edits": st["steps_applied"], "vertices_edited": rep_t["vertices_edited"],
+            "edit_ratio": round(rep_t["vertices_edited"] / n, 6),
+            "max_abs_err": rep_t["max_abs_err"],
+            "halving_vertices_edited": rep_h["vertices_edited"],
+            "halving_edit_ratio": round(rep_h["vertices_edited"] / n, 6),
+            "halving_max_abs_err": rep_h["max_abs_err"],
+            "directions_restored": rep_t["asc_mismatch"] == 0 and rep_t["desc_mismatch"] == 0}
 
 
 def bench_serving(dev, rates, n_requests, pool_per_class, seed):
@@ -212,6 +260,8 @@ def main():
     ap.add_argument("--cpu-planes", type=int, default=512)
     ap.add_argument("--batch-fields", type=int, default=256,
                     help="fields of the uneven 2D batch (0 skips the batched comparison)")
+    ap.add_argument("--targeted-steps", type=int, default=3,
+                    help="timed steps of the targeted-edit variant on the same workload (0 skips)")
     ap.add_argument("--large-steps", type=int, default=3,
                     help="timed steps of the 1024x1024x768 binary64 workload (0 skips it)")
     ap.add_argument("--serve-rates", default="50,200,500",
@@ -247,7 +297,7 @@ def main():
         src = torch.empty(args.copy_probe_mib << 18, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        torch.add(src, 1.0, out=dst)  # one elementwise kernel: reads and writes the size once
+        dst.copy_(src)  # a device-to-device copy: HIP's copy kernel reads and writes the size once
         torch.cuda.synchronize()
         log("copy probe: %d MiB read, %d MiB written" % (args.copy_probe_mib, args.copy_probe_mib))
         del src, dst
@@ -259,14 +309,12 @@ def main():
     torch.cuda.synchronize()
 
     log("timing", K, "steps")
-    eng_ms, tims, stats = [], [], []
+    tims, stats, rounds_all = [], [], []
     t0 = time.perf_counter()
     for i in range(K):
         _, st = pmsz.correct(f, gs[W + i], xi, inplace=True, ws=ws)
-        tm = pmsz.last_timing()
-        per_round = pmsz.last_rounds()
-        eng_ms.append(tm["engine_ms"])
-        tims.append(tm)
+        tims.append(pmsz.last_timing())
+        rounds_all.append(pmsz.last_rounds())
         stats.append(st)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -276,14 +324,32 @@ def main():
         assert st["status"] == "OK" and st["iterations"] == stats[0]["iterations"], st
 
     tm = tims[-1]
+    per_round = rounds_all[-1]
     s = f.element_size()
-    alg = algorithmic_bytes(tm["voxels"], tm["swept"], tm["edits"], s)
-    avg_ms = sum(eng_ms) / len(eng_ms)
-    achieved = alg / (avg_ms * 1e-3) / 1e9
+    # the dominant kernel: the largest share of the correction's device time
+    split = {}
+    for t, rr in zip(tims, rounds_all):
+        for k, (ms, n, b) in kernel_split(t, rr, s).items():
+            acc = split.setdefault(k, [0.0, 0, 0.0])
+            acc[0] += ms
+            acc[1] += n
+            acc[2] += b
+    dom = max(split, key=lambda k: split[k][0])
+    ms_tot, launches, bytes_tot = split[dom]
+    avg_ms = ms_tot / launches
+    per_launch = bytes_tot / launches
+    achieved = per_launch / (avg_ms * 1e-3) / 1e9
+    name = dom + "<float>"
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(), "kernel": ENGINE_KERNEL,
-                "kernel_avg_ms": round(avg_ms, 4), "algorithmic_bytes": int(alg)}
+                "traffic": measured_traffic(name), "kernel": name,
+                "kernel_avg_ms": round(avg_ms, 4), "algorithmic_bytes": int(per_launch),
+                "launches_per_step": launches // len(tims)}
+    kernels = {k + "<float>": {"ms_per_step": round(v[0] / len(tims), 4),
+                               "launches_per_step": v[1] // len(tims),
+                               "algorithmic_gbs": round(v[2] / (v[0] * 1e-3) / 1e9, 1)
+                               if v[0] > 0 else None}
+               for k, v in split.items()}
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "Gvoxels/s", "n_gpus": 1,
         "steps": K, "warmup": W, "ms_per_step": round(ms_per_step, 4),
@@ -296,16 +362,20 @@ def main():
         "detail": {"iterations": stats[0]["iterations"], "edits": stats[0]["steps_applied"],
                    "mismatch_initial": stats[0]["mismatch_initial"], "rounds": tm["rounds"],
                    "swept_vertices": tm["swept"], "tiles": tm["tiles"], "grid": tm["grid"],
-                   "engine_ms_per_step": round(avg_ms, 4),
+                   "kernels": kernels,
                    "first_round_ms": round(tm["first_round_ms"], 4),
                    "later_detect_ms": round(tm["detect_ms"], 4),
                    "later_apply_ms": round(tm["apply_ms"], 4),
                    "per_round": {"detect_ms": [round(r["detect_ms"], 4) for r in per_round],
+                                 "sparse": [r["sparse"] for r in per_round],
                                  "apply_ms": [round(r["apply_ms"], 4) for r in per_round],
                                  "swept": [r["swept"] for r in per_round],
                                  "flagged": [r["flagged"] for r in per_round],
                                  "edits": [r["edits"] for r in per_round]}},
     }
+    if args.targeted_steps:
+        log("targeted-edit variant:", args.targeted_steps, "steps")
+        out["targeted"] = bench_targeted(f, fhat, xi, args.targeted_steps, gs[-1])
     del gs
     torch.cuda.empty_cache()
     if args.batch_fields:

@@ -110,7 +110,10 @@ typedef struct {
 } pmsz_field;
 
 /* Workspace kinds for pmsz_workspace_size. */
-enum { PMSZ_WS_CORRECT = 0, PMSZ_WS_VERIFY = 1, PMSZ_WS_LABELS = 2 };
+enum { PMSZ_WS_CORRECT = 0, PMSZ_WS_VERIFY = 1, PMSZ_WS_LABELS = 2, PMSZ_WS_CORRECT_TARGETED = 3 };
+
+/* Edit rules for pmsz_correct_mode. */
+enum { PMSZ_EDIT_HALVING = 0, PMSZ_EDIT_TARGETED = 1 };
 
 /* Bytes of device workspace that operation `op` needs for `grid`
  * (*bytes, host).  Returns PMSZ_ERR_INVALID_ARG for a bad grid or op. */
@@ -144,6 +147,22 @@ int pmsz_directions(const pmsz_grid* grid, const void* field, uint8_t* dirs, voi
 int pmsz_correct(const pmsz_grid* grid, const void* f, void* g, double xi,
                  const uint8_t* dirs_f, void* ws, size_t ws_bytes, int64_t max_iters,
                  pmsz_stats* stats, void* stream);
+
+/* pmsz_correct with a choice of edit rule.  PMSZ_EDIT_HALVING is
+ * pmsz_correct.  PMSZ_EDIT_TARGETED follows the worked examples of Sec. IV-A,
+ * where a vertex is lowered to its rival's value "or slightly below": every
+ * flag carries a proposal for its target, the highest value at which the
+ * target no longer beats its rival in the (value, index) order (ascending
+ * rule: the rival is n_max^f(i); descending rule: the current n_min^g(i)),
+ * i.e. the rival's value when the target has the smaller index, else the next
+ * value below it (+0 for zero); each flagged t then takes
+ * max(lb_t, smallest proposal).  The stopping rules are those of
+ * pmsz_correct.  ws: pmsz_workspace_size(grid, PMSZ_WS_CORRECT_TARGETED)
+ * bytes for the targeted rule (one proposal word of the value size per
+ * vertex more).  An unknown mode returns PMSZ_ERR_INVALID_ARG. */
+int pmsz_correct_mode(const pmsz_grid* grid, const void* f, void* g, double xi,
+                      const uint8_t* dirs_f, int edit_mode, void* ws, size_t ws_bytes,
+                      int64_t max_iters, pmsz_stats* stats, void* stream);
 
 /* Batched correction of n independent fields in one persistent launch.  Each
  * field follows exactly the iteration of pmsz_correct (bit-identical results
@@ -211,11 +230,11 @@ int pmsz_session_remove(pmsz_session* s, int32_t handle);
 int pmsz_session_destroy(pmsz_session* s);
 
 /* Measurements of the last pmsz_correct / pmsz_correct_batched call made on
- * this thread (host struct): the duration of its persistent correction
- * kernel, timed with HIP events recorded on the caller's stream around that
- * launch, and the work it did.  Used by the benchmark for roofline figures. */
+ * this thread (host struct): the durations of its kernels, timed with HIP
+ * events recorded on the caller's stream around each launch, and the work it
+ * did.  Used by the benchmark for roofline figures. */
 typedef struct {
-  double engine_ms;  /* duration of the correction kernel launch             */
+  double engine_ms;  /* the persistent correction kernel                       */
   int64_t rounds;    /* detect/apply rounds it ran                            */
   int64_t swept;     /* vertices examined by detect passes, all rounds        */
   int64_t edits;     /* value changes, all fields                             */
@@ -242,6 +261,9 @@ typedef struct {
   int64_t swept;     /* vertices examined by the detect pass                */
   int64_t flagged;   /* |F|: distinct flagged vertices                      */
   int64_t edits;     /* values changed by the apply pass                    */
+  int64_t sparse;    /* of `swept`, examinations of a sparse round (the
+                        neighbours of the previous round's targets); the
+                        rest were swept in tiles                               */
 } pmsz_round;
 
 /* Copies min(cap, rounds recorded) records into out[] (host) and stores the

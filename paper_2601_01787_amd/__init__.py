@@ -19,14 +19,15 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpmsz.so")
 
 F32, F64 = 0, 1
-WS_CORRECT, WS_VERIFY, WS_LABELS = 0, 1, 2
+WS_CORRECT, WS_VERIFY, WS_LABELS, WS_CORRECT_TARGETED = 0, 1, 2, 3
+EDIT_MODES = {"halving": 0, "targeted": 1}
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "NONFINITE", 3: "INPUT_BOUND", 4: "NOT_CONVERGED",
           5: "STALLED", 6: "OOM", 7: "DEVICE"}
 DEFAULT_MAX_ITERS = 1 << 40
 
 EXPORTS = ("pmsz_workspace_size", "pmsz_directions", "pmsz_correct",
            "pmsz_batched_workspace_size", "pmsz_correct_batched", "pmsz_labels",
-           "pmsz_verify", "pmsz_last_timing", "pmsz_last_rounds", "pmsz_session_workspace_size",
+           "pmsz_correct_mode", "pmsz_verify", "pmsz_last_timing", "pmsz_last_rounds", "pmsz_session_workspace_size",
            "pmsz_field_workspace_size", "pmsz_session_create", "pmsz_session_add",
            "pmsz_session_step", "pmsz_session_sync", "pmsz_session_result",
            "pmsz_session_remove", "pmsz_session_destroy", "pmsz_status_string",
@@ -81,7 +82,8 @@ class Timing(ctypes.Structure):
 
 class Round(ctypes.Structure):
     _fields_ = [("detect_ms", ctypes.c_double), ("apply_ms", ctypes.c_double),
-                ("swept", ctypes.c_int64), ("flagged", ctypes.c_int64), ("edits", ctypes.c_int64)]
+                ("swept", ctypes.c_int64), ("flagged", ctypes.c_int64), ("edits", ctypes.c_int64),
+                ("sparse", ctypes.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -110,6 +112,8 @@ def load():
     L.pmsz_workspace_size.argtypes = [G, ctypes.c_int, ctypes.POINTER(sz)]
     L.pmsz_directions.argtypes = [G, vp, vp, vp]
     L.pmsz_correct.argtypes = [G, vp, vp, dbl, vp, vp, sz, i64, ctypes.POINTER(Stats), vp]
+    L.pmsz_correct_mode.argtypes = [G, vp, vp, dbl, vp, ctypes.c_int, vp, sz, i64,
+                                    ctypes.POINTER(Stats), vp]
     L.pmsz_batched_workspace_size.argtypes = [i32, ctypes.POINTER(Field), ctypes.POINTER(sz)]
     L.pmsz_correct_batched.argtypes = [i32, ctypes.POINTER(Field), vp, sz, i64,
                                        ctypes.POINTER(Stats), vp]
@@ -198,26 +202,29 @@ def directions(h, out=None):
     return out
 
 
-def correct(f, fhat, xi, *, inplace=False, max_iters=DEFAULT_MAX_ITERS, dirs_f=None, ws=None):
+def correct(f, fhat, xi, *, inplace=False, max_iters=DEFAULT_MAX_ITERS, dirs_f=None, ws=None,
+            mode="halving"):
     """Correct fhat toward f's topology within |g - f| <= xi.
 
-    Returns (g, stats).  ``stats['status']`` is "OK", "STALLED",
-    "NOT_CONVERGED", "NONFINITE" or "INPUT_BOUND"; argument and device errors
-    raise PmszError."""
+    mode: "halving" (pmsz_correct) or "targeted" (pmsz_correct_mode with
+    PMSZ_EDIT_TARGETED).  Returns (g, stats).  ``stats['status']`` is "OK",
+    "STALLED", "NOT_CONVERGED", "NONFINITE" or "INPUT_BOUND"; argument and
+    device errors raise PmszError."""
     _dev(f, "f")
     _dev(fhat, "fhat")
     if fhat.shape != f.shape or fhat.dtype != f.dtype or fhat.device != f.device:
         raise ValueError("f and fhat must match in shape, dtype and device")
     g = fhat if inplace else fhat.clone()
     grid = grid_of(f)
+    emode = EDIT_MODES[mode]
     if ws is None:
-        ws = workspace(grid, WS_CORRECT, f.device)
+        ws = workspace(grid, WS_CORRECT_TARGETED if emode else WS_CORRECT, f.device)
     st = Stats()
     dptr = ctypes.c_void_p(_dev(dirs_f, "dirs_f").data_ptr()) if dirs_f is not None else None
-    code = load().pmsz_correct(ctypes.byref(grid), ctypes.c_void_p(f.data_ptr()),
-                               ctypes.c_void_p(g.data_ptr()), float(xi), dptr,
-                               ctypes.c_void_p(ws.data_ptr()), ws.numel(), int(max_iters),
-                               ctypes.byref(st), _stream(f))
+    code = load().pmsz_correct_mode(ctypes.byref(grid), ctypes.c_void_p(f.data_ptr()),
+                                    ctypes.c_void_p(g.data_ptr()), float(xi), dptr, emode,
+                                    ctypes.c_void_p(ws.data_ptr()), ws.numel(), int(max_iters),
+                                    ctypes.byref(st), _stream(f))
     _raise_if(code, allowed=(0, 2, 3, 4, 5))
     return g, st.as_dict()
 

@@ -97,10 +97,11 @@ VerifyLayout verify_layout(const Geo& G) {
 // bytes is cleared by one kernel before the launch.
 // ---------------------------------------------------------------------------
 struct BatchPlan {
-  size_t ctl = 0, desc = 0, out = 0, trace = 0, fields = 0, dirs = 0, total = 0;
+  size_t ctl = 0, desc = 0, out = 0, trace = 0, fields = 0, dirs = 0, prop = 0, total = 0;
   int64_t total_tiles = 0, total_segs = 0;
+  int edit_mode = 0;  // 0 halving, 1 targeted (proposal arrays after dirs)
   std::vector<FieldDesc> fd;
-  std::vector<size_t> field_off, dirs_off;
+  std::vector<size_t> field_off, dirs_off, prop_off;
 };
 
 // Descriptor of one field with everything but its device pointers.
@@ -121,11 +122,13 @@ int describe_field(const pmsz_field& fld, int64_t max_iters, int dirs_given, Fie
 }
 
 int plan_batch(int32_t n, const pmsz_field* fields, const uint8_t* const* dirs_given,
-               int64_t max_iters, BatchPlan& P) {
+               int64_t max_iters, BatchPlan& P, int edit_mode = 0) {
   P.fd.resize(n);
   P.field_off.resize(n);
   P.dirs_off.resize(n);
-  size_t fbytes = 0, dbytes = 0;
+  P.prop_off.resize(n);
+  P.edit_mode = edit_mode;
+  size_t fbytes = 0, dbytes = 0, pbytes = 0;
   for (int32_t i = 0; i < n; ++i) {
     if (fields[i].grid.dtype != fields[0].grid.dtype)
       return fail(PMSZ_ERR_INVALID_ARG, "all fields of a batch must share one dtype");
@@ -141,6 +144,9 @@ int plan_batch(int32_t n, const pmsz_field* fields, const uint8_t* const* dirs_g
     fbytes += L.total;
     P.dirs_off[i] = dbytes;
     if (!d.dirs_given) dbytes += align_up((size_t)d.geo.n);
+    P.prop_off[i] = pbytes;
+    const size_t vsize = fields[i].grid.dtype == PMSZ_F64 ? 8 : 4;
+    if (edit_mode) pbytes += align_up((size_t)d.geo.n * vsize);
   }
   P.ctl = 0;
   P.desc = align_up(sizeof(EngineCtl));
@@ -148,7 +154,8 @@ int plan_batch(int32_t n, const pmsz_field* fields, const uint8_t* const* dirs_g
   P.trace = P.out + align_up(sizeof(FieldIter) * (size_t)n);
   P.fields = P.trace + align_up(kTraceBytes);
   P.dirs = P.fields + fbytes;
-  P.total = P.dirs + dbytes;
+  P.prop = P.dirs + dbytes;
+  P.total = P.prop + pbytes;
   return PMSZ_OK;
 }
 
@@ -177,7 +184,7 @@ int staging(Staging& s, size_t bytes, void** out) {
 
 // Events around the engine launch and the figures of the last run.
 struct Timing {
-  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // engine start, engine end, dirs start
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // directions, engine, end
   pmsz_timing last;
   pmsz_round rounds[kTraceRounds];
   int64_t nrounds = 0;
@@ -217,6 +224,7 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
     d.list = (uint32_t*)(fb + L.list);
     d.list_cap = list_capacity(d.geo);
     d.dirs = d.dirs_given ? (uint8_t*)dirs_given[i] : (uint8_t*)(base + P.dirs + P.dirs_off[i]);
+    d.prop = P.edit_mode ? (void*)(base + P.prop + P.prop_off[i]) : nullptr;
   }
   const size_t up = sizeof(FieldDesc) * (size_t)n;
   const size_t down = sizeof(EngineCtl) + kTraceBytes + sizeof(FieldIter) * (size_t)n;
@@ -227,6 +235,8 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
   EngineCtl* ctl = (EngineCtl*)(base + P.ctl);
   FieldIter* out = (FieldIter*)(base + P.out);
   HIP_TRY(engine_zero(base, P.dirs, s));
+  // proposal keys start unset (all ones)
+  if (P.edit_mode) HIP_TRY(engine_fill(base + P.prop, P.total - P.prop, 0xFFFFFFFFu, s));
   HIP_TRY(hipMemcpyAsync(base + P.desc, stage, up, hipMemcpyHostToDevice, s));
   EngineArgs a;
   a.fd = (const FieldDesc*)(base + P.desc);
@@ -244,11 +254,12 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
   int grid = 0;
   bool need_dirs = false;
   for (int32_t i = 0; i < n; ++i) need_dirs |= !P.fd[i].dirs_given;
-  HIP_TRY(hipEventRecord(tm.ev[2], s));
-  if (need_dirs) HIP_TRY(engine_dirs(dtype, a.fd, n, P.total_tiles, s));
+  // directions of f, then the whole correction loop in one launch
   HIP_TRY(hipEventRecord(tm.ev[0], s));
-  HIP_TRY(engine_launch(dtype, a, s, &grid));
+  if (need_dirs) HIP_TRY(engine_dirs(dtype, a.fd, n, P.total_tiles, s));
   HIP_TRY(hipEventRecord(tm.ev[1], s));
+  HIP_TRY(engine_launch(dtype, a, s, &grid));
+  HIP_TRY(hipEventRecord(tm.ev[2], s));
   // the staging buffer is reused for the results: the upload above is
   // stream-ordered before this copy, so it has been consumed
   HIP_TRY(hipMemcpyAsync(stage, ctl, sizeof(EngineCtl), hipMemcpyDeviceToHost, s));
@@ -262,12 +273,11 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
   const FieldIter* hs =
       (const FieldIter*)((char*)stage + sizeof(EngineCtl) + kTraceBytes);
   if (hc->error) return fail(PMSZ_ERR_DEVICE, "grid barrier timed out in the correction engine");
-  float ms = 0.f, dms = 0.f;
-  HIP_TRY(hipEventElapsedTime(&ms, tm.ev[0], tm.ev[1]));
-  HIP_TRY(hipEventElapsedTime(&dms, tm.ev[2], tm.ev[0]));
+  float el[2];
+  for (int k = 0; k < 2; ++k) HIP_TRY(hipEventElapsedTime(&el[k], tm.ev[k], tm.ev[k + 1]));
   memset(&tm.last, 0, sizeof(tm.last));
-  tm.last.engine_ms = ms;
-  tm.last.dirs_ms = dms;
+  tm.last.dirs_ms = el[0];
+  tm.last.engine_ms = el[1];
   tm.last.rounds = (int64_t)hc->rounds;
   tm.last.tiles = P.total_tiles;
   tm.last.grid = grid;
@@ -284,6 +294,7 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
       o.swept = (int64_t)t[3];
       o.flagged = (int64_t)t[4];
       o.edits = (int64_t)t[5];
+      o.sparse = (int64_t)t[6];
       if (r == 0) {
         tm.last.first_round_ms = o.detect_ms + o.apply_ms;
       } else {
@@ -408,12 +419,13 @@ int pmsz_workspace_size(const pmsz_grid* grid, int op, size_t* bytes) {
   if (!bytes) return fail(PMSZ_ERR_INVALID_ARG, "bytes is NULL");
   const Geo G = make_geo(*grid);
   switch (op) {
-    case PMSZ_WS_CORRECT: {
+    case PMSZ_WS_CORRECT:
+    case PMSZ_WS_CORRECT_TARGETED: {
       pmsz_field one;
       memset(&one, 0, sizeof(one));
       one.grid = *grid;
       BatchPlan P;
-      if ((r = plan_batch(1, &one, nullptr, 0, P))) return r;
+      if ((r = plan_batch(1, &one, nullptr, 0, P, op == PMSZ_WS_CORRECT_TARGETED))) return r;
       *bytes = P.total;
       break;
     }
@@ -436,6 +448,15 @@ int pmsz_directions(const pmsz_grid* grid, const void* field, uint8_t* dirs, voi
 int pmsz_correct(const pmsz_grid* grid, const void* f, void* g, double xi,
                  const uint8_t* dirs_f, void* ws, size_t ws_bytes, int64_t max_iters,
                  pmsz_stats* stats, void* stream) {
+  return pmsz_correct_mode(grid, f, g, xi, dirs_f, PMSZ_EDIT_HALVING, ws, ws_bytes, max_iters,
+                           stats, stream);
+}
+
+int pmsz_correct_mode(const pmsz_grid* grid, const void* f, void* g, double xi,
+                      const uint8_t* dirs_f, int edit_mode, void* ws, size_t ws_bytes,
+                      int64_t max_iters, pmsz_stats* stats, void* stream) {
+  if (edit_mode != PMSZ_EDIT_HALVING && edit_mode != PMSZ_EDIT_TARGETED)
+    return fail(PMSZ_ERR_INVALID_ARG, "unknown edit mode %d", edit_mode);
   int r = check_grid(grid);
   if (r) return r;
   if (!f || !g || !ws || !stats) return fail(PMSZ_ERR_INVALID_ARG, "NULL argument");
@@ -449,7 +470,7 @@ int pmsz_correct(const pmsz_grid* grid, const void* f, void* g, double xi,
   one.xi = xi;
   const uint8_t* given[1] = {dirs_f};
   BatchPlan P;
-  if ((r = plan_batch(1, &one, given, max_iters, P))) return r;
+  if ((r = plan_batch(1, &one, given, max_iters, P, edit_mode))) return r;
   if (ws_bytes < P.total) return fail(PMSZ_ERR_OOM, "workspace %zu bytes, need %zu", ws_bytes, P.total);
   memset(stats, 0, sizeof(*stats));
   return run_batch(grid->dtype, P, given, ws, stats, (hipStream_t)stream);

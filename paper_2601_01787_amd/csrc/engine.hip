@@ -296,15 +296,21 @@ __device__ __forceinline__ void gather_dirs(const TileGeo& G, gptr<const T> g, i
   }
 }
 
-// Examination m of a sparse round: neighbour m % per of listed target m / per.
-// Returns the number of mismatches found (0, 1 or 2).
+// Examination m of a sparse round: neighbour m % per of the target m / per
+// listed by the previous round's apply pass.  Returns the targets the
+// examined vertex flags (-1: none) and its number of mismatches.
+struct Exam {
+  int32_t ta, td;  // ascending-rule and descending-rule targets
+  unsigned n;      // mismatches found (0, 1 or 2)
+};
+
 template <class T>
-__device__ __forceinline__ unsigned sparse_examine(const FieldDesc& d, uint32_t m) {
+__device__ __forceinline__ Exam sparse_examine(const FieldDesc& d, uint32_t m) {
   const TileGeo& G = d.geo;
   const bool three = G.ndim == 3;
   const uint32_t k = three ? m / 15u : m / 7u;
   const uint32_t j = m - k * (three ? 15u : 7u);
-  const int32_t t = (int32_t)d.list[k];
+  const int32_t t = (int32_t)as_global(d.list)[k];
   // the vertex itself, then its neighbours: 3D codes 1..7, 9..15; 2D 1..3, 9..11
   const int code = three ? (j < 8 ? (int)j : (int)j + 1) : (j < 4 ? (int)j : (int)j + 5);
   // is the neighbour inside the box?
@@ -314,31 +320,91 @@ __device__ __forceinline__ unsigned sparse_examine(const FieldDesc& d, uint32_t 
   const int32_t y = three ? (t / G.nx) % G.ny : t / G.nx;
   const int32_t z = three ? t / G.sxy : 0;
   const int32_t X = x + sg * (mm & 1), Y = y + sg * ((mm >> 1) & 1), Z = z + sg * ((mm >> 2) & 1);
-  if (X < 0 || X >= G.nx || Y < 0 || Y >= G.ny || Z < 0 || Z >= G.nz) return 0;
+  Exam ex{-1, -1, 0u};
+  if (X < 0 || X >= G.nx || Y < 0 || Y >= G.ny || Z < 0 || Z >= G.nz) return ex;
   const int32_t v = t + code_offset(G, code);
   int ca, cd;
   gather_dirs<T>(G, as_global((const T*)d.g), v, X, Y, Z, ca, cd);
   const int d8 = as_global(d.dirs)[v];
   const int fa = d8 & 15, fd = d8 >> 4;
-  const gptr<uint32_t> bm = as_global(d.bm);
-  unsigned n = 0;
   // targets are neighbours of v, inside the box for directions made by the
   // direction pass; the range check only guards the bitmap
+  const gptr<const T> g = as_global((const T*)d.g);
   if (ca != fa) {
     const int32_t tt = v + code_offset(G, ca);
-    if ((uint32_t)tt < (uint32_t)G.n)
-      __hip_atomic_fetch_or(bm + (tt >> 5), 1u << (tt & 31), __ATOMIC_RELAXED,
-                            __HIP_MEMORY_SCOPE_AGENT);
-    ++n;
+    if ((uint32_t)tt < (uint32_t)G.n) {
+      ex.ta = tt;
+      if (d.prop) {
+        const int32_t c = v + code_offset(G, fa);
+        propose<T>(d.prop, tt, c, g[c]);
+      }
+    }
+    ++ex.n;
   }
   if (cd != fd) {
     const int32_t tt = v + code_offset(G, fd);
-    if ((uint32_t)tt < (uint32_t)G.n)
-      __hip_atomic_fetch_or(bm + (tt >> 5), 1u << (tt & 31), __ATOMIC_RELAXED,
-                            __HIP_MEMORY_SCOPE_AGENT);
-    ++n;
+    if ((uint32_t)tt < (uint32_t)G.n) {
+      ex.td = tt;
+      if (d.prop) {
+        const int32_t r = v + code_offset(G, cd);
+        propose<T>(d.prop, tt, r, g[r]);
+      }
+    }
+    ++ex.n;
   }
-  return n;
+  return ex;
+}
+
+// Per-thread running count for one field at a time; `flush` adds a wave's
+// counts with one atomic when its lanes agree on the field.
+struct FieldAcc {
+  int f = -1;
+  unsigned long long n = 0;
+};
+template <class Ptr>
+__device__ __forceinline__ void acc_add(FieldAcc& acc, int fi, unsigned long long v, Ptr ptr) {
+  if (fi != acc.f) {
+    if (acc.n) atomicAdd(ptr(acc.f), acc.n);
+    acc.f = fi;
+    acc.n = 0;
+  }
+  acc.n += v;
+}
+template <class Ptr>
+__device__ __forceinline__ void acc_flush(FieldAcc& acc, Ptr ptr) {  // whole waves
+  const int f0 = __shfl(acc.f, 0, 64);
+  if (__all(acc.f == f0 || acc.n == 0)) {
+    const unsigned long long w = wave_sum(acc.n);
+    if ((threadIdx.x & 63) == 0 && w) atomicAdd(ptr(f0), w);
+  } else if (acc.n) {
+    atomicAdd(ptr(acc.f), acc.n);
+  }
+  acc.f = -1;
+  acc.n = 0;
+}
+
+// Inclusive prefix sums of one value per thread into s_pre; returns the
+// total (all threads).
+__device__ __forceinline__ long long block_prefix(long long v, long long* s_pre) {
+  const int tid = threadIdx.x;
+  s_pre[tid] = v;
+  __syncthreads();
+  for (int o = 1; o < 256; o <<= 1) {
+    const long long u = tid >= o ? s_pre[tid - o] : 0;
+    __syncthreads();
+    s_pre[tid] += u;
+    __syncthreads();
+  }
+  return s_pre[255];
+}
+// First entry of s_pre[0..n) exceeding m.
+__device__ __forceinline__ int prefix_find(const long long* s_pre, int n, long long m) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (s_pre[mid] > m) hi = mid; else lo = mid + 1;
+  }
+  return lo;
 }
 
 constexpr int kApplyCap = 2048;   // targets per compaction pass
@@ -350,7 +416,7 @@ template <class T>
 __device__ __forceinline__ void apply_segment(const FieldDesc& d, int32_t w0, int32_t w1,
                                               bool edit, uint8_t* nxt, uint32_t* list,
                                               int* scan, long long* lbase_sh, FieldCtr* cq,
-                                              unsigned long long& nflag,
+                                              uint32_t* tlist, unsigned long long& nflag,
                                               unsigned long long& at_lb,
                                               unsigned long long& edits) {
   constexpr int kPer = 16;
@@ -404,15 +470,119 @@ __device__ __forceinline__ void apply_segment(const FieldDesc& d, int32_t w0, in
       const T gt = g[t];
       const T lb = lower_bound<T>(f[t], xi);
       const bool above = gt > lb;
-      if (above && edit) g[t] = halving_edit<T>(gt, lb);
+      if (d.prop) {
+        // targeted edit: the smallest proposal, never below the bound; the
+        // proposal slot is reset for the next round
+        using K = decltype(prop_key(gt));
+        K* slot = (K*)d.prop + t;
+        if (above && edit) {
+          const T pv = prop_value(*slot);
+          g[t] = pv > lb ? pv : lb;
+        }
+        *slot = ~K(0);
+      } else if (above && edit) {
+        g[t] = halving_edit<T>(gt, lb);
+      }
       edits += (above && edit) ? 1u : 0u;
       at_lb += above ? 0u : 1u;
       if (edit) {
         mark_box(d, box_of(d.geo, t), nxt);
-        if (lbase + j < d.list_cap) d.list[lbase + j] = (uint32_t)t;
+        if (lbase + j < d.list_cap) tlist[lbase + j] = (uint32_t)t;
       }
     }
     lds_barrier();
+  }
+}
+
+// Tile part of round E's detect: the block examines the active tiles among
+// first, first + G, first + 2G, ... (activity bytes of round parity E & 1,
+// read and cleared 256 at a time, one per thread, and the active ones
+// listed); SETS planes are in flight per tile march.
+template <class T, int SETS>
+__device__ void detect_tiles(const EngineArgs& a, TileLds<T>& sm, unsigned long long* red,
+                             uint16_t* s_tiles, int* s_scan, unsigned long long E,
+                             unsigned long long E0, int64_t first, unsigned G) {
+  const int tid = threadIdx.x;
+  const int p = (int)(E & 1);
+  const int q = (int)(E % 3);
+  EngineCtl* ctl = a.ctl;
+  unsigned long long acc_m = 0, acc_nf = 0, acc_nb = 0, acc_sw = 0;
+  int cur = -1, cached = -1, cached_kind = -1;
+  for (int64_t base = first; base < a.total_tiles; base += (int64_t)G * 256) {
+    const int64_t mine = base + (int64_t)tid * G;
+    int take = 0;
+    if (mine < a.total_tiles) {
+      const FieldDesc& d = a.fd[field_of_tile(a.fd, a.nf, mine)];
+      uint8_t* flag = d.act + p * tile_count(d.geo) + (mine - d.tile_base);
+      if (*flag) {
+        *flag = 0;
+        take = 1;
+      }
+    }
+    int n_act = 0;
+    const int pos = block_scan(take, s_scan, &n_act);
+    if (take) s_tiles[pos] = (uint16_t)tid;
+    __syncthreads();
+    for (int j = 0; j < n_act; ++j) {
+      const int64_t tt = base + (int64_t)s_tiles[j] * G;
+      const int fi = field_of_tile(a.fd, a.nf, tt);
+      if (fi != cached) {
+        const FieldIter s = state_at(a.fd[fi], E, E0);
+        cached = fi;
+        cached_kind = (s.done || sparse_items(a.fd[fi], s, E) >= 0) ? -1
+                    : s.started ? KIND_NEXT : KIND_FIRST_GIVEN;
+      }
+      const int kind = cached_kind;
+      if (kind < 0) continue;
+      const FieldDesc& d = a.fd[fi];
+      if (tid == 0 && fi != cur) {
+        if (cur >= 0) {
+          FieldCtr* c = &a.fd[cur].st->c[q];
+          if (acc_m) atomicAdd(&c->mism, acc_m);
+          if (acc_nf) atomicAdd(&c->bad_nf, acc_nf);
+          if (acc_nb) atomicAdd(&c->bad_b, acc_nb);
+          if (acc_sw) {
+            atomicAdd(&c->swept, acc_sw);
+            atomicAdd(&ctl->swept[q], acc_sw);
+          }
+        }
+        acc_m = acc_nf = acc_nb = acc_sw = 0;
+        cur = fi;
+      }
+      const int64_t tile = tt - d.tile_base;
+      const T* g = (const T*)d.g;
+      const T* f = (const T*)d.f;
+      const T xi = (T)d.xi_t;
+      TileCounts tc;
+      if (d.geo.ndim == 3) {
+        if (kind == KIND_NEXT)
+          tc = tile3<T, KIND_NEXT, SETS>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile, d.prop);
+        else
+          tc = tile3<T, KIND_FIRST_GIVEN, SETS>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile, d.prop);
+      } else {
+        if (kind == KIND_NEXT)
+          tc = tile2<T, KIND_NEXT, SETS>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile, d.prop);
+        else
+          tc = tile2<T, KIND_FIRST_GIVEN, SETS>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile, d.prop);
+      }
+      if (tid == 0) {
+        acc_m += unpack3(tc, 0);
+        acc_nf += unpack3(tc, 1);
+        acc_nb += unpack3(tc, 2);
+        acc_sw += (unsigned long long)tile_voxels(d.geo, tile);
+      }
+    }
+    __syncthreads();  // s_tiles is rewritten by the next batch
+  }
+  if (tid == 0 && cur >= 0) {
+    FieldCtr* c = &a.fd[cur].st->c[q];
+    if (acc_m) atomicAdd(&c->mism, acc_m);
+    if (acc_nf) atomicAdd(&c->bad_nf, acc_nf);
+    if (acc_nb) atomicAdd(&c->bad_b, acc_nb);
+    if (acc_sw) {
+      atomicAdd(&c->swept, acc_sw);
+      atomicAdd(&ctl->swept[q], acc_sw);
+    }
   }
 }
 
@@ -463,151 +633,68 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
       if (tid == 0) {
         ctl->edits[qn] = 0;
         ctl->swept[qn] = 0;
+        ctl->sparse[qn] = 0;
         ctl->flagged[qn] = 0;
       }
     }
 
     // ---- detect ------------------------------------------------------------
-    unsigned long long acc_m = 0, acc_nf = 0, acc_nb = 0, acc_sw = 0;
-    int cur = -1, cached = -1, cached_kind = -1;
-    // The block's tiles are base + j*G; their activity bytes are read and
-    // cleared 256 at a time, one per thread, and the active ones listed.
-    for (int64_t base = blockIdx.x; base < a.total_tiles; base += (int64_t)G * 256) {
-      const int64_t mine = base + (int64_t)tid * G;
-      int take = 0;
-      if (mine < a.total_tiles) {
-        const FieldDesc& d = a.fd[field_of_tile(a.fd, a.nf, mine)];
-        uint8_t* flag = d.act + p * tile_count(d.geo) + (mine - d.tile_base);
-        if (*flag) {
-          *flag = 0;
-          take = 1;
-        }
-      }
-      int n_act = 0;
-      const int pos = block_scan(take, s_scan, &n_act);
-      if (take) s_tiles[pos] = (uint16_t)tid;
-      __syncthreads();
-      for (int j = 0; j < n_act; ++j) {
-        const int64_t tt = base + (int64_t)s_tiles[j] * G;
-        const int fi = field_of_tile(a.fd, a.nf, tt);
-        if (fi != cached) {
-          const FieldIter s = state_at(a.fd[fi], E, E0);
-          cached = fi;
-          cached_kind = (s.done || sparse_items(a.fd[fi], s, E) >= 0) ? -1
-                      : s.started ? KIND_NEXT : KIND_FIRST_GIVEN;
-        }
-        const int kind = cached_kind;
-        if (kind < 0) continue;
-        const FieldDesc& d = a.fd[fi];
-        if (tid == 0 && fi != cur) {
-          if (cur >= 0) {
-            FieldCtr* c = &a.fd[cur].st->c[q];
-            if (acc_m) atomicAdd(&c->mism, acc_m);
-            if (acc_nf) atomicAdd(&c->bad_nf, acc_nf);
-            if (acc_nb) atomicAdd(&c->bad_b, acc_nb);
-            if (acc_sw) {
-              atomicAdd(&c->swept, acc_sw);
-              atomicAdd(&ctl->swept[q], acc_sw);
-            }
-          }
-          acc_m = acc_nf = acc_nb = acc_sw = 0;
-          cur = fi;
-        }
-        const int64_t tile = tt - d.tile_base;
-        const T* g = (const T*)d.g;
-        const T* f = (const T*)d.f;
-        const T xi = (T)d.xi_t;
-        TileCounts tc;
-        if (d.geo.ndim == 3) {
-          if (kind == KIND_NEXT)
-            tc = tile3<T, KIND_NEXT>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile);
-          else
-            tc = tile3<T, KIND_FIRST_GIVEN>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile);
-        } else {
-          if (kind == KIND_NEXT)
-            tc = tile2<T, KIND_NEXT>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile);
-          else
-            tc = tile2<T, KIND_FIRST_GIVEN>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile);
-        }
-        if (tid == 0) {
-          acc_m += unpack3(tc, 0);
-          acc_nf += unpack3(tc, 1);
-          acc_nb += unpack3(tc, 2);
-          acc_sw += (unsigned long long)tile_voxels(d.geo, tile);
-        }
-      }
-      __syncthreads();  // s_tiles is rewritten by the next batch
-    }
-    if (tid == 0 && cur >= 0) {
-      FieldCtr* c = &a.fd[cur].st->c[q];
-      if (acc_m) atomicAdd(&c->mism, acc_m);
-      if (acc_nf) atomicAdd(&c->bad_nf, acc_nf);
-      if (acc_nb) atomicAdd(&c->bad_b, acc_nb);
-      if (acc_sw) {
-        atomicAdd(&c->swept, acc_sw);
-        atomicAdd(&ctl->swept[q], acc_sw);
-      }
-    }
-    // Sparse rounds: the examinations of up to 256 fields at a time form one
-    // index space (prefix sums in LDS) that the grid strides over.
+    // Sparse rounds first: the examinations of up to 256 fields at a time form
+    // one index space (prefix sums in LDS) that the grid strides over.  The
+    // mismatch counts are only tested against zero in these rounds.
+    int any_tiles = 0;
     for (int f0 = 0; f0 < a.nf; f0 += 256) {
       const int fi = f0 + tid;
       long long items = 0;
+      int sweeps = 0;
       if (fi < a.nf) {
         const FieldDesc& d = a.fd[fi];
-        items = sparse_items(d, state_at(d, E, E0), E);
-        if (items < 0) items = 0;
+        const FieldIter s = state_at(d, E, E0);
+        items = sparse_items(d, s, E);
+        if (items < 0) {
+          sweeps = !s.done;
+          items = 0;
+        }
         if (items > 0 && blockIdx.x == 0) {
           FieldCtr* c = &d.st->c[q];
           atomicAdd(&c->swept, (unsigned long long)items);
           atomicAdd(&ctl->swept[q], (unsigned long long)items);
+          atomicAdd(&ctl->sparse[q], (unsigned long long)items);
         }
       }
-      s_pre[tid] = items;
-      __syncthreads();
-      for (int o = 1; o < 256; o <<= 1) {  // inclusive prefix sum
-        const long long v = tid >= o ? s_pre[tid - o] : 0;
-        __syncthreads();
-        s_pre[tid] += v;
-        __syncthreads();
-      }
-      const long long total = s_pre[255];
+      any_tiles |= __syncthreads_or(sweeps);
+      const long long total = block_prefix(items, s_pre);
       const int nfc = a.nf - f0 < 256 ? a.nf - f0 : 256;
-      // Mismatches are only tested against zero in these rounds: each thread
-      // keeps one count for its current field and a wave adds them with a
-      // single atomic when its lanes agree on the field, so the counter does
-      // not serialise thousands of atomics.
-      int pend_f = -1;
-      unsigned pend_n = 0;
+      FieldAcc mism;
+      auto mism_ptr = [&](int f) { return &a.fd[f].st->c[q].mism; };
       for (long long m = (long long)blockIdx.x * 256 + tid; m < total; m += (long long)G * 256) {
-        int lo = 0, hi = nfc - 1;  // first field whose inclusive sum exceeds m
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (s_pre[mid] > m) hi = mid; else lo = mid + 1;
-        }
-        const long long start = lo ? s_pre[lo - 1] : 0;
-        const int fi = f0 + lo;
-        if (fi != pend_f) {
-          if (pend_n) atomicAdd(&a.fd[pend_f].st->c[q].mism, (unsigned long long)pend_n);
-          pend_f = fi;
-          pend_n = 0;
-        }
-        pend_n += sparse_examine<T>(a.fd[fi], (uint32_t)(m - start));
+        const int lo = prefix_find(s_pre, nfc, m);
+        const int fx = f0 + lo;
+        const Exam ex = sparse_examine<T>(a.fd[fx], (uint32_t)(m - (lo ? s_pre[lo - 1] : 0)));
+        acc_add(mism, fx, ex.n, mism_ptr);
+        // fire-and-forget flags: the apply pass reads them after the barrier
+        const gptr<uint32_t> bm = as_global(a.fd[fx].bm);
+        if (ex.ta >= 0)
+          __hip_atomic_fetch_or(bm + (ex.ta >> 5), 1u << (ex.ta & 31), __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_AGENT);
+        if (ex.td >= 0)
+          __hip_atomic_fetch_or(bm + (ex.td >> 5), 1u << (ex.td & 31), __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_AGENT);
       }
-      const int f_lane0 = __shfl(pend_f, 0, 64);
-      if (__all(pend_f == f_lane0 || pend_n == 0)) {
-        const unsigned w = wave_sum(pend_n);
-        if ((tid & 63) == 0 && w) atomicAdd(&a.fd[f_lane0].st->c[q].mism, (unsigned long long)w);
-      } else if (pend_n) {
-        atomicAdd(&a.fd[pend_f].st->c[q].mism, (unsigned long long)pend_n);
-      }
+      acc_flush(mism, mism_ptr);
       __syncthreads();  // s_pre is rewritten by the next group
     }
+    // Tiles: skipped when every running field is in a sparse round (marks
+    // left from earlier rounds then only widen a later tile round).
+    if (any_tiles)
+      detect_tiles<T, sets_for<T, KIND_NEXT>()>(a, sm, red, s_tiles, s_scan, E, E0, blockIdx.x,
+                                                G);
     grid_sync(ctl, G, gen);
     if (engine_failed(ctl)) break;
     if (tracer && r < kTraceRounds) a.trace[kTraceSlots * r + 1] = wall_clock64();
 
     // ---- apply -------------------------------------------------------------
+    // One pass per 4096-word segment of each field's flag bitmap.
     for (int64_t sg = blockIdx.x; sg < a.total_segs; sg += G) {
       const int fi = field_of_seg(a.fd, a.nf, sg);
       const FieldDesc& d = a.fd[fi];
@@ -621,7 +708,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
       const int32_t w0 = (int32_t)((sg - d.seg_base) * kSegWords);
       const int32_t w1 = (w0 + kSegWords < d.words) ? w0 + (int32_t)kSegWords : (int32_t)d.words;
       unsigned long long nflag = 0, at_lb = 0, edits = 0;
-      apply_segment<T>(d, w0, w1, edit, nxt, s_list, s_scan, &s_lbase, cq, nflag, at_lb, edits);
+      apply_segment<T>(d, w0, w1, edit, nxt, s_list, s_scan, &s_lbase, cq, d.list, nflag,
+                       at_lb, edits);
       // a segment holds at most 128K vertices: the three counts pack into
       // 21-bit fields of one word for a single block reduction
       const unsigned long long tot =
@@ -645,6 +733,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
       t[3] = relaxed_load(&ctl->swept[q]);
       t[4] = relaxed_load(&ctl->flagged[q]);
       t[5] = relaxed_load(&ctl->edits[q]);
+      t[6] = relaxed_load(&ctl->sparse[q]);
     }
     const unsigned long long edited = relaxed_load(&ctl->edits[q]);
     ++E;
@@ -696,19 +785,21 @@ hipError_t engine_dirs(int dtype, const FieldDesc* fd, int nf, int64_t total_til
   return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void k_zero(uint32_t* p, int64_t words) {
+__global__ __launch_bounds__(256) void k_fill(uint32_t* p, int64_t words, uint32_t v) {
   const int64_t stride = (int64_t)gridDim.x * 256;
-  for (int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x; w < words; w += stride) p[w] = 0u;
+  for (int64_t w = (int64_t)blockIdx.x * 256 + threadIdx.x; w < words; w += stride) p[w] = v;
 }
 
-hipError_t engine_zero(void* p, size_t bytes, hipStream_t s) {
+hipError_t engine_fill(void* p, size_t bytes, uint32_t v, hipStream_t s) {
   const int64_t words = (int64_t)(bytes / 4);
   int64_t b = (words + 255) / 256;
   if (b < 1) b = 1;
   if (b > 4096) b = 4096;
-  hipLaunchKernelGGL(k_zero, dim3((unsigned)b), dim3(256), 0, s, (uint32_t*)p, words);
+  hipLaunchKernelGGL(k_fill, dim3((unsigned)b), dim3(256), 0, s, (uint32_t*)p, words, v);
   return hipGetLastError();
 }
+
+hipError_t engine_zero(void* p, size_t bytes, hipStream_t s) { return engine_fill(p, bytes, 0u, s); }
 
 // Cooperative grid: as many resident blocks as the chip holds, but no more
 // than there is work for (fewer arrivals make the barrier cheaper).

@@ -25,7 +25,7 @@ struct FieldIter {
 // to c[E%3], reads c[(E-1)%3], and clears c[(E+1)%3].
 struct FieldCtr {
   unsigned long long mism, nflag, at_lb, bad_nf, bad_b, swept;
-  unsigned long long nlist;  // targets appended to the field's target list
+  unsigned long long nlist;  // targets the apply pass appended to the target list
 };
 
 struct FieldState {
@@ -43,6 +43,8 @@ struct FieldDesc {
   uint8_t* act;       // per tile and round parity: examine in that round
                       // (act[p * tiles + tile])
   uint32_t* list;     // targets of the last apply pass (list_cap entries)
+  void* prop;         // targeted edit: per-vertex proposal keys; nullptr for
+                      // the halving edit
   TileGeo geo;
   double xi_t;        // xi in the field type, <= xi
   int64_t max_iters;
@@ -69,6 +71,7 @@ struct EngineCtl {
   unsigned long long rounds;    // rounds run by the last launch
   unsigned long long edits[3];  // value changes per round (mod 3), all fields
   unsigned long long swept[3];  // vertices examined per round (mod 3), all fields
+  unsigned long long sparse[3]; // of which by sparse examination
   unsigned long long flagged[3];  // flagged vertices per round (mod 3), all fields
   int error;                    // a grid barrier timed out
   int pad;
@@ -89,10 +92,10 @@ struct EngineArgs {
 // Round trace, for the first kTraceRounds rounds of a launch: block 0 stamps
 // the 100 MHz wall clock at the start of a round, after its detect barrier
 // and after its apply barrier, then copies the round's totals (vertices
-// examined, flagged vertices, edits); slot kTraceRounds*kTraceSlots holds the
-// launch start.
+// examined, flagged vertices, edits, sparse examinations); slot
+// kTraceRounds*kTraceSlots holds the launch start.
 constexpr int kTraceRounds = 64;
-constexpr int kTraceSlots = 6;
+constexpr int kTraceSlots = 7;
 constexpr size_t kTraceBytes = (kTraceRounds * kTraceSlots + 1) * 8;
 
 // Host side (engine.hip).
@@ -105,6 +108,8 @@ hipError_t engine_dirs(int dtype, const FieldDesc* fd, int nf, int64_t total_til
 // Zero `bytes` bytes (multiple of 4, 4-byte aligned) with a kernel, so that
 // the call can sit inside a captured graph.
 hipError_t engine_zero(void* p, size_t bytes, hipStream_t s);
+// Fill `bytes` bytes (multiple of 4, 4-byte aligned) with the 32-bit word v.
+hipError_t engine_fill(void* p, size_t bytes, uint32_t v, hipStream_t s);
 
 // Target list: when a round flags at most this many vertices, the next
 // round examines the Freudenthal neighbours of exactly those vertices

@@ -150,6 +150,35 @@ struct TileLds {
   uint32_t flags[kFlagWords];
 };
 
+// Targeted edit: a flag also proposes a value for its target, the highest
+// value at which the target no longer beats its rival in the (value, index)
+// order -- the rival's value when the target's index is the smaller (the tie
+// then goes to the rival), else the next value below it; zero is +0.  The
+// proposals for a target meet in prop[t] by atomic minimum over an
+// order-preserving unsigned key (unset = all ones).
+__device__ __forceinline__ uint32_t prop_key(float v) {
+  const uint32_t b = __float_as_uint(v);
+  return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ unsigned long long prop_key(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  return (b & 0x8000000000000000ull) ? ~b : (b | 0x8000000000000000ull);
+}
+__device__ __forceinline__ float prop_value(uint32_t k) {
+  return __uint_as_float((k & 0x80000000u) ? (k & 0x7fffffffu) : ~k);
+}
+__device__ __forceinline__ double prop_value(unsigned long long k) {
+  return __longlong_as_double(
+      (long long)((k & 0x8000000000000000ull) ? (k & 0x7fffffffffffffffull) : ~k));
+}
+template <class T>
+__device__ __forceinline__ void propose(void* prop, int32_t t, int32_t rival, T rv) {
+  T v = t < rival ? rv : next_down<T>(rv);
+  if (v == T(0)) v = T(0);  // +0
+  using K = decltype(prop_key(v));
+  __hip_atomic_fetch_min((K*)prop + t, prop_key(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Flag the targets of one vertex's mismatches (Sec. IV-A):
 //   ascending mismatch  -> the vertex that is now n_max (the spurious
 //                          maximum; the vertex itself for a false maximum);
@@ -173,18 +202,30 @@ __device__ __forceinline__ void flag_lds(uint32_t* flags, const FlagBox& fb, con
   atomicOr(flags + row * fb.words + ((gb >> 5) - first), 1u << (gb & 31));
 }
 
+// With prop set (targeted edit) each flag also proposes a value: the
+// ascending rival is n_max under f (value read from g), the descending rival
+// is the current n_min, whose value `lo` the stencil already holds.
+template <class T>
 __device__ __forceinline__ unsigned flag_targets3(int32_t X, int32_t Y, int32_t Z, int ca, int cd,
                                                   int fa, int fd, const FlagBox& fb,
-                                                  const TileGeo& G, uint32_t* flags) {
+                                                  const TileGeo& G, uint32_t* flags, void* prop,
+                                                  gptr<const T> g, T lo) {
   unsigned cnt = 0;
+  const int32_t v = X + G.nx * Y + G.sxy * Z;
   if (ca != fa) {
     const int m = ca & 7, sg = (ca & 8) ? -1 : 1;
     flag_lds(flags, fb, G, X + sg * (m & 1), Y + sg * ((m >> 1) & 1), Z + sg * ((m >> 2) & 1));
+    if (prop) {
+      const int32_t c = v + code_delta32(fa, G.nx, G.sxy);
+      propose<T>(prop, v + code_delta32(ca, G.nx, G.sxy), c, g[c]);
+    }
     ++cnt;
   }
   if (cd != fd) {
     const int m = fd & 7, sg = (fd & 8) ? -1 : 1;
     flag_lds(flags, fb, G, X + sg * (m & 1), Y + sg * ((m >> 1) & 1), Z + sg * ((m >> 2) & 1));
+    if (prop)
+      propose<T>(prop, v + code_delta32(fd, G.nx, G.sxy), v + code_delta32(cd, G.nx, G.sxy), lo);
     ++cnt;
   }
   return cnt;
@@ -250,10 +291,10 @@ __device__ __forceinline__ int bound_class(T a, T b, T xi) {
 // substitute NaN at commit), and the barriers order LDS only, so the wait
 // before each commit covers just the set being committed.  Two LDS buffers
 // with one barrier per step suffice: a step reads only its own plane.
-template <class T, int KIND>
+template <class T, int KIND, int SETS = sets_for<T, KIND>()>
 __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_in,
                             const T* f_in, uint8_t* dirs_in, uint32_t* bm_in, T xi,
-                            const TileGeo G, int64_t tile) {
+                            const TileGeo G, int64_t tile, void* prop = nullptr) {
   const gptr<const T> h = as_global(h_in);
   const gptr<const T> f = as_global(f_in);
   const gptr<uint8_t> dirs = as_global(dirs_in);
@@ -261,7 +302,7 @@ __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_
   constexpr int PER = (PLANE + 255) / 256;
   constexpr bool kReadDirs = (KIND == KIND_NEXT || KIND == KIND_FIRST_GIVEN);
   constexpr bool kGivenF = (KIND == KIND_FIRST_GIVEN);
-  constexpr int kSets = sets_for<T, KIND>();
+  constexpr int kSets = SETS;
   const int tid = threadIdx.x, tx = tid & (TX - 1), ty = tid / TX;
   const int32_t t32 = (int32_t)tile;
   const int32_t bx = t32 % G.tiles_x, by = (t32 / G.tiles_x) % G.tiles_y,
@@ -361,7 +402,7 @@ __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_
           nf += bc == 1;
           nb += bc == 2;
         }
-        mism += flag_targets3(X, Y, v, ca, cd, fa, fd, fbx, G, sm.flags);
+        mism += flag_targets3<T>(X, Y, v, ca, cd, fa, fd, fbx, G, sm.flags, prop, h, e.lo);
       }
     }
     gu = su;
@@ -396,10 +437,10 @@ __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_
 // One 2D tile (256-wide strip, `chunk` rows), marched along y like tile3:
 // step r stages row r, reduces the thread's upper pair (x..x+1) and lower
 // pair (x-1..x) and finishes vertex r-1.
-template <class T, int KIND>
+template <class T, int KIND, int SETS = sets_for<T, KIND>()>
 __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_in,
                             const T* f_in, uint8_t* dirs_in, uint32_t* bm_in, T xi,
-                            const TileGeo G, int64_t tile) {
+                            const TileGeo G, int64_t tile, void* prop = nullptr) {
   const gptr<const T> h = as_global(h_in);
   const gptr<const T> f = as_global(f_in);
   const gptr<uint8_t> dirs = as_global(dirs_in);
@@ -407,7 +448,7 @@ __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_
   constexpr int PER = (RW + 255) / 256;
   constexpr bool kReadDirs = (KIND == KIND_NEXT || KIND == KIND_FIRST_GIVEN);
   constexpr bool kGivenF = (KIND == KIND_FIRST_GIVEN);
-  constexpr int kSets = sets_for<T, KIND>();
+  constexpr int kSets = SETS;
   const int tid = threadIdx.x;
   const int32_t t32 = (int32_t)tile;
   const int32_t bx = t32 % G.tiles_x, by = t32 / G.tiles_x;
@@ -498,12 +539,20 @@ __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_
           nb += bc == 2;
         }
         // 2D codes only use the x and y bits; rows are indexed by y
+        const int32_t vi = X + G.nx * v;
         if (ca != fa) {
           flag2(v, ca);
+          if (prop) {
+            const int32_t c = vi + code_delta32(fa, G.nx, G.sxy);
+            propose<T>(prop, vi + code_delta32(ca, G.nx, G.sxy), c, h[c]);
+          }
           ++mism;
         }
         if (cd != fd) {
           flag2(v, fd);
+          if (prop)
+            propose<T>(prop, vi + code_delta32(fd, G.nx, G.sxy),
+                       vi + code_delta32(cd, G.nx, G.sxy), e.lo);
           ++mism;
         }
       }

@@ -41,8 +41,9 @@ def test_host_only_calls():
     g = pmsz.Grid(3, pmsz.F32, 512, 512, 512)
     n = pmsz.workspace_size(g, pmsz.WS_CORRECT)
     N = 512 ** 3
-    # bitmap (N/8) + direction bytes (N) + target list (4 bytes for N/256 + 1024
-    # entries) + a few bytes per tile of >= 2048 vertices + fixed control blocks
+    # bitmap (N/8) + direction bytes (N) + target list (4 bytes for N/256 +
+    # 1024 entries) + a few bytes per tile of >= 2048 vertices + fixed
+    # control blocks
     lst = 4 * (N // 256 + 1024)
     assert N + N // 8 + lst <= n <= N + N // 8 + lst + 12 * (N // 2048) + 65536
     with pytest.raises(pmsz.PmszError) as e:
