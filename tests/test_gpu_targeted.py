@@ -62,3 +62,23 @@ def test_unknown_mode_rejected():
     f = np.zeros((4, 4), np.float32)
     with pytest.raises(KeyError):
         pmsz.correct(dev(f), dev(f), 0.1, mode="bogus")
+
+
+def test_targeted_full_size_perlin_512():
+    """512^3 binary32 Perlin with the targeted edit: the corrected field and
+    statistics against the hash and counts the oracle wrote."""
+    import hashlib
+    import json
+    import os
+    import torch
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "perlin512_f32_targeted.json")
+    gold = json.load(open(path))
+    f, fhat, xi = synth.large_perlin_case(device="cuda:0")
+    sha = lambda t: hashlib.sha256(host(t).view(np.uint8)).hexdigest()  # noqa: E731
+    assert sha(fhat) == gold["sha256_fhat"], "input generator differs on this host"
+    g, st = pmsz.correct(f, fhat, xi, mode="targeted")
+    for k in STAT_KEYS:
+        assert st[k] == gold["stats"][k], (k, st, gold["stats"])
+    assert sha(g) == gold["sha256_g"]
+    assert int(torch.count_nonzero(g != fhat)) == gold["vertices_edited"]
