@@ -185,6 +185,20 @@ def bench_targeted(f, fhat, xi, steps, g_halving):
     rep_h = pmsz.verify(f, g_halving, fhat, xi)
     n = f.numel()
     ms_step = sum(ms) / len(ms)
+    # storage of the corrections: the edit stream of each result
+    raw = n * f.element_size()
+    storage = {}
+    for name, gg in (("halving", g_halving), ("targeted", g)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        stream, ne = pmsz.encode_edits(fhat, gg)
+        torch.cuda.synchronize()
+        t_enc = (time.perf_counter() - t0) * 1e3
+        back = pmsz.decode_edits(fhat, stream)
+        storage[name] = {"edits": ne, "bytes": stream.numel(),
+                         "bits_per_edit": round(8 * stream.numel() / max(ne, 1), 2),
+                         "fraction_of_raw_field": round(stream.numel() / raw, 6),
+                         "encode_ms": round(t_enc, 3), "lossless": bool(torch.equal(back, gg))}
     return {"ms_per_step": round(ms_step, 4), "gvox_s": round(n / ms_step / 1e6, 3),
             "status": st["status"], "iterations": st["iterations"],
             "edits": st["steps_applied"], "vertices_edited": rep_t["vertices_edited"],
@@ -193,7 +207,8 @@ def bench_targeted(f, fhat, xi, steps, g_halving):
             "halving_vertices_edited": rep_h["vertices_edited"],
             "halving_edit_ratio": round(rep_h["vertices_edited"] / n, 6),
             "halving_max_abs_err": rep_h["max_abs_err"],
-            "directions_restored": rep_t["asc_mismatch"] == 0 and rep_t["desc_mismatch"] == 0}
+            "directions_restored": rep_t["asc_mismatch"] == 0 and rep_t["desc_mismatch"] == 0,
+            "edit_storage": storage}
 
 
 def bench_serving(dev, rates, n_requests, pool_per_class, seed):

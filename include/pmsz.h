@@ -174,6 +174,36 @@ int pmsz_batched_workspace_size(int32_t n, const pmsz_field* fields, size_t* byt
 int pmsz_correct_batched(int32_t n, const pmsz_field* fields, void* ws, size_t ws_bytes,
                          int64_t max_iters, pmsz_stats* stats, void* stream);
 
+/* Edit stream: the corrections as stored next to the compressed field
+ * (Sec. V-D reports this storage as the method's overhead; the format is this
+ * library's).  Layout, little-endian:
+ *   header  "PMSE", u8 version 1, u8 dtype, u16 0, u64 vertices, u64 edits,
+ *           u64 payload bytes, u32 chunk (4096), u32 chunks   (40 bytes)
+ *   table   per chunk of 4096 entries: u64 payload offset of its first entry,
+ *           u64 index of the edited vertex before it (all ones when none)
+ *   payload per vertex i whose bits differ between fhat and g, ascending:
+ *           gap = i - previous edited index - 1, then steps = the number of
+ *           representable values in (g_i, fhat_i], each an unsigned LEB128
+ *           varint.
+ * pmsz_edits_workspace_size: device workspace for encoding up to max_edits
+ * edits.  pmsz_edits_max_bytes: stream capacity that any n_edits edits fit.
+ * pmsz_encode_edits: fhat, g: device fields of `grid`; out: device, 8-byte
+ * aligned, out_cap bytes.  Sets *n_edits and *n_bytes (stream length); with
+ * more than max_edits edits returns PMSZ_ERR_OOM with *n_edits set and writes
+ * nothing; likewise when the stream exceeds out_cap (*n_bytes set).
+ * Synchronises.  pmsz_decode_edits: g holds fhat on entry and the corrected
+ * field on return; in: device stream of n_bytes bytes, 8-byte aligned; ws: 256
+ * device bytes, 256-byte aligned.  A stream of another grid or type, or a
+ * malformed payload, returns PMSZ_ERR_INVALID_ARG (with a malformed payload g
+ * may be partly written).  Synchronises. */
+int pmsz_edits_workspace_size(const pmsz_grid* grid, int64_t max_edits, size_t* bytes);
+int pmsz_edits_max_bytes(int64_t n_edits, size_t* bytes);
+int pmsz_encode_edits(const pmsz_grid* grid, const void* fhat, const void* g, int64_t max_edits,
+                      void* ws, size_t ws_bytes, uint8_t* out, size_t out_cap, int64_t* n_edits,
+                      int64_t* n_bytes, void* stream);
+int pmsz_decode_edits(const pmsz_grid* grid, const uint8_t* in, size_t n_bytes, void* g,
+                      void* ws, size_t ws_bytes, void* stream);
+
 /* Segmentation labels (Sec. III-A: integral lines end at an extremum; the
  * ascending / descending segmentation groups vertices by that extremum).
  * dirs: device direction bytes.  max_label / min_label: device int32 arrays of

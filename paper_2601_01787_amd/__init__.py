@@ -25,13 +25,15 @@ STATUS = {0: "OK", 1: "INVALID_ARG", 2: "NONFINITE", 3: "INPUT_BOUND", 4: "NOT_C
           5: "STALLED", 6: "OOM", 7: "DEVICE"}
 DEFAULT_MAX_ITERS = 1 << 40
 
+# the last two return strings, the others a status code
 EXPORTS = ("pmsz_workspace_size", "pmsz_directions", "pmsz_correct",
            "pmsz_batched_workspace_size", "pmsz_correct_batched", "pmsz_labels",
-           "pmsz_correct_mode", "pmsz_verify", "pmsz_last_timing", "pmsz_last_rounds", "pmsz_session_workspace_size",
-           "pmsz_field_workspace_size", "pmsz_session_create", "pmsz_session_add",
-           "pmsz_session_step", "pmsz_session_sync", "pmsz_session_result",
-           "pmsz_session_remove", "pmsz_session_destroy", "pmsz_status_string",
-           "pmsz_last_error")
+           "pmsz_correct_mode", "pmsz_verify", "pmsz_last_timing", "pmsz_last_rounds",
+           "pmsz_session_workspace_size", "pmsz_field_workspace_size", "pmsz_session_create",
+           "pmsz_session_add", "pmsz_session_step", "pmsz_session_sync", "pmsz_session_result",
+           "pmsz_session_remove", "pmsz_session_destroy", "pmsz_edits_workspace_size",
+           "pmsz_edits_max_bytes", "pmsz_encode_edits", "pmsz_decode_edits",
+           "pmsz_status_string", "pmsz_last_error")
 
 
 class PmszError(RuntimeError):
@@ -120,6 +122,11 @@ def load():
     L.pmsz_labels.argtypes = [G, vp, vp, vp, vp, sz, vp]
     L.pmsz_verify.argtypes = [G, vp, vp, vp, dbl, vp, sz, ctypes.POINTER(Report), vp]
     L.pmsz_last_timing.argtypes = [ctypes.POINTER(Timing)]
+    L.pmsz_edits_workspace_size.argtypes = [G, i64, ctypes.POINTER(sz)]
+    L.pmsz_edits_max_bytes.argtypes = [i64, ctypes.POINTER(sz)]
+    L.pmsz_encode_edits.argtypes = [G, vp, vp, i64, vp, sz, vp, sz, ctypes.POINTER(i64),
+                                    ctypes.POINTER(i64), vp]
+    L.pmsz_decode_edits.argtypes = [G, vp, sz, vp, vp, sz, vp]
     L.pmsz_last_rounds.argtypes = [ctypes.POINTER(Round), ctypes.c_int64,
                                    ctypes.POINTER(ctypes.c_int64)]
     L.pmsz_session_workspace_size.argtypes = [i32, ctypes.POINTER(sz)]
@@ -371,3 +378,50 @@ def verify(f, g, fhat, xi):
                                  float(xi), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
                                  ctypes.byref(rep), _stream(f)))
     return rep.as_dict()
+
+
+def encode_edits(fhat, g, *, max_edits=None):
+    """Edit stream of a corrected field g against fhat (uint8 tensor on the
+    same device; format in pmsz.h).  max_edits bounds the workspace (default:
+    every vertex)."""
+    _dev(fhat, "fhat")
+    _dev(g, "g")
+    if fhat.shape != g.shape or fhat.dtype != g.dtype:
+        raise ValueError("fhat and g must match")
+    grid = grid_of(g)
+    cap = g.numel() if max_edits is None else int(max_edits)
+    need = ctypes.c_size_t()
+    _raise_if(load().pmsz_edits_workspace_size(ctypes.byref(grid), cap, ctypes.byref(need)))
+    ws = torch.empty(need.value + 256, dtype=torch.uint8, device=g.device)
+    off = (-ws.data_ptr()) % 256
+    ws = ws[off:off + need.value]
+    outcap = ctypes.c_size_t()
+    _raise_if(load().pmsz_edits_max_bytes(cap, ctypes.byref(outcap)))
+    out = torch.empty(outcap.value + 8, dtype=torch.uint8, device=g.device)
+    o8 = (-out.data_ptr()) % 8
+    out = out[o8:o8 + outcap.value]
+    ne, nb = ctypes.c_int64(), ctypes.c_int64()
+    _raise_if(load().pmsz_encode_edits(ctypes.byref(grid), ctypes.c_void_p(fhat.data_ptr()),
+                                       ctypes.c_void_p(g.data_ptr()), cap,
+                                       ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                       ctypes.c_void_p(out.data_ptr()), out.numel(),
+                                       ctypes.byref(ne), ctypes.byref(nb), _stream(g)))
+    return out[:nb.value], ne.value
+
+
+def decode_edits(fhat, stream):
+    """The corrected field from fhat and an edit stream (device uint8 tensor)."""
+    _dev(fhat, "fhat")
+    _dev(stream, "stream")
+    g = fhat.clone()
+    grid = grid_of(g)
+    s = stream
+    if s.data_ptr() % 8:
+        s = s.clone()
+    ws = torch.empty(512, dtype=torch.uint8, device=g.device)
+    off = (-ws.data_ptr()) % 256
+    ws = ws[off:off + 256]
+    _raise_if(load().pmsz_decode_edits(ctypes.byref(grid), ctypes.c_void_p(s.data_ptr()),
+                                       s.numel(), ctypes.c_void_p(g.data_ptr()),
+                                       ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(g)))
+    return g

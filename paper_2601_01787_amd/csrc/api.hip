@@ -476,6 +476,87 @@ int pmsz_correct_mode(const pmsz_grid* grid, const void* f, void* g, double xi,
   return run_batch(grid->dtype, P, given, ws, stats, (hipStream_t)stream);
 }
 
+int pmsz_edits_workspace_size(const pmsz_grid* grid, int64_t max_edits, size_t* bytes) {
+  int r = check_grid(grid);
+  if (r) return r;
+  if (!bytes) return fail(PMSZ_ERR_INVALID_ARG, "bytes is NULL");
+  if (max_edits < 0) return fail(PMSZ_ERR_INVALID_ARG, "max_edits must be >= 0");
+  const Geo G = make_geo(*grid);
+  *bytes = edits_workspace_bytes(G.n, max_edits < G.n ? max_edits : G.n);
+  return PMSZ_OK;
+}
+
+int pmsz_edits_max_bytes(int64_t n_edits, size_t* bytes) {
+  if (!bytes || n_edits < 0) return fail(PMSZ_ERR_INVALID_ARG, "bad argument");
+  *bytes = edits_stream_bytes(n_edits);
+  return PMSZ_OK;
+}
+
+int pmsz_encode_edits(const pmsz_grid* grid, const void* fhat, const void* g, int64_t max_edits,
+                      void* ws, size_t ws_bytes, uint8_t* out, size_t out_cap, int64_t* n_edits,
+                      int64_t* n_bytes, void* stream) {
+  int r = check_grid(grid);
+  if (r) return r;
+  if (!fhat || !g || !ws || !out || !n_edits || !n_bytes)
+    return fail(PMSZ_ERR_INVALID_ARG, "NULL argument");
+  if (max_edits < 0) return fail(PMSZ_ERR_INVALID_ARG, "max_edits must be >= 0");
+  if ((uintptr_t)ws % kAlign || (uintptr_t)out % 8)
+    return fail(PMSZ_ERR_INVALID_ARG, "workspace must be 256-byte and out 8-byte aligned");
+  const Geo G = make_geo(*grid);
+  const int64_t cap = max_edits < G.n ? max_edits : G.n;
+  const size_t need = edits_workspace_bytes(G.n, cap);
+  if (ws_bytes < need) return fail(PMSZ_ERR_OOM, "workspace %zu bytes, need %zu", ws_bytes, need);
+  *n_edits = *n_bytes = 0;
+  hipError_t he = hipSuccess;
+  const int res = edits_encode(grid->dtype, fhat, g, G.n, cap, ws, out, out_cap, n_edits, n_bytes,
+                               &he, (hipStream_t)stream);
+  if (res < 0) return fail(PMSZ_ERR_DEVICE, "edit encoding: %s", hipGetErrorString(he));
+  if (res == 1)
+    return fail(PMSZ_ERR_OOM, "%lld edits exceed max_edits %lld", (long long)*n_edits,
+                (long long)cap);
+  if (res == 2)
+    return fail(PMSZ_ERR_OOM, "stream needs %lld bytes, out holds %zu", (long long)*n_bytes,
+                out_cap);
+  return PMSZ_OK;
+}
+
+int pmsz_decode_edits(const pmsz_grid* grid, const uint8_t* in, size_t n_bytes, void* g,
+                      void* ws, size_t ws_bytes, void* stream) {
+  int r = check_grid(grid);
+  if (r) return r;
+  if (!in || !g || !ws) return fail(PMSZ_ERR_INVALID_ARG, "NULL argument");
+  if (ws_bytes < kAlign || (uintptr_t)ws % kAlign || (uintptr_t)in % 8)
+    return fail(PMSZ_ERR_INVALID_ARG, "need a 256-byte aligned workspace of 256 bytes and an "
+                                      "8-byte aligned stream");
+  if (n_bytes < 40) return fail(PMSZ_ERR_INVALID_ARG, "stream shorter than its header");
+  hipStream_t s = (hipStream_t)stream;
+  unsigned char h[40];
+  HIP_TRY(hipMemcpyAsync(h, in, 40, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  unsigned long long nv, ne, nb;
+  uint32_t chunk, chunks;
+  memcpy(&nv, h + 8, 8);
+  memcpy(&ne, h + 16, 8);
+  memcpy(&nb, h + 24, 8);
+  memcpy(&chunk, h + 32, 4);
+  memcpy(&chunks, h + 36, 4);
+  const Geo G = make_geo(*grid);
+  const int dt = grid->dtype == PMSZ_F64 ? 1 : 0;
+  if (memcmp(h, "PMSE", 4) || h[4] != 1 || h[5] != dt || nv != (unsigned long long)G.n ||
+      chunk != 4096 || chunks != (ne + 4095) / 4096 || ne > nv ||
+      40 + 16 * (unsigned long long)chunks + nb > n_bytes)
+    return fail(PMSZ_ERR_INVALID_ARG, "not an edit stream of this grid and type");
+  int* err = (int*)ws;
+  HIP_TRY(engine_zero(err, 256, s));
+  HIP_TRY(edits_decode(grid->dtype, in + 40, in + 40 + 16 * (size_t)chunks, (int64_t)nb,
+                       (int64_t)ne, G.n, g, err, s));
+  int herr = 0;
+  HIP_TRY(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (herr) return fail(PMSZ_ERR_INVALID_ARG, "malformed edit stream payload");
+  return PMSZ_OK;
+}
+
 int pmsz_labels(const pmsz_grid* grid, const uint8_t* dirs, int32_t* max_label,
                 int32_t* min_label, void* ws, size_t ws_bytes, void* stream) {
   int r = check_grid(grid);

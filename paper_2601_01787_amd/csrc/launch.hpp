@@ -44,4 +44,14 @@ hipError_t launch_verify(int dtype, const void* f, const void* g, const void* fh
                          const int32_t* lf_min, const int32_t* lg_max, const int32_t* lg_min,
                          VerifyCounts* out, hipStream_t s);
 
+// edits.hip
+size_t edits_workspace_bytes(int64_t n, int64_t cap);
+size_t edits_stream_bytes(int64_t ne);
+int edits_encode(int dtype, const void* fhat, const void* g, int64_t n, int64_t cap, void* ws,
+                 uint8_t* out, size_t out_cap, int64_t* ne, int64_t* nbytes, hipError_t* herr,
+                 hipStream_t s);
+hipError_t edits_decode(int dtype, const uint8_t* table, const uint8_t* payload,
+                        int64_t payload_bytes, int64_t ne, int64_t n, void* g, int* err,
+                        hipStream_t s);
+
 }  // namespace pmsz
