@@ -47,6 +47,12 @@ __device__ __forceinline__ unsigned relaxed_load(const unsigned* p) {
 __device__ __forceinline__ unsigned long long relaxed_load(const unsigned long long* p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ unsigned long long relaxed_load(gptr<const unsigned long long> p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void relaxed_add(gptr<unsigned long long> p, unsigned long long v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
 
 __device__ __forceinline__ void grid_sync(EngineCtl* ctl, unsigned nblocks, unsigned& gen) {
   __syncthreads();
@@ -142,8 +148,40 @@ __device__ __forceinline__ FieldIter next_state(FieldIter s, const FieldCtr& c,
   return s;
 }
 
+// Whole-struct copies through global-space pointers, member by member (the
+// implicit copy operations take generic references).
+__device__ __forceinline__ FieldIter load_iter(gptr<const FieldIter> p) {
+  FieldIter r;
+  r.k = p->k;
+  r.steps = p->steps;
+  r.mism0 = p->mism0;
+  r.flagged_final = p->flagged_final;
+  r.stalled_final = p->stalled_final;
+  r.swept = p->swept;
+  r.status = p->status;
+  r.done = p->done;
+  r.started = p->started;
+  r.pad = p->pad;
+  return r;
+}
+__device__ __forceinline__ void store_iter(gptr<FieldIter> p, const FieldIter& s) {
+  p->k = s.k;
+  p->steps = s.steps;
+  p->mism0 = s.mism0;
+  p->flagged_final = s.flagged_final;
+  p->stalled_final = s.stalled_final;
+  p->swept = s.swept;
+  p->status = s.status;
+  p->done = s.done;
+  p->started = s.started;
+  p->pad = s.pad;
+}
+__device__ __forceinline__ void clear_ctr(gptr<FieldCtr> c) {
+  c->mism = c->nflag = c->at_lb = c->bad_nf = c->bad_b = c->swept = c->nlist = 0;
+}
+
 // Counters of a finished round (read after the barrier that completed them).
-__device__ __forceinline__ FieldCtr load_ctr(const FieldCtr* c) {
+__device__ __forceinline__ FieldCtr load_ctr(gptr<const FieldCtr> c) {
   FieldCtr r;
   r.mism = relaxed_load(&c->mism);
   r.nflag = relaxed_load(&c->nflag);
@@ -157,9 +195,9 @@ __device__ __forceinline__ FieldCtr load_ctr(const FieldCtr* c) {
 // State of a field at the start of round E.
 __device__ __forceinline__ FieldIter state_at(const FieldDesc& d, unsigned long long E,
                                               unsigned long long E0) {
-  const FieldState& st = *d.st;
-  if (E == E0) return st.s[E & 1];
-  return next_state(st.s[(E - 1) & 1], load_ctr(&st.c[(E - 1) % 3]), d.max_iters);
+  const gptr<const FieldState> st = as_global((const FieldState*)d.st);
+  if (E == E0) return load_iter(&st->s[E & 1]);
+  return next_state(load_iter(&st->s[(E - 1) & 1]), load_ctr(&st->c[(E - 1) % 3]), d.max_iters);
 }
 
 // Tiles containing a vertex within one step of target t (Freudenthal
@@ -187,7 +225,7 @@ __device__ __forceinline__ TileBox box_of(const TileGeo& G, int32_t t) {
 
 // Plain byte stores into the field's activity bytes of the next round: every
 // writer stores the same value.
-__device__ __forceinline__ void mark_box(const FieldDesc& d, const TileBox& b, uint8_t* nxt) {
+__device__ __forceinline__ void mark_box(const FieldDesc& d, const TileBox& b, gptr<uint8_t> nxt) {
   for (int32_t bz = b.z0; bz <= b.z1; ++bz)
     for (int32_t by = b.y0; by <= b.y1; ++by)
       for (int32_t bx = b.x0; bx <= b.x1; ++bx) {
@@ -234,7 +272,7 @@ __device__ __forceinline__ int block_scan(int v, int* sh, int* total) {
 __device__ __forceinline__ long long sparse_items(const FieldDesc& d, const FieldIter& s,
                                                   unsigned long long E) {
   if (!s.started || s.done) return -1;
-  const unsigned long long n = relaxed_load(&d.st->c[(E + 2) % 3].nlist);
+  const unsigned long long n = relaxed_load(&as_global((const FieldState*)d.st)->c[(E + 2) % 3].nlist);
   if (n > (unsigned long long)d.list_cap) return -1;
   return (long long)n * (d.geo.ndim == 3 ? 15 : 7);
 }
@@ -364,7 +402,7 @@ struct FieldAcc {
 template <class Ptr>
 __device__ __forceinline__ void acc_add(FieldAcc& acc, int fi, unsigned long long v, Ptr ptr) {
   if (fi != acc.f) {
-    if (acc.n) atomicAdd(ptr(acc.f), acc.n);
+    if (acc.n) relaxed_add(ptr(acc.f), acc.n);
     acc.f = fi;
     acc.n = 0;
   }
@@ -375,9 +413,9 @@ __device__ __forceinline__ void acc_flush(FieldAcc& acc, Ptr ptr) {  // whole wa
   const int f0 = __shfl(acc.f, 0, 64);
   if (__all(acc.f == f0 || acc.n == 0)) {
     const unsigned long long w = wave_sum(acc.n);
-    if ((threadIdx.x & 63) == 0 && w) atomicAdd(ptr(f0), w);
+    if ((threadIdx.x & 63) == 0 && w) relaxed_add(ptr(f0), w);
   } else if (acc.n) {
-    atomicAdd(ptr(acc.f), acc.n);
+    relaxed_add(ptr(acc.f), acc.n);
   }
   acc.f = -1;
   acc.n = 0;
@@ -414,9 +452,9 @@ constexpr int kApplyCap = 2048;   // targets per compaction pass
 // LDS list, and edits the listed targets with all threads at once.
 template <class T>
 __device__ __forceinline__ void apply_segment(const FieldDesc& d, int32_t w0, int32_t w1,
-                                              bool edit, uint8_t* nxt, uint32_t* list,
-                                              int* scan, long long* lbase_sh, FieldCtr* cq,
-                                              uint32_t* tlist, unsigned long long& nflag,
+                                              bool edit, gptr<uint8_t> nxt, uint32_t* list,
+                                              int* scan, long long* lbase_sh, gptr<FieldCtr> cq,
+                                              gptr<uint32_t> tlist, unsigned long long& nflag,
                                               unsigned long long& at_lb,
                                               unsigned long long& edits) {
   constexpr int kPer = 16;
@@ -439,8 +477,8 @@ __device__ __forceinline__ void apply_segment(const FieldDesc& d, int32_t w0, in
   nflag += (unsigned)cnt;
   int total = 0;
   const int off = block_scan(cnt, scan, &total);
-  const T* f = (const T*)d.f;
-  T* g = (T*)d.g;
+  const gptr<const T> f = as_global((const T*)d.f);
+  const gptr<T> g = as_global((T*)d.g);
   const T xi = (T)d.xi_t;
   for (int base = 0; base < total; base += kApplyCap) {
     int o = off;
@@ -462,7 +500,8 @@ __device__ __forceinline__ void apply_segment(const FieldDesc& d, int32_t w0, in
     // examination); entries past the capacity are dropped, and the count
     // then sends the next round to a tile sweep
     if (edit && tid == 0)
-      *lbase_sh = (long long)atomicAdd(&cq->nlist, (unsigned long long)n);
+      *lbase_sh = (long long)__hip_atomic_fetch_add(&cq->nlist, (unsigned long long)n,
+                                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     lds_barrier();
     const long long lbase = edit ? *lbase_sh : 0;
     for (int j = tid; j < n; j += 256) {
@@ -474,7 +513,7 @@ __device__ __forceinline__ void apply_segment(const FieldDesc& d, int32_t w0, in
         // targeted edit: the smallest proposal, never below the bound; the
         // proposal slot is reset for the next round
         using K = decltype(prop_key(gt));
-        K* slot = (K*)d.prop + t;
+        const gptr<K> slot = (gptr<K>)d.prop + t;
         if (above && edit) {
           const T pv = prop_value(*slot);
           g[t] = pv > lb ? pv : lb;
@@ -498,6 +537,19 @@ __device__ __forceinline__ void apply_segment(const FieldDesc& d, int32_t w0, in
 // first, first + G, first + 2G, ... (activity bytes of round parity E & 1,
 // read and cleared 256 at a time, one per thread, and the active ones
 // listed); SETS planes are in flight per tile march.
+// A block's detect counts for one field, added once per field change.
+__device__ __forceinline__ void flush_counts(gptr<FieldCtr> c, unsigned long long m,
+                                             unsigned long long nf, unsigned long long nb,
+                                             unsigned long long sw, unsigned long long* all_sw) {
+  if (m) relaxed_add(&c->mism, m);
+  if (nf) relaxed_add(&c->bad_nf, nf);
+  if (nb) relaxed_add(&c->bad_b, nb);
+  if (sw) {
+    relaxed_add(&c->swept, sw);
+    atomicAdd(all_sw, sw);
+  }
+}
+
 template <class T, int SETS>
 __device__ void detect_tiles(const EngineArgs& a, TileLds<T>& sm, unsigned long long* red,
                              uint16_t* s_tiles, int* s_scan, unsigned long long E,
@@ -513,7 +565,7 @@ __device__ void detect_tiles(const EngineArgs& a, TileLds<T>& sm, unsigned long 
     int take = 0;
     if (mine < a.total_tiles) {
       const FieldDesc& d = a.fd[field_of_tile(a.fd, a.nf, mine)];
-      uint8_t* flag = d.act + p * tile_count(d.geo) + (mine - d.tile_base);
+      const gptr<uint8_t> flag = as_global(d.act) + p * tile_count(d.geo) + (mine - d.tile_base);
       if (*flag) {
         *flag = 0;
         take = 1;
@@ -537,14 +589,8 @@ __device__ void detect_tiles(const EngineArgs& a, TileLds<T>& sm, unsigned long 
       const FieldDesc& d = a.fd[fi];
       if (tid == 0 && fi != cur) {
         if (cur >= 0) {
-          FieldCtr* c = &a.fd[cur].st->c[q];
-          if (acc_m) atomicAdd(&c->mism, acc_m);
-          if (acc_nf) atomicAdd(&c->bad_nf, acc_nf);
-          if (acc_nb) atomicAdd(&c->bad_b, acc_nb);
-          if (acc_sw) {
-            atomicAdd(&c->swept, acc_sw);
-            atomicAdd(&ctl->swept[q], acc_sw);
-          }
+          flush_counts(&as_global(a.fd[cur].st)->c[q], acc_m, acc_nf, acc_nb, acc_sw,
+                       &ctl->swept[q]);
         }
         acc_m = acc_nf = acc_nb = acc_sw = 0;
         cur = fi;
@@ -575,14 +621,7 @@ __device__ void detect_tiles(const EngineArgs& a, TileLds<T>& sm, unsigned long 
     __syncthreads();  // s_tiles is rewritten by the next batch
   }
   if (tid == 0 && cur >= 0) {
-    FieldCtr* c = &a.fd[cur].st->c[q];
-    if (acc_m) atomicAdd(&c->mism, acc_m);
-    if (acc_nf) atomicAdd(&c->bad_nf, acc_nf);
-    if (acc_nb) atomicAdd(&c->bad_b, acc_nb);
-    if (acc_sw) {
-      atomicAdd(&c->swept, acc_sw);
-      atomicAdd(&ctl->swept[q], acc_sw);
-    }
+    flush_counts(&as_global(a.fd[cur].st)->c[q], acc_m, acc_nf, acc_nb, acc_sw, &ctl->swept[q]);
   }
 }
 
@@ -610,9 +649,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
   if (a.has_fresh) {
     for (int64_t tt = (int64_t)blockIdx.x * 256 + tid; tt < a.total_tiles; tt += (int64_t)G * 256) {
       const FieldDesc& d = a.fd[field_of_tile(a.fd, a.nf, tt)];
-      const FieldIter& s = d.st->s[E0 & 1];
+      const FieldIter s = load_iter(&as_global(d.st)->s[E0 & 1]);
       if (!s.started && !s.done)
-        d.act[(E0 & 1) * tile_count(d.geo) + (tt - d.tile_base)] = 1;
+        as_global(d.act)[(E0 & 1) * tile_count(d.geo) + (tt - d.tile_base)] = 1;
     }
     grid_sync(ctl, G, gen);
   }
@@ -627,8 +666,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     if (blockIdx.x == 0) {
       for (int fi = tid; fi < a.nf; fi += 256) {
         const FieldDesc& d = a.fd[fi];
-        if (E > E0) d.st->s[p] = state_at(d, E, E0);
-        d.st->c[qn] = FieldCtr{0, 0, 0, 0, 0, 0};
+        const gptr<FieldState> st = as_global(d.st);
+        if (E > E0) store_iter(&st->s[p], state_at(d, E, E0));
+        clear_ctr(&st->c[qn]);
       }
       if (tid == 0) {
         ctl->edits[qn] = 0;
@@ -656,8 +696,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
           items = 0;
         }
         if (items > 0 && blockIdx.x == 0) {
-          FieldCtr* c = &d.st->c[q];
-          atomicAdd(&c->swept, (unsigned long long)items);
+          relaxed_add(&as_global(d.st)->c[q].swept, (unsigned long long)items);
           atomicAdd(&ctl->swept[q], (unsigned long long)items);
           atomicAdd(&ctl->sparse[q], (unsigned long long)items);
         }
@@ -666,7 +705,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
       const long long total = block_prefix(items, s_pre);
       const int nfc = a.nf - f0 < 256 ? a.nf - f0 : 256;
       FieldAcc mism;
-      auto mism_ptr = [&](int f) { return &a.fd[f].st->c[q].mism; };
+      auto mism_ptr = [&](int f) { return &as_global(a.fd[f].st)->c[q].mism; };
       for (long long m = (long long)blockIdx.x * 256 + tid; m < total; m += (long long)G * 256) {
         const int lo = prefix_find(s_pre, nfc, m);
         const int fx = f0 + lo;
@@ -698,9 +737,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     for (int64_t sg = blockIdx.x; sg < a.total_segs; sg += G) {
       const int fi = field_of_seg(a.fd, a.nf, sg);
       const FieldDesc& d = a.fd[fi];
-      const FieldIter s = d.st->s[p];  // persisted by block 0 before the barrier
-      FieldCtr* cq = &d.st->c[q];
-      uint8_t* nxt = d.act + (p ^ 1) * tile_count(d.geo);
+      const FieldIter s = load_iter(&as_global(d.st)->s[p]);  // persisted by block 0 before the barrier
+      const gptr<FieldCtr> cq = &as_global(d.st)->c[q];
+      const gptr<uint8_t> nxt = as_global(d.act) + (p ^ 1) * tile_count(d.geo);
       const unsigned long long mism = relaxed_load(&cq->mism);
       const bool bad = !s.started && (relaxed_load(&cq->bad_nf) || relaxed_load(&cq->bad_b));
       if (s.done || bad || mism == 0) continue;
@@ -708,7 +747,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
       const int32_t w0 = (int32_t)((sg - d.seg_base) * kSegWords);
       const int32_t w1 = (w0 + kSegWords < d.words) ? w0 + (int32_t)kSegWords : (int32_t)d.words;
       unsigned long long nflag = 0, at_lb = 0, edits = 0;
-      apply_segment<T>(d, w0, w1, edit, nxt, s_list, s_scan, &s_lbase, cq, d.list, nflag,
+      apply_segment<T>(d, w0, w1, edit, nxt, s_list, s_scan, &s_lbase, cq, as_global(d.list), nflag,
                        at_lb, edits);
       // a segment holds at most 128K vertices: the three counts pack into
       // 21-bit fields of one word for a single block reduction
@@ -718,10 +757,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
         const unsigned long long nf_ = unpack3(tot, 0), al_ = unpack3(tot, 1),
                                  ed_ = unpack3(tot, 2);
         if (nf_) {
-          atomicAdd(&cq->nflag, nf_);
+          relaxed_add(&cq->nflag, nf_);
           atomicAdd(&ctl->flagged[q], nf_);
         }
-        if (al_) atomicAdd(&cq->at_lb, al_);
+        if (al_) relaxed_add(&cq->at_lb, al_);
         if (ed_) atomicAdd(&ctl->edits[q], ed_);
       }
     }
@@ -744,7 +783,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     for (int fi = tid; fi < a.nf; fi += 256) {
       const FieldDesc& d = a.fd[fi];
       const FieldIter s = state_at(d, E, E0);
-      if (E > E0) d.st->s[E & 1] = s;
+      if (E > E0) store_iter(&as_global(d.st)->s[E & 1], s);
       if (a.out) a.out[fi] = s;
     }
     if (tid == 0) {

@@ -176,7 +176,8 @@ __device__ __forceinline__ void propose(void* prop, int32_t t, int32_t rival, T 
   T v = t < rival ? rv : next_down<T>(rv);
   if (v == T(0)) v = T(0);  // +0
   using K = decltype(prop_key(v));
-  __hip_atomic_fetch_min((K*)prop + t, prop_key(v), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __hip_atomic_fetch_min((gptr<K>)prop + t, prop_key(v), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Flag the targets of one vertex's mismatches (Sec. IV-A):
