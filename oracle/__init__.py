@@ -69,13 +69,15 @@ def lib():
         L.orc_correct.argtypes = grid + [i32, vp, vp, dbl, vp, i64, ctypes.POINTER(Stats)]
         L.orc_correct_mode.argtypes = grid + [i32, vp, vp, dbl, vp, i64, i32,
                                               ctypes.POINTER(Stats)]
+        L.orc_correct_core.argtypes = grid + [i32, vp, vp, dbl, vp, i64, i32, vp,
+                                              ctypes.POINTER(Stats)]
         L.orc_flags_targeted.argtypes = grid + [i32, vp, vp, vp, vp]
         L.orc_flags_targeted.restype = i64
         L.orc_labels.argtypes = grid + [vp, vp, vp]
         L.orc_labels_at.argtypes = grid + [i32, vp, vp, i64, vp, vp]
         L.orc_verify.argtypes = grid + [i32, vp, vp, vp, dbl, ctypes.POINTER(Report)]
         for name in ("orc_directions", "orc_directions_at", "orc_validate", "orc_correct",
-                     "orc_correct_mode",
+                     "orc_correct_mode", "orc_correct_core",
                      "orc_labels", "orc_labels_at", "orc_verify"):
             getattr(L, name).restype = i32
         _lib = L
@@ -187,6 +189,23 @@ def correct(f, fhat, xi, max_iters=1 << 40, dirs_f=None, mode="halving"):
     d = st.as_dict()
     d["status"] = STATUS[d["status"]]
     return g, d
+
+
+def correct_core(f, g, xi, core, max_iters=1 << 40, dirs_f=None, mode="halving"):
+    """The correction of one block of a decomposed domain (Sec. IV-B), in
+    place on g: the loop of `correct`, with only the vertices of the box
+    core = (x0, x1, y0, y1, z0, z1) (half-open) compared; flags may target any
+    vertex of the array.  Returns the stats dict."""
+    f, g = _c(f), _c(g)
+    box = (ctypes.c_int64 * 6)(*[int(c) for c in core])
+    st = Stats()
+    lib().orc_correct_core(*grid_of(f), _dtype_code(f), _ptr(f), _ptr(g), float(xi),
+                           _ptr(dirs_f) if dirs_f is not None else None, int(max_iters),
+                           EDIT_MODES[mode], ctypes.cast(box, ctypes.c_void_p),
+                           ctypes.byref(st))
+    d = st.as_dict()
+    d["status"] = STATUS[d["status"]]
+    return d
 
 
 def flags_targeted(g, dirs_f):

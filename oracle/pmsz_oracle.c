@@ -18,7 +18,10 @@
  *   - ascending / descending segmentation labels by following the steepest
  *     directions to the extremum they end at (Sec. III-A, integral lines);
  *   - the evaluation counts: wrongly labelled points, false maxima / minima
- *     (Sec. V-D).
+ *     (Sec. V-D);
+ *   - the correction of one block of a decomposed domain (Sec. IV-B): the
+ *     same loop with the comparisons restricted to the block's core, the
+ *     outer ghost layer only providing neighbour values and receiving flags.
  *
  * Readings of points the paper leaves open (all written out in the design doc):
  *   - neighbourhood N*(i) = {i} + the Freudenthal (Kuhn) neighbours, 14 in 3D
@@ -343,8 +346,18 @@ int orc_validate(int ndim, int64_t nx, int64_t ny, int64_t nz, int dtype, const 
  *     rival.
  * flags[t] = 1 for every flagged t.  Returns the number of mismatching
  * (vertex, direction) pairs. */
-int64_t orc_flags(int ndim, int64_t nx, int64_t ny, int64_t nz, int dtype, const void* g,
-                  const uint8_t* dirs_f, uint8_t* flags) {
+/* Is vertex i inside the box core = {x0, x1, y0, y1, z0, z1} (half-open)? */
+static int in_box(const grid_t* G, int64_t i, const int64_t* core) {
+  int64_t x = i % G->nx, y = (i / G->nx) % G->ny, z = i / (G->nx * G->ny);
+  return x >= core[0] && x < core[1] && y >= core[2] && y < core[3] && z >= core[4] &&
+         z < core[5];
+}
+
+/* orc_flags with the comparisons restricted to the vertices of `core` (the
+ * targets they flag may lie anywhere). */
+static int64_t flags_core(int ndim, int64_t nx, int64_t ny, int64_t nz, int dtype,
+                          const void* g, const uint8_t* dirs_f, uint8_t* flags,
+                          const int64_t* core) {
   grid_t G = {ndim, nx, ny, nz};
   int64_t n = nverts(&G);
   int32_t* ag = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
@@ -362,6 +375,7 @@ int64_t orc_flags(int ndim, int64_t nx, int64_t ny, int64_t nz, int dtype, const
   memset(flags, 0, (size_t)n);
   int64_t mism = 0;
   for (int64_t i = 0; i < n; ++i) {
+    if (!in_box(&G, i, core)) continue;
     int64_t af = follow(&G, i, dirs_f[i] & 15);
     int64_t df = follow(&G, i, dirs_f[i] >> 4);
     if (ag[i] != af) { flags[ag[i]] = 1; mism++; }
@@ -370,6 +384,12 @@ int64_t orc_flags(int ndim, int64_t nx, int64_t ny, int64_t nz, int dtype, const
   free(ag);
   free(dg);
   return mism;
+}
+
+int64_t orc_flags(int ndim, int64_t nx, int64_t ny, int64_t nz, int dtype, const void* g,
+                  const uint8_t* dirs_f, uint8_t* flags) {
+  const int64_t all[6] = {0, nx, 0, ny, 0, nz};
+  return flags_core(ndim, nx, ny, nz, dtype, g, dirs_f, flags, all);
 }
 
 /* Targeted edit (the variant of Sec. IV-A's worked examples, where a spurious
@@ -387,8 +407,9 @@ static double next_below(int dtype, double v) {
   return dtype == ORC_F32 ? (double)nextafterf((float)v, -INFINITY) : nextafter(v, -INFINITY);
 }
 
-int64_t orc_flags_targeted(int ndim, int64_t nx, int64_t ny, int64_t nz, int dtype,
-                           const void* g, const uint8_t* dirs_f, uint8_t* flags, double* prop) {
+static int64_t flags_targeted_core(int ndim, int64_t nx, int64_t ny, int64_t nz, int dtype,
+                                   const void* g, const uint8_t* dirs_f, uint8_t* flags,
+                                   double* prop, const int64_t* core) {
   grid_t G = {ndim, nx, ny, nz};
   int64_t n = nverts(&G);
   int32_t* ag = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
@@ -405,6 +426,7 @@ int64_t orc_flags_targeted(int ndim, int64_t nx, int64_t ny, int64_t nz, int dty
   for (int64_t t = 0; t < n; ++t) prop[t] = INFINITY;
   int64_t mism = 0;
   for (int64_t i = 0; i < n; ++i) {
+    if (!in_box(&G, i, core)) continue;
     int64_t af = follow(&G, i, dirs_f[i] & 15);
     int64_t df = follow(&G, i, dirs_f[i] >> 4);
     int64_t t = -1, rival = -1;
@@ -431,6 +453,12 @@ int64_t orc_flags_targeted(int ndim, int64_t nx, int64_t ny, int64_t nz, int dty
   return mism;
 }
 
+int64_t orc_flags_targeted(int ndim, int64_t nx, int64_t ny, int64_t nz, int dtype,
+                           const void* g, const uint8_t* dirs_f, uint8_t* flags, double* prop) {
+  const int64_t all[6] = {0, nx, 0, ny, 0, nz};
+  return flags_targeted_core(ndim, nx, ny, nz, dtype, g, dirs_f, flags, prop, all);
+}
+
 /* The correction loop.  g holds fhat on entry and the last iterate on exit.
  *   k = 0
  *   repeat: F = flags(g^k)
@@ -438,10 +466,12 @@ int64_t orc_flags_targeted(int ndim, int64_t nx, int64_t ny, int64_t nz, int dty
  *           every t in F has g_t = lb -> STALLED (no edit can act)
  *           k == max_iters            -> NOT_CONVERGED
  *           g_t <- edit(g_t) for t in F, simultaneously; k += 1
- * dirs_f may be NULL (then computed here). */
-int orc_correct_mode(int ndim, int64_t nx, int64_t ny, int64_t nz, int dtype, const void* f,
+ * dirs_f may be NULL (then computed here).  Only the vertices of `core`
+ * ({x0, x1, y0, y1, z0, z1}, half-open) are compared; the whole grid for a
+ * single field, a block's core for a decomposed domain. */
+int orc_correct_core(int ndim, int64_t nx, int64_t ny, int64_t nz, int dtype, const void* f,
                      void* g, double xi, const uint8_t* dirs_f_in, int64_t max_iters,
-                     int mode, orc_stats* st) {
+                     int mode, const int64_t* core, orc_stats* st) {
   memset(st, 0, sizeof(*st));
   int s = orc_validate(ndim, nx, ny, nz, dtype, f, g, xi);
   if (s == ORC_OK && max_iters < 0) s = ORC_INVALID;
@@ -469,8 +499,9 @@ int orc_correct_mode(int ndim, int64_t nx, int64_t ny, int64_t nz, int dtype, co
   int64_t k = 0;
   int status;
   for (;;) {
-    int64_t mism = mode ? orc_flags_targeted(ndim, nx, ny, nz, dtype, g, dirs_f, flags, prop)
-                        : orc_flags(ndim, nx, ny, nz, dtype, g, dirs_f, flags);
+    int64_t mism = mode ? flags_targeted_core(ndim, nx, ny, nz, dtype, g, dirs_f, flags, prop,
+                                              core)
+                        : flags_core(ndim, nx, ny, nz, dtype, g, dirs_f, flags, core);
     if (mism < 0) { status = ORC_OOM; break; }
     if (k == 0) st->mismatch_initial = mism;
     int64_t nflag = 0, at_lb = 0;
@@ -518,6 +549,14 @@ int orc_correct_mode(int ndim, int64_t nx, int64_t ny, int64_t nz, int dtype, co
   free(prop);
   free(own);
   return status;
+}
+
+int orc_correct_mode(int ndim, int64_t nx, int64_t ny, int64_t nz, int dtype, const void* f,
+                     void* g, double xi, const uint8_t* dirs_f_in, int64_t max_iters,
+                     int mode, orc_stats* st) {
+  const int64_t all[6] = {0, nx, 0, ny, 0, nz};
+  return orc_correct_core(ndim, nx, ny, nz, dtype, f, g, xi, dirs_f_in, max_iters, mode, all,
+                          st);
 }
 
 /* The correction with the halving edit of Eq. 1 (mode 0). */

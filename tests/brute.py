@@ -105,9 +105,11 @@ def beats(vals, a, b):
     return vals[a] > vals[b] or (vals[a] == vals[b] and a > b)
 
 
-def slow_correct(f, fhat, xi_t, adj, max_iters=10 ** 6, mode="halving"):
+def slow_correct(f, fhat, xi_t, adj, max_iters=10 ** 6, mode="halving", core=None):
     """Reference correction loop written from the rules of Sec. IV-A, in the
     field's own numpy scalar type.  Returns (g, iterations, status).
+    core: the set of vertex ids that are compared (all when None); the
+    vertices they flag may lie outside it.
     mode "targeted": each target is lowered to the highest value at which it
     no longer beats its rival (found here by stepping down value by value from
     the rival's value), the smallest such value over its flaggers, never below
@@ -122,6 +124,8 @@ def slow_correct(f, fhat, xi_t, adj, max_iters=10 ** 6, mode="halving"):
     while True:
         targets = set()
         for i in range(n):
+            if core is not None and i not in core:
+                continue
             up, down = steepest(g, adj, i)
             if up != dir_f[i][0]:
                 targets.add(up)          # spurious maximum / false maximum
@@ -137,6 +141,8 @@ def slow_correct(f, fhat, xi_t, adj, max_iters=10 ** 6, mode="halving"):
         if mode == "targeted":
             best = {}
             for i in range(n):
+                if core is not None and i not in core:
+                    continue
                 up, down = steepest(g, adj, i)
                 pairs = []
                 if up != dir_f[i][0]:
@@ -164,3 +170,83 @@ def slow_correct(f, fhat, xi_t, adj, max_iters=10 ** 6, mode="halving"):
                 new[t] = m if m < g[t] else lb[t]
         g = new
         k += 1
+
+
+def slow_blocks(f, fhat, xi_t, blocks, per_round=False, max_phases=1000):
+    """The decomposed correction of Sec. IV-B on a tiny grid, written out with
+    explicit vertex lists: every block copies its core plus the vertices one
+    step outside it (its ghost layer), corrects the copy comparing core
+    vertices only, then every vertex takes the smallest value among its
+    copies.  Block k of an axis of n vertices cut b ways owns
+    [k n // b, (k+1) n // b).  Returns (g, phases, lowered, critical rounds,
+    status)."""
+    ndim = f.ndim
+    dims = list(reversed(f.shape))  # nx, ny[, nz]
+    nb = list(blocks[:ndim])
+    owned = []
+    for n, b in zip(dims, nb):
+        owned.append([list(range(k * n // b, (k + 1) * n // b)) for k in range(b)])
+    flat_f = f.reshape(-1)
+    g = fhat.reshape(-1).copy()
+    nx, ny = dims[0], dims[1]
+    blocks_list = []
+    for combo in np.ndindex(*reversed(nb)):
+        ks = list(reversed(combo))  # kx, ky[, kz]
+        ranges = []
+        core_ranges = []
+        for a in range(ndim):
+            own = owned[a][ks[a]]
+            lo, hi = max(own[0] - 1, 0), min(own[-1] + 2, dims[a])
+            ranges.append(list(range(lo, hi)))
+            core_ranges.append(set(own))
+        local = []   # global ids of the copy, in local id order (x fastest)
+        core = set()
+        zr = ranges[2] if ndim == 3 else [0]
+        for z in zr:
+            for y in ranges[1]:
+                for x in ranges[0]:
+                    lid = len(local)
+                    local.append(vid(x, y, z, nx, ny))
+                    if x in core_ranges[0] and y in core_ranges[1] and \
+                            (ndim == 2 or z in core_ranges[2]):
+                        core.add(lid)
+        shape = (len(zr), len(ranges[1]), len(ranges[0]))
+        adj = adjacency(ndim, shape[2], shape[1], shape[0])
+        blocks_list.append((local, core, shape, adj))
+    copies = [np.array([g[i] for i in local], dtype=f.dtype) for local, _, _, _ in blocks_list]
+    lfs = [np.array([flat_f[i] for i in local], dtype=f.dtype) for local, _, _, _ in blocks_list]
+    phases = lowered_total = critical = 0
+    while phases < max_phases:
+        results = []
+        changed = False
+        for b, (local, core, shape, adj) in enumerate(blocks_list):
+            before = copies[b].copy()
+            gb, k, status = slow_correct(lfs[b], copies[b], xi_t, adj,
+                                         max_iters=1 if per_round else 10 ** 6, core=core)
+            copies[b] = gb.reshape(-1).copy()
+            changed |= bool((copies[b] != before).any())
+            results.append((k, status))
+        # exchange: smallest copy of every vertex, everywhere
+        best = {}
+        for b, (local, _, _, _) in enumerate(blocks_list):
+            for lid, gid in enumerate(local):
+                v = copies[b][lid]
+                if gid not in best or v < best[gid]:
+                    best[gid] = v
+        lowered = 0
+        for b, (local, _, _, _) in enumerate(blocks_list):
+            for lid, gid in enumerate(local):
+                if copies[b][lid] > best[gid]:
+                    lowered += 1
+                    copies[b][lid] = best[gid]
+        for gid, v in best.items():
+            g[gid] = v
+        phases += 1
+        lowered_total += lowered
+        critical += max(k for k, _ in results)
+        if all(st == "OK" for _, st in results) and lowered == 0:
+            return g.reshape(f.shape), phases, lowered_total, critical, "OK"
+        if not changed and lowered == 0:
+            st = "STALLED" if any(st == "STALLED" for _, st in results) else "NOT_CONVERGED"
+            return g.reshape(f.shape), phases, lowered_total, critical, st
+    return g.reshape(f.shape), phases, lowered_total, critical, "NOT_CONVERGED"
