@@ -211,6 +211,40 @@ def bench_targeted(f, fhat, xi, steps, g_halving):
             "edit_storage": storage}
 
 
+def bench_blocks(f, fhat, xi, configs):
+    """The decomposed-domain correction (Sec. IV-B) emulated on one GPU: for
+    each block grid, relaxed exchanges (each block converges locally first)
+    against per-round exchanges.  Reports exchanges (phases), the schedule's
+    length in rounds with one GPU per block (critical_rounds), all rounds,
+    lowered copies, device time of the local corrections and of the
+    exchanges, and that every direction is restored."""
+    import torch
+
+    import paper_2601_01787_amd as pmsz
+    out = {}
+    for bl in configs:
+        key = "x".join(map(str, bl))
+        out[key] = {}
+        for name, per_round in (("relaxed", False), ("per_round", True)):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g, st = pmsz.correct_blocks(f, fhat, xi, bl, per_round=per_round)
+            torch.cuda.synchronize()
+            wall = (time.perf_counter() - t0) * 1e3
+            rep = pmsz.verify(f, g, fhat, xi)
+            out[key][name] = {
+                "status": st["status"], "phases": st["phases"],
+                "critical_rounds": st["critical_rounds"], "local_rounds": st["local_rounds"],
+                "lowered": st["lowered"], "edits": st["steps_applied"],
+                "compute_ms": round(st["compute_ms"], 3),
+                "exchange_ms": round(st["exchange_ms"], 3), "wall_ms": round(wall, 3),
+                "vertices_edited": rep["vertices_edited"],
+                "directions_restored": rep["asc_mismatch"] == 0 and rep["desc_mismatch"] == 0,
+                "bound_violations": rep["bound_violations"]}
+            del g
+    return out
+
+
 def bench_serving(dev, rates, n_requests, pool_per_class, seed):
     """Open-loop serving: Poisson arrivals at each rate; requests drawn from a
     pre-generated pool (generation stays out of the loop) over five classes
@@ -284,6 +318,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-pool", type=int, default=4,
                     help="pre-generated fields per request class")
+    ap.add_argument("--blocks", default="2x2x2,4x4x4",
+                    help="block grids of the decomposed-domain leg ('' to skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -393,6 +429,11 @@ def main():
         out["targeted"] = bench_targeted(f, fhat, xi, args.targeted_steps, gs[-1])
     del gs
     torch.cuda.empty_cache()
+    if args.blocks:
+        configs = [tuple(int(v) for v in c.split("x")) for c in args.blocks.split(",") if c]
+        log("decomposed domain:", configs)
+        out["blocks"] = bench_blocks(f, fhat, xi, configs)
+        torch.cuda.empty_cache()
     if args.batch_fields:
         log("batched vs plain on", args.batch_fields, "2D fields")
         out["batched"] = bench_batched(dev, args.batch_fields, 256)

@@ -174,6 +174,45 @@ int pmsz_batched_workspace_size(int32_t n, const pmsz_field* fields, size_t* byt
 int pmsz_correct_batched(int32_t n, const pmsz_field* fields, void* ws, size_t ws_bytes,
                          int64_t max_iters, pmsz_stats* stats, void* stream);
 
+/* Decomposed domain (Sec. IV-B, domain decomposition, ghost layer
+ * synchronisation and relaxed synchronisation), run on one GPU: the grid is
+ * cut into blocks[0] x blocks[1] x blocks[2] blocks (blocks[2] == 1 in 2D);
+ * along an axis of n vertices cut b ways, block k owns
+ * [floor(k n / b), floor((k+1) n / b)), and its copy spans one more vertex on
+ * each side that has a neighbour block (the ghost layer).  A phase corrects
+ * every block's copy (only owned vertices are compared; a flag may lower a
+ * ghost copy), then exchanges: every vertex takes the smallest of its copies
+ * in all of them and in g.  per_round = 0: each block runs to local
+ * convergence (at most max_iters rounds) before the exchange (pMSz);
+ * per_round = 1: one edit round per block between exchanges (sync-pMSz).  The
+ * loop ends with PMSZ_OK when every block's last check found no mismatch and
+ * the exchange lowered no copy; PMSZ_ERR_STALLED (or NOT_CONVERGED) when a
+ * phase changed no value; PMSZ_ERR_NOT_CONVERGED after max_phases phases.
+ * Results are valid corrections but differ from pmsz_correct on the whole
+ * grid (the blocks' iterate sequences differ).  f, g: device fields of `grid`
+ * (g: fhat in, result out; left unchanged when the inputs are rejected).
+ * blocks: host, three counts in [1, extent].  ws: device, 256-byte aligned,
+ * pmsz_blocks_workspace_size() bytes (copies of f and g per block, their
+ * direction bytes and an engine workspace for the blocks).  stats: host.
+ * Synchronises with `stream`. */
+typedef struct {
+  int64_t phases;          /* exchanges performed                                */
+  int64_t local_rounds;    /* edit rounds summed over blocks and phases          */
+  int64_t critical_rounds; /* per phase the most rounds of any block, summed:
+                              the schedule's length with one GPU per block      */
+  int64_t lowered;         /* block copies lowered by the exchanges             */
+  int64_t steps_applied;   /* value changes made by the local corrections      */
+  double compute_ms;       /* device time of the local corrections, all phases */
+  double exchange_ms;      /* device time of the exchanges, all phases         */
+  int32_t status;          /* pmsz_status of the run                            */
+  int32_t reserved;
+} pmsz_blocks_stats;
+int pmsz_blocks_workspace_size(const pmsz_grid* grid, const int32_t* blocks, size_t* bytes);
+int pmsz_correct_blocks(const pmsz_grid* grid, const void* f, void* g, double xi,
+                        const int32_t* blocks, int32_t per_round, int64_t max_phases,
+                        int64_t max_iters, void* ws, size_t ws_bytes, pmsz_blocks_stats* stats,
+                        void* stream);
+
 /* Edit stream: the corrections as stored next to the compressed field
  * (Sec. V-D reports this storage as the method's overhead; the format is this
  * library's).  Layout, little-endian:

@@ -33,6 +33,7 @@ EXPORTS = ("pmsz_workspace_size", "pmsz_directions", "pmsz_correct",
            "pmsz_session_add", "pmsz_session_step", "pmsz_session_sync", "pmsz_session_result",
            "pmsz_session_remove", "pmsz_session_destroy", "pmsz_edits_workspace_size",
            "pmsz_edits_max_bytes", "pmsz_encode_edits", "pmsz_decode_edits",
+           "pmsz_blocks_workspace_size", "pmsz_correct_blocks",
            "pmsz_status_string", "pmsz_last_error")
 
 
@@ -91,6 +92,19 @@ class Round(ctypes.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class BlocksStats(ctypes.Structure):
+    _fields_ = [("phases", ctypes.c_int64), ("local_rounds", ctypes.c_int64),
+                ("critical_rounds", ctypes.c_int64), ("lowered", ctypes.c_int64),
+                ("steps_applied", ctypes.c_int64), ("compute_ms", ctypes.c_double),
+                ("exchange_ms", ctypes.c_double), ("status", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        d = {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        d["status"] = STATUS.get(d["status"], d["status"])
+        return d
+
+
 class Field(ctypes.Structure):
     _fields_ = [("grid", Grid), ("f", ctypes.c_void_p), ("g", ctypes.c_void_p),
                 ("xi", ctypes.c_double)]
@@ -127,6 +141,9 @@ def load():
     L.pmsz_encode_edits.argtypes = [G, vp, vp, i64, vp, sz, vp, sz, ctypes.POINTER(i64),
                                     ctypes.POINTER(i64), vp]
     L.pmsz_decode_edits.argtypes = [G, vp, sz, vp, vp, sz, vp]
+    L.pmsz_blocks_workspace_size.argtypes = [G, vp, ctypes.POINTER(sz)]
+    L.pmsz_correct_blocks.argtypes = [G, vp, vp, dbl, vp, i32, i64, i64, vp, sz,
+                                      ctypes.POINTER(BlocksStats), vp]
     L.pmsz_last_rounds.argtypes = [ctypes.POINTER(Round), ctypes.c_int64,
                                    ctypes.POINTER(ctypes.c_int64)]
     L.pmsz_session_workspace_size.argtypes = [i32, ctypes.POINTER(sz)]
@@ -256,6 +273,32 @@ def correct_batched(fields, *, max_iters=DEFAULT_MAX_ITERS):
                                        ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream))
     _raise_if(code, allowed=(0, 2, 3, 4, 5))
     return [st[i].as_dict() for i in range(n)]
+
+
+def correct_blocks(f, fhat, xi, blocks, *, per_round=False, max_phases=1 << 20,
+                   max_iters=DEFAULT_MAX_ITERS, inplace=False):
+    """Decomposed-domain correction (pmsz_correct_blocks): blocks = (bx, by)
+    or (bx, by, bz) virtual ranks; per_round=False runs each block to local
+    convergence between exchanges, True one round.  Returns (g, stats)."""
+    _dev(f, "f")
+    _dev(fhat, "fhat")
+    if fhat.shape != f.shape or fhat.dtype != f.dtype or fhat.device != f.device:
+        raise ValueError("f and fhat must match in shape, dtype and device")
+    g = fhat if inplace else fhat.clone()
+    grid = grid_of(f)
+    bl = (ctypes.c_int32 * 3)(*(list(blocks) + [1] * (3 - len(blocks))))
+    need = ctypes.c_size_t()
+    _raise_if(load().pmsz_blocks_workspace_size(ctypes.byref(grid), bl, ctypes.byref(need)))
+    buf = torch.empty(need.value + 256, dtype=torch.uint8, device=f.device)
+    off = (-buf.data_ptr()) % 256
+    st = BlocksStats()
+    code = load().pmsz_correct_blocks(ctypes.byref(grid), ctypes.c_void_p(f.data_ptr()),
+                                      ctypes.c_void_p(g.data_ptr()), float(xi), bl,
+                                      1 if per_round else 0, int(max_phases), int(max_iters),
+                                      ctypes.c_void_p(buf.data_ptr() + off), need.value,
+                                      ctypes.byref(st), _stream(f))
+    _raise_if(code, allowed=(0, 2, 3, 4, 5))
+    return g, st.as_dict()
 
 
 def last_timing():

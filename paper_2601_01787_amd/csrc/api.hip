@@ -39,6 +39,12 @@ int fail(int code, const char* fmt, ...) {
       return fail(PMSZ_ERR_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
   } while (0)
 
+// Status of a HIP call, for code that releases resources before returning.
+inline int hip_check(hipError_t e) {
+  return e == hipSuccess ? PMSZ_OK
+                         : fail(PMSZ_ERR_DEVICE, "HIP call failed: %s", hipGetErrorString(e));
+}
+
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -316,6 +322,92 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
   return PMSZ_OK;
 }
 
+
+
+// ---------------------------------------------------------------------------
+// Decomposed domain (Sec. IV-B), emulated on one GPU.  Workspace:
+//   [block table][exchange counter][per block: copy of f, copy of g,
+//   direction bytes of the copy of f][engine workspace of the R block fields]
+// The direction bytes of the copies are computed once and given to every
+// phase's engine launch.
+// ---------------------------------------------------------------------------
+struct BlocksPlan {
+  int32_t nb[3] = {1, 1, 1};
+  int64_t R = 0;
+  std::vector<int64_t> org, ext, core;  // 3R, 3R, 6R
+  std::vector<size_t> off_f, off_g, off_d;
+  size_t tab = 0, ctr = 0, batch = 0, total = 0;
+  std::vector<pmsz_field> fields;
+  std::vector<const uint8_t*> dirs;
+  BatchPlan P;
+};
+
+int plan_blocks(const pmsz_grid& grid, const int32_t* blocks, double xi, int64_t cap,
+                uintptr_t base, BlocksPlan& B) {
+  const int64_t n[3] = {grid.nx, grid.ny, grid.nz};
+  for (int a = 0; a < 3; ++a) {
+    B.nb[a] = blocks[a];
+    if (blocks[a] < 1 || blocks[a] > n[a])
+      return fail(PMSZ_ERR_INVALID_ARG, "blocks[%d] = %d must lie in [1, %lld]", a, blocks[a],
+                  (long long)n[a]);
+  }
+  B.R = (int64_t)B.nb[0] * B.nb[1] * B.nb[2];
+  if (B.R > 65536) return fail(PMSZ_ERR_INVALID_ARG, "at most 65536 blocks");
+  const size_t vs = grid.dtype == PMSZ_F64 ? 8 : 4;
+  B.org.resize(3 * B.R);
+  B.ext.resize(3 * B.R);
+  B.core.resize(6 * B.R);
+  B.off_f.resize(B.R);
+  B.off_g.resize(B.R);
+  B.off_d.resize(B.R);
+  B.fields.resize(B.R);
+  B.dirs.resize(B.R);
+  B.tab = 0;
+  B.ctr = align_up(sizeof(BlockCopy) * (size_t)B.R);
+  size_t at = B.ctr + align_up(sizeof(unsigned long long));
+  for (int64_t id = 0; id < B.R; ++id) {
+    const int64_t k[3] = {id % B.nb[0], (id / B.nb[0]) % B.nb[1], id / ((int64_t)B.nb[0] * B.nb[1])};
+    int64_t cells = 1;
+    for (int a = 0; a < 3; ++a) {
+      const int64_t b = B.nb[a], s0 = k[a] * n[a] / b, s1 = (k[a] + 1) * n[a] / b;
+      const int64_t lo = s0 > 0 ? s0 - 1 : 0, hi = s1 < n[a] ? s1 + 1 : n[a];
+      B.org[3 * id + a] = lo;
+      B.ext[3 * id + a] = hi - lo;
+      B.core[6 * id + 2 * a] = s0 - lo;
+      B.core[6 * id + 2 * a + 1] = s1 - lo;
+      cells *= hi - lo;
+    }
+    B.off_f[id] = at;
+    at += align_up((size_t)cells * vs);
+    B.off_g[id] = at;
+    at += align_up((size_t)cells * vs);
+    B.off_d[id] = at;
+    at += align_up((size_t)cells);
+    pmsz_field& fl = B.fields[id];
+    fl.grid = grid;
+    fl.grid.nx = B.ext[3 * id];
+    fl.grid.ny = B.ext[3 * id + 1];
+    fl.grid.nz = B.ext[3 * id + 2];
+    fl.f = (const void*)(base + B.off_f[id]);
+    fl.g = (void*)(base + B.off_g[id]);
+    fl.xi = xi;
+    B.dirs[id] = (const uint8_t*)(base + B.off_d[id]);
+  }
+  B.batch = at;
+  int r = plan_batch((int32_t)B.R, B.fields.data(), B.dirs.data(), cap, B.P);
+  if (r) return r;
+  for (int64_t id = 0; id < B.R; ++id) {
+    TileGeo& G = B.P.fd[id].geo;
+    G.cx0 = (int32_t)B.core[6 * id];
+    G.cx1 = (int32_t)B.core[6 * id + 1];
+    G.cy0 = (int32_t)B.core[6 * id + 2];
+    G.cy1 = (int32_t)B.core[6 * id + 3];
+    G.cz0 = (int32_t)B.core[6 * id + 4];
+    G.cz1 = (int32_t)B.core[6 * id + 5];
+  }
+  B.total = B.batch + B.P.total;
+  return PMSZ_OK;
+}
 
 }  // namespace
 
@@ -638,6 +730,128 @@ int pmsz_correct_batched(int32_t n, const pmsz_field* fields, void* ws, size_t w
   return run_batch(fields[0].grid.dtype, P, nullptr, ws, stats, (hipStream_t)stream);
 }
 
+
+int pmsz_blocks_workspace_size(const pmsz_grid* grid, const int32_t* blocks, size_t* bytes) {
+  int r = check_grid(grid);
+  if (r) return r;
+  if (!blocks || !bytes) return fail(PMSZ_ERR_INVALID_ARG, "NULL argument");
+  BlocksPlan B;
+  if ((r = plan_blocks(*grid, blocks, 0.0, 0, (uintptr_t)kAlign, B))) return r;
+  *bytes = B.total;
+  return PMSZ_OK;
+}
+
+int pmsz_correct_blocks(const pmsz_grid* grid, const void* f, void* g, double xi,
+                        const int32_t* blocks, int32_t per_round, int64_t max_phases,
+                        int64_t max_iters, void* ws, size_t ws_bytes, pmsz_blocks_stats* stats,
+                        void* stream) {
+  int r = check_grid(grid);
+  if (r) return r;
+  if (!f || !g || !blocks || !ws || !stats) return fail(PMSZ_ERR_INVALID_ARG, "NULL argument");
+  if (!isfinite(xi) || xi < 0) return fail(PMSZ_ERR_INVALID_ARG, "xi must be finite and >= 0");
+  if (max_phases < 1) return fail(PMSZ_ERR_INVALID_ARG, "max_phases must be >= 1");
+  if (max_iters < 0) return fail(PMSZ_ERR_INVALID_ARG, "max_iters must be >= 0");
+  if ((uintptr_t)ws % kAlign) return fail(PMSZ_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  memset(stats, 0, sizeof(*stats));
+  BlocksPlan B;
+  const int64_t cap = per_round ? 1 : max_iters;
+  if ((r = plan_blocks(*grid, blocks, xi, cap, (uintptr_t)ws, B))) return r;
+  if (ws_bytes < B.total) return fail(PMSZ_ERR_OOM, "workspace %zu bytes, need %zu", ws_bytes, B.total);
+  hipStream_t s = (hipStream_t)stream;
+  char* base = (char*)ws;
+  const Geo G = make_geo(*grid);
+  // block table for the exchange
+  {
+    std::vector<BlockCopy> tab((size_t)B.R);
+    for (int64_t id = 0; id < B.R; ++id) {
+      tab[id].ox = B.org[3 * id];
+      tab[id].oy = B.org[3 * id + 1];
+      tab[id].oz = B.org[3 * id + 2];
+      tab[id].lnx = B.ext[3 * id];
+      tab[id].lny = B.ext[3 * id + 1];
+      tab[id].g = base + B.off_g[id];
+    }
+    void* stage;
+    if ((r = staging(t_stage, sizeof(BlockCopy) * tab.size(), &stage))) return r;
+    memcpy(stage, tab.data(), sizeof(BlockCopy) * tab.size());
+    HIP_TRY(hipMemcpyAsync(base + B.tab, stage, sizeof(BlockCopy) * tab.size(),
+                           hipMemcpyHostToDevice, s));
+    HIP_TRY(hipStreamSynchronize(s));  // the staging buffer is reused below
+  }
+  // copies of f and fhat, and the directions of each copy of f
+  for (int64_t id = 0; id < B.R; ++id) {
+    HIP_TRY(blocks_gather(grid->dtype, f, G, &B.org[3 * id], &B.ext[3 * id], base + B.off_f[id], s));
+    HIP_TRY(blocks_gather(grid->dtype, g, G, &B.org[3 * id], &B.ext[3 * id], base + B.off_g[id], s));
+    HIP_TRY(launch_dirs(grid->dtype, base + B.off_f[id], make_geo(B.fields[id].grid),
+                        (uint8_t*)(base + B.off_d[id]), s));
+  }
+  hipEvent_t ev[2];
+  HIP_TRY(hipEventCreate(&ev[0]));
+  HIP_TRY(hipEventCreate(&ev[1]));
+  std::vector<pmsz_stats> st((size_t)B.R);
+  unsigned long long* ctr = (unsigned long long*)(base + B.ctr);
+  int status = PMSZ_OK;
+  r = PMSZ_OK;
+  for (;;) {
+    if (stats->phases == max_phases) {
+      status = PMSZ_ERR_NOT_CONVERGED;
+      break;
+    }
+    // local correction of every block: the blocks are the fields of one
+    // engine launch, each comparing its core only
+    r = run_batch(grid->dtype, B.P, B.dirs.data(), base + B.batch, st.data(), s);
+    if (r != PMSZ_OK && r != PMSZ_ERR_NOT_CONVERGED && r != PMSZ_ERR_STALLED) break;
+    r = PMSZ_OK;
+    // a block whose copy failed validation (first phase only): g untouched
+    for (int64_t id = 0; id < B.R && r == PMSZ_OK; ++id)
+      if (st[id].status == PMSZ_ERR_NONFINITE || st[id].status == PMSZ_ERR_INPUT_BOUND)
+        r = fail(st[id].status, "block %lld: %s", (long long)id,
+                 pmsz_status_string(st[id].status));
+    if (r != PMSZ_OK) break;
+    stats->compute_ms += t_timing.last.dirs_ms + t_timing.last.engine_ms;
+    // ghost-layer exchange
+    unsigned long long lowered = 0;
+    if ((r = hip_check(engine_fill(ctr, sizeof(unsigned long long), 0u, s)))) break;
+    if ((r = hip_check(hipEventRecord(ev[0], s)))) break;
+    if ((r = hip_check(blocks_exchange(grid->dtype, g, G, B.nb,
+                                       (const BlockCopy*)(base + B.tab), ctr, s))))
+      break;
+    if ((r = hip_check(hipEventRecord(ev[1], s)))) break;
+    if ((r = hip_check(hipMemcpyAsync(&lowered, ctr, sizeof(lowered), hipMemcpyDeviceToHost, s))))
+      break;
+    if ((r = hip_check(hipStreamSynchronize(s)))) break;
+    float ms = 0.f;
+    if ((r = hip_check(hipEventElapsedTime(&ms, ev[0], ev[1])))) break;
+    stats->exchange_ms += ms;
+    int64_t steps = 0, most = 0;
+    bool all_ok = true, any_stalled = false;
+    for (int64_t id = 0; id < B.R; ++id) {
+      steps += st[id].steps_applied;
+      stats->local_rounds += st[id].iterations;
+      most = std::max(most, st[id].iterations);
+      all_ok &= st[id].status == PMSZ_OK;
+      any_stalled |= st[id].status == PMSZ_ERR_STALLED;
+    }
+    stats->phases += 1;
+    stats->critical_rounds += most;
+    stats->lowered += (int64_t)lowered;
+    stats->steps_applied += steps;
+    if (all_ok && lowered == 0) break;
+    if (steps == 0 && lowered == 0) {
+      status = any_stalled ? PMSZ_ERR_STALLED : PMSZ_ERR_NOT_CONVERGED;
+      break;
+    }
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  if (r != PMSZ_OK) {
+    stats->status = r;
+    return r;
+  }
+  stats->status = status;
+  if (status != PMSZ_OK) return fail(status, "%s", pmsz_status_string(status));
+  return PMSZ_OK;
+}
 
 int pmsz_session_workspace_size(int32_t max_fields, size_t* bytes) {
   if (max_fields < 1 || !bytes) return fail(PMSZ_ERR_INVALID_ARG, "max_fields must be >= 1");

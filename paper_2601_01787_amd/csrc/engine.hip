@@ -351,7 +351,7 @@ __device__ __forceinline__ Exam sparse_examine(const FieldDesc& d, uint32_t m) {
   const int32_t t = (int32_t)as_global(d.list)[k];
   // the vertex itself, then its neighbours: 3D codes 1..7, 9..15; 2D 1..3, 9..11
   const int code = three ? (j < 8 ? (int)j : (int)j + 1) : (j < 4 ? (int)j : (int)j + 5);
-  // is the neighbour inside the box?
+  // the neighbour's offset
   const int mm = code & 7;
   const int sg = (code & 8) ? -1 : 1;
   const int32_t x = t % G.nx;
@@ -359,7 +359,8 @@ __device__ __forceinline__ Exam sparse_examine(const FieldDesc& d, uint32_t m) {
   const int32_t z = three ? t / G.sxy : 0;
   const int32_t X = x + sg * (mm & 1), Y = y + sg * ((mm >> 1) & 1), Z = z + sg * ((mm >> 2) & 1);
   Exam ex{-1, -1, 0u};
-  if (X < 0 || X >= G.nx || Y < 0 || Y >= G.ny || Z < 0 || Z >= G.nz) return ex;
+  // only vertices of the detection box are examined (it lies inside the grid)
+  if (X < G.cx0 || X >= G.cx1 || Y < G.cy0 || Y >= G.cy1 || Z < G.cz0 || Z >= G.cz1) return ex;
   const int32_t v = t + code_offset(G, code);
   int ca, cd;
   gather_dirs<T>(G, as_global((const T*)d.g), v, X, Y, Z, ca, cd);

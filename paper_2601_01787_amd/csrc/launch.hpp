@@ -44,6 +44,19 @@ hipError_t launch_verify(int dtype, const void* f, const void* g, const void* fh
                          const int32_t* lf_min, const int32_t* lg_max, const int32_t* lg_min,
                          VerifyCounts* out, hipStream_t s);
 
+// blocks.hip: one block of a decomposed domain as the exchange sees it --
+// the origin of its copy in the global grid, the copy's x and y extents and
+// the copy's values (dense, x fastest).
+struct BlockCopy {
+  int64_t ox, oy, oz;
+  int64_t lnx, lny;
+  void* g;
+};
+hipError_t blocks_gather(int dtype, const void* src, const Geo& G, const int64_t o[3],
+                         const int64_t l[3], void* dst, hipStream_t s);
+hipError_t blocks_exchange(int dtype, void* g, const Geo& G, const int32_t nb[3],
+                           const BlockCopy* tab, unsigned long long* lowered, hipStream_t s);
+
 // edits.hip
 size_t edits_workspace_bytes(int64_t n, int64_t cap);
 size_t edits_stream_bytes(int64_t ne);

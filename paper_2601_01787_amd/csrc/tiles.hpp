@@ -81,6 +81,11 @@ struct TileGeo {
   int32_t ndim;
   int32_t chunk;       // planes (3D) or rows (2D) per tile
   int32_t tiles_x, tiles_y, tiles_z;
+  // Detection box [cx0, cx1) x [cy0, cy1) x [cz0, cz1): only the vertices in
+  // it are compared and can flag (their targets may lie outside it).  The
+  // whole grid, except for a block of a decomposed domain (Sec. IV-B), whose
+  // outer layer is a ghost copy of its neighbours' vertices.
+  int32_t cx0, cx1, cy0, cy1, cz0, cz1;
 };
 
 __host__ __device__ inline int64_t tile_count(const TileGeo& G) {
@@ -96,6 +101,12 @@ inline TileGeo make_tile_geo(int ndim, int64_t nx, int64_t ny, int64_t nz, int c
   G.n = (int32_t)(nx * ny * nz);
   G.ndim = ndim;
   G.chunk = chunk;
+  G.cx0 = 0;
+  G.cx1 = (int32_t)nx;
+  G.cy0 = 0;
+  G.cy1 = (int32_t)ny;
+  G.cz0 = 0;
+  G.cz1 = (int32_t)nz;
   if (ndim == 3) {
     G.tiles_x = (int32_t)((nx + TX - 1) / TX);
     G.tiles_y = (int32_t)((ny + TY - 1) / TY);
@@ -338,6 +349,7 @@ __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_
   };
   const int32_t X = x0 + tx, Y = y0 + ty;
   const bool mine = X < G.nx && Y < G.ny;
+  const bool core_col = mine && X >= G.cx0 && X < G.cx1 && Y >= G.cy0 && Y < G.cy1;
   // this column from the corner (the tile's first vertex for idle lanes)
   const uint32_t rel = mine ? (uint32_t)(ty + 1) * (uint32_t)G.nx + (uint32_t)(tx + 1) : safe;
   auto fetch = [&](int32_t z, Set& S) {
@@ -403,7 +415,8 @@ __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_
           nf += bc == 1;
           nb += bc == 2;
         }
-        mism += flag_targets3<T>(X, Y, v, ca, cd, fa, fd, fbx, G, sm.flags, prop, h, e.lo);
+        if (core_col && v >= G.cz0 && v < G.cz1)
+          mism += flag_targets3<T>(X, Y, v, ca, cd, fa, fd, fbx, G, sm.flags, prop, h, e.lo);
       }
     }
     gu = su;
@@ -475,6 +488,7 @@ __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_
   };
   const int32_t X = x0 + tid;
   const bool mine = X < G.nx;
+  const bool core_col = mine && X >= G.cx0 && X < G.cx1;
   const uint32_t rel = mine ? (uint32_t)tid + 1u : 1u;  // from the corner x0-1
   const int64_t corner = (int64_t)x0 - 1;
   auto fetch = [&](int32_t y, Set& S) {
@@ -541,7 +555,8 @@ __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_
         }
         // 2D codes only use the x and y bits; rows are indexed by y
         const int32_t vi = X + G.nx * v;
-        if (ca != fa) {
+        const bool core = core_col && v >= G.cy0 && v < G.cy1;
+        if (core && ca != fa) {
           flag2(v, ca);
           if (prop) {
             const int32_t c = vi + code_delta32(fa, G.nx, G.sxy);
@@ -549,7 +564,7 @@ __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_
           }
           ++mism;
         }
-        if (cd != fd) {
+        if (core && cd != fd) {
           flag2(v, fd);
           if (prop)
             propose<T>(prop, vi + code_delta32(fd, G.nx, G.sxy),

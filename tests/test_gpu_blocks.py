@@ -1,0 +1,86 @@
+"""GPU parity of the decomposed-domain correction (pmsz_correct_blocks,
+Sec. IV-B) against the oracle's block driver, bit for bit and stat for stat:
+relaxed and per-round exchanges, 2D and 3D, binary32 and binary64, ragged
+cuts, blocks one vertex wide (three holders per axis), a phase limit, the
+single-block case and the Perlin workload."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2601_01787_amd as pmsz
+import synth
+from oracle import multiblock as mb
+from test_gpu_parity import dev, host, random_case, same_bits
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("status", "phases", "local_rounds", "critical_rounds", "lowered", "steps_applied")
+
+CASES = [((64, 64, 64), (2, 2, 2), np.float32, False),
+         ((33, 40, 70), (3, 2, 4), np.float32, True),
+         ((20, 17, 31), (1, 3, 2), np.float64, False),
+         ((300, 517), (4, 3), np.float32, False),
+         ((257, 255), (2, 5), np.float64, True),
+         ((9, 7), (7, 9), np.float32, False),        # one-vertex-wide blocks
+         ((6, 5, 8), (8, 5, 3), np.float32, True)]
+
+
+def _check(f, fhat, xi, blocks, per_round, **kw):
+    g_ref, st_ref = mb.correct_blocks(f, fhat, xi, blocks, per_round=per_round, **kw)
+    g, st = pmsz.correct_blocks(dev(f), dev(fhat), xi, blocks, per_round=per_round, **kw)
+    for k in KEYS:
+        assert st[k] == st_ref[k], (k, st, st_ref)
+    assert same_bits(host(g), g_ref)
+    return st
+
+
+@pytest.mark.parametrize("shape,blocks,dtype,ties", CASES,
+                         ids=lambda v: "x".join(map(str, v)) if isinstance(v, tuple) else None)
+@pytest.mark.parametrize("per_round", [False, True])
+def test_blocks_match_oracle(shape, blocks, dtype, ties, per_round):
+    f, fhat, xi = random_case(shape, dtype, seed=3 * sum(shape) + len(blocks), ties=ties)
+    _check(f, fhat, xi, blocks, per_round)
+
+
+def test_blocks_perlin_relaxed_needs_fewer_exchanges():
+    f, fhat, xi = synth.small_perlin_case()
+    f, fhat = f.numpy(), fhat.numpy()
+    relaxed = _check(f, fhat, xi, (2, 2, 2), False)
+    sync = _check(f, fhat, xi, (2, 2, 2), True)
+    assert relaxed["status"] == sync["status"] == "OK"
+    assert relaxed["phases"] < sync["phases"]
+
+
+def test_blocks_peaks_2d():
+    f, fhat, xi = synth.make_2d_case(613, 401, 1e-3, 99)
+    f, fhat = f.numpy(), fhat.numpy()
+    _check(f, fhat, xi, (3, 4), False)
+    _check(f, fhat, xi, (3, 4), True)
+
+
+@pytest.mark.parametrize("phases", [1, 2])
+def test_blocks_phase_limit(phases):
+    f, fhat, xi = random_case((40, 33, 29), np.float32, seed=11)
+    st = _check(f, fhat, xi, (2, 2, 2), True, max_phases=phases)
+    assert st["status"] == "NOT_CONVERGED" and st["phases"] == phases
+
+
+def test_one_block_is_pmsz_correct():
+    f, fhat, xi = random_case((45, 50, 61), np.float32, seed=4)
+    g1, s1 = pmsz.correct(dev(f), dev(fhat), xi)
+    g, st = pmsz.correct_blocks(dev(f), dev(fhat), xi, (1, 1, 1))
+    assert st["phases"] == 1 and st["lowered"] == 0
+    assert st["local_rounds"] == s1["iterations"]
+    assert same_bits(host(g), host(g1))
+
+
+def test_blocks_reject_bad_input_and_leave_g():
+    f, fhat, xi = random_case((16, 16, 16), np.float32, seed=2)
+    fhat = fhat.copy()
+    fhat[3, 4, 5] = f[3, 4, 5] + 4 * xi       # outside the bound
+    gd = dev(fhat)
+    g, st = pmsz.correct_blocks(dev(f), gd, xi, (2, 2, 2), inplace=True)
+    assert st["status"] == "INPUT_BOUND"
+    assert same_bits(host(g), fhat)
+    with pytest.raises(pmsz.PmszError):
+        pmsz.correct_blocks(dev(f), dev(fhat), xi, (17, 1, 1))

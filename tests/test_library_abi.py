@@ -59,3 +59,22 @@ def test_host_only_calls():
                             ctypes.byref(st), None)
     assert code == 1
     assert b"NULL" in lib.pmsz_last_error()
+
+
+def test_blocks_workspace_size_host_only():
+    """pmsz_blocks_workspace_size: per block copies of f and g (value size),
+    direction bytes, plus the engine workspace of the block fields; bad block
+    counts are rejected."""
+    import paper_2601_01787_amd as pmsz
+    lib = pmsz.load()
+    g = pmsz.Grid(3, pmsz.F32, 64, 64, 64)
+    b = (ctypes.c_int32 * 3)(2, 2, 2)
+    n = ctypes.c_size_t()
+    assert lib.pmsz_blocks_workspace_size(ctypes.byref(g), b, ctypes.byref(n)) == 0
+    copies = 8 * 33 ** 3
+    assert n.value >= copies * (4 + 4 + 1)
+    assert n.value <= copies * (4 + 4 + 1) * 2 + (1 << 22)
+    for bad in ((65, 1, 1), (0, 1, 1), (1, 1, 2)):
+        gg = pmsz.Grid(3, pmsz.F32, 64, 64, 64) if bad[2] < 2 else pmsz.Grid(2, pmsz.F32, 64, 64, 1)
+        assert lib.pmsz_blocks_workspace_size(ctypes.byref(gg), (ctypes.c_int32 * 3)(*bad),
+                                              ctypes.byref(n)) == 1
