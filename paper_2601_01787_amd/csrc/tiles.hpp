@@ -122,6 +122,8 @@ inline TileGeo make_tile_geo(int ndim, int64_t nx, int64_t ny, int64_t nz, int c
 // What a tile pass does with the directions it computes.
 enum TileKind {
   KIND_DIRS = 0,        // write the direction bytes of h
+  KIND_DIRS_CHECK = 1,  // the same, plus the first round's validation of the
+                        // field passed as f (fhat) against h (f)
   KIND_FIRST_GIVEN = 2, // first round: validation of g against f, mismatch
                         // detection of g against the given directions of f
   KIND_NEXT = 3         // later rounds: mismatch detection of g
@@ -155,7 +157,7 @@ constexpr int kFlagWords = (kMaxChunk + 2) * (TY + 2) * kFlagW3 > (kMaxChunk + 2
 template <class T>
 struct TileLds {
   union {
-    T p3[2][PLANE];  // [buffer][haloed plane]
+    T p3[4][PLANE];  // [slot][haloed plane]: two pairs of planes
     T r2[2][RW];
   } ring;
   uint32_t flags[kFlagWords];
@@ -291,18 +293,21 @@ __device__ __forceinline__ int bound_class(T a, T b, T xi) {
 // written (DIRS).  bm: the field's flag bitmap.  Returns the packed counts in
 // thread 0.
 //
-// The march visits planes p = z0-1 .. z1 (z1 = end of the tile).  Step p
-// stages plane p in LDS, reduces the thread's upper square (x..x+1, y..y+1)
-// and lower square (x-1..x, y-1..y) of plane p, completes the upper box of
-// vertex p-1 and the lower box of vertex p, and finishes vertex p-1.
+// The march visits planes p = z0-1 .. z1 (z1 = end of the tile), two per
+// step.  For each plane p it reduces the thread's upper square (x..x+1,
+// y..y+1) and lower square (x-1..x, y-1..y), completes the upper box of
+// vertex p-1 and the lower box of vertex p, and finishes vertex p-1.  Two
+// planes per barrier halve the barriers and give each wave two independent
+// reduction chains to interleave.
 //
-// Software pipeline: the march is unrolled over kSets register sets; while
-// plane p is reduced, planes p+1 .. p+kSets-1 (and the direction bytes of
-// the matching vertices) are in flight in the other sets.  Loads are
-// unconditional (out-of-box lanes read a clamped in-box address and
-// substitute NaN at commit), and the barriers order LDS only, so the wait
-// before each commit covers just the set being committed.  Two LDS buffers
-// with one barrier per step suffice: a step reads only its own plane.
+// Software pipeline: the march is unrolled over kSets register sets (an
+// even number); while a pair of planes is reduced, the next kSets-2 planes
+// (and the direction bytes of the matching vertices) are in flight in the
+// other sets.  Loads are unconditional (out-of-box lanes read a clamped
+// in-box address and substitute NaN at commit), and the barriers order LDS
+// only, so the wait before each commit covers just the sets being committed.
+// Two pairs of LDS slots with one barrier per step suffice: a step reads
+// only its own pair.
 template <class T, int KIND, int SETS = sets_for<T, KIND>()>
 __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_in,
                             const T* f_in, uint8_t* dirs_in, uint32_t* bm_in, T xi,
@@ -313,7 +318,10 @@ __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_
   const gptr<uint32_t> bm = as_global(bm_in);
   constexpr int PER = (PLANE + 255) / 256;
   constexpr bool kReadDirs = (KIND == KIND_NEXT || KIND == KIND_FIRST_GIVEN);
-  constexpr bool kGivenF = (KIND == KIND_FIRST_GIVEN);
+  constexpr bool kWrite = (KIND == KIND_DIRS || KIND == KIND_DIRS_CHECK);
+  // the second field's value at each vertex: f for the first round's
+  // validation, fhat when the directions pass validates
+  constexpr bool kGivenF = (KIND == KIND_FIRST_GIVEN || KIND == KIND_DIRS_CHECK);
   constexpr int kSets = SETS;
   const int tid = threadIdx.x, tx = tid & (TX - 1), ty = tid / TX;
   const int32_t t32 = (int32_t)tile;
@@ -389,43 +397,64 @@ __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_
   FlagBox fbx{x0, y0, z0, TY + 2, kFlagW3, TX + 1};
   unsigned mism = 0, nf = 0, nb = 0;
   // carried from plane p-1: its squares, the lower box of vertex p-1 and the
-  // centre values (for validation)
+  // centre value (for validation)
   Ext<T> gu{}, gl{}, gbox{};
   T gc = T(0);
-  auto step = [&](int32_t p, Set& S, bool out) {
-    const int buf = (p - z0 + 1) & 1;
-    commit(buf, S);
-    const int d_cur = S.d;
-    const T f_cur = S.fv;
-    fetch(p + kSets, S);
-    lds_barrier();
-    Ext<T> su, sd;
-    squares(sm.ring.p3[buf], su, sd);
-    const Ext<T> glo = merge_dn(with_bits(gl, 12), sd);  // lower box of vertex p
-    if (out && mine) {
-      const int32_t v = p - 1;
-      const Ext<T> e = merge_up(gbox, merge_up(gu, with_bits(su, 4)));
-      const int ca = e.ca, cd = e.cd;
-      if (KIND == KIND_DIRS) {
-        (dirs + ((int64_t)G.sxy * v + corner))[rel] = (uint8_t)(ca | (cd << 4));
-      } else {
-        const int fa = d_cur & 15, fd = d_cur >> 4;
-        if (kGivenF) {
-          const int bc = bound_class<T>(f_cur, gc, xi);
-          nf += bc == 1;
-          nb += bc == 2;
-        }
-        if (core_col && v >= G.cz0 && v < G.cz1)
-          mism += flag_targets3<T>(X, Y, v, ca, cd, fa, fd, fbx, G, sm.flags, prop, h, e.lo);
+  // Finish vertex v from the lower box `lob` of v, its upper square `up` in
+  // its own plane and `upn` in the plane above.
+  auto finish = [&](int32_t v, const Ext<T>& lob, const Ext<T>& up, const Ext<T>& upn, int d,
+                    T fv, T centre) {
+    const Ext<T> e = merge_up(lob, merge_up(up, with_bits(upn, 4)));
+    const int ca = e.ca, cd = e.cd;
+    if (kWrite) {
+      (dirs + ((int64_t)G.sxy * v + corner))[rel] = (uint8_t)(ca | (cd << 4));
+      if (KIND == KIND_DIRS_CHECK) {
+        const int bc = bound_class<T>(centre, fv, xi);
+        nf += bc == 1;
+        nb += bc == 2;
       }
+    } else {
+      const int fa = d & 15, fd = d >> 4;
+      if (kGivenF) {
+        const int bc = bound_class<T>(fv, centre, xi);
+        nf += bc == 1;
+        nb += bc == 2;
+      }
+      if (core_col && v >= G.cz0 && v < G.cz1)
+        mism += flag_targets3<T>(X, Y, v, ca, cd, fa, fd, fbx, G, sm.flags, prop, h, e.lo);
     }
-    gu = su;
-    gl = sd;
-    gbox = glo;
-    gc = sm.ring.p3[buf][c];
+  };
+  // Two planes per barrier: step p stages planes p and p+1 in one pair of LDS
+  // slots, reduces both planes' squares (two independent chains), and
+  // finishes vertices p-1 and p.  Pairs alternate between the two slot
+  // pairs, so one barrier per pair orders all reuse.
+  auto step = [&](int32_t p, Set& S0, Set& S1, bool out0, bool out1) {
+    const int a = ((p - z0 + 1) >> 1) & 1;
+    T* P0 = sm.ring.p3[2 * a];
+    T* P1 = sm.ring.p3[2 * a + 1];
+    commit(2 * a, S0);
+    commit(2 * a + 1, S1);
+    const int d0 = S0.d, d1 = S1.d;
+    const T f0 = S0.fv, f1 = S1.fv;
+    fetch(p + kSets, S0);
+    fetch(p + 1 + kSets, S1);
+    lds_barrier();
+    Ext<T> su0, sd0, su1, sd1;
+    squares(P0, su0, sd0);
+    squares(P1, su1, sd1);
+    const Ext<T> glo0 = merge_dn(with_bits(gl, 12), sd0);   // lower box of vertex p
+    const Ext<T> glo1 = merge_dn(with_bits(sd0, 12), sd1);  // lower box of vertex p+1
+    const T c0 = P0[c];
+    if (out0 && mine) finish(p - 1, gbox, gu, su0, d0, f0, gc);
+    if (out1 && mine) finish(p, glo0, su0, su1, d1, f1, c0);
+    gu = su1;
+    gl = sd1;
+    gbox = glo1;
+    gc = P1[c];
     // issued after the evaluation so the old own values are dead (no
     // register copy of an in-flight load at the loop latch)
-    fetch_own(p + kSets - 1, S);
+    fetch_own(p + kSets - 1, S0);
+    fetch_own(p + kSets, S1);
   };
 
   Set Q[kSets];
@@ -436,14 +465,15 @@ __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_
     fetch(z0 - 1 + k, Q[k]);
     fetch_own(z0 - 2 + k, Q[k]);
   }
-  step(z0 - 1, Q[0], false);
-  step(z0, Q[1 % kSets], false);
+  step(z0 - 1, Q[0], Q[1], false, false);
   for (int32_t p = z0 + 1; p <= z1; p += kSets) {
 #pragma unroll
-    for (int k = 0; k < kSets; ++k) step(p + k, Q[(k + 2) % kSets], p + k <= z1);
+    for (int k = 0; k < kSets; k += 2)
+      step(p + k, Q[(k + 2) % kSets], Q[(k + 3) % kSets], p + k <= z1, p + k + 1 <= z1);
   }
   lds_barrier();  // the next tile of this block reuses the LDS buffers
   if (KIND == KIND_DIRS) return 0;
+  if (KIND == KIND_DIRS_CHECK) return block_sum(pack3(0u, nf, nb), red);
   flush_flags(sm.flags, fbx, G, (z1 - z0 + 2) * (TY + 2), bm);
   return block_sum(pack3(mism, nf, nb), red);
 }
@@ -461,7 +491,8 @@ __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_
   const gptr<uint32_t> bm = as_global(bm_in);
   constexpr int PER = (RW + 255) / 256;
   constexpr bool kReadDirs = (KIND == KIND_NEXT || KIND == KIND_FIRST_GIVEN);
-  constexpr bool kGivenF = (KIND == KIND_FIRST_GIVEN);
+  constexpr bool kWrite = (KIND == KIND_DIRS || KIND == KIND_DIRS_CHECK);
+  constexpr bool kGivenF = (KIND == KIND_FIRST_GIVEN || KIND == KIND_DIRS_CHECK);
   constexpr int kSets = SETS;
   const int tid = threadIdx.x;
   const int32_t t32 = (int32_t)tile;
@@ -544,8 +575,13 @@ __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_
       const int32_t v = r - 1;
       const Ext<T> e = merge_up(gbox, merge_up(gu, with_bits(su, 2)));
       const int ca = e.ca, cd = e.cd;
-      if (KIND == KIND_DIRS) {
+      if (kWrite) {
         (dirs + ((int64_t)G.nx * v + corner))[rel] = (uint8_t)(ca | (cd << 4));
+        if (KIND == KIND_DIRS_CHECK) {
+          const int bc = bound_class<T>(gc, f_cur, xi);
+          nf += bc == 1;
+          nb += bc == 2;
+        }
       } else {
         const int fa = d_cur & 15, fd = d_cur >> 4;
         if (kGivenF) {
@@ -596,6 +632,7 @@ __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_
   }
   lds_barrier();  // the next tile of this block reuses the LDS buffers
   if (KIND == KIND_DIRS) return 0;
+  if (KIND == KIND_DIRS_CHECK) return block_sum(pack3(0u, nf, nb), red);
   flush_flags(sm.flags, fbx, G, y1 - y0 + 2, bm);
   return block_sum(pack3(mism, nf, nb), red);
 }
