@@ -39,11 +39,10 @@ def source_hash():
 
 def algorithmic_bytes(voxels, swept, edits, s):
     """Bytes the method must move (per-unit figures): once per vertex f and fhat
-    read and its direction byte written (2s+1, the directions pass, which also
-    validates fhat); per vertex examined by a detect pass (every round, the
-    first included) g and the direction byte read and a flag bit written
+    read and its direction byte written (2s+1); per vertex examined by a later
+    detect pass g and the direction byte read and a flag bit written
     (s + 1 + 1/8); per edit f and g read and g written (3s)."""
-    return voxels * (2 * s + 1) + swept * (s + 1.125) + edits * 3 * s
+    return voxels * (2 * s + 1) + max(swept - voxels, 0) * (s + 1.125) + edits * 3 * s
 
 
 def measured_traffic(kernel):
@@ -60,14 +59,15 @@ def measured_traffic(kernel):
 
 def kernel_split(tm, rounds, s):
     """Per kernel of one correction: (total ms, launches, algorithmic bytes).
-    The directions kernel reads f and fhat and writes the direction bytes
-    (2s + 1 per vertex; it also validates fhat).  Every engine round reads g
-    and the direction bytes and writes flag bits (s + 1.125) per vertex
-    examined, in tiles or by sparse examination; an edit reads f and g and
-    writes g (3s)."""
+    The directions kernel reads f and writes the direction bytes (s + 1 per
+    vertex).  The engine's first round reads fhat, f and the direction bytes
+    (2s + 1 per vertex); a later round reads g and the direction bytes and
+    writes flag bits (s + 1.125) per vertex examined, in tiles or by sparse
+    examination; an edit reads f and g and writes g (3s)."""
     swept = [r["swept"] for r in rounds]
-    engine_bytes = sum(swept) * (s + 1.125) + tm["edits"] * 3 * s
-    return {"k_dirs_fields": (tm["dirs_ms"], 1, tm["voxels"] * (2 * s + 1)),
+    engine_bytes = (swept[0] * (2 * s + 1) if swept else 0) + \
+        sum(swept[1:]) * (s + 1.125) + tm["edits"] * 3 * s
+    return {"k_dirs_fields": (tm["dirs_ms"], 1, tm["voxels"] * (s + 1)),
             "k_engine": (tm["engine_ms"], 1, engine_bytes)}
 
 

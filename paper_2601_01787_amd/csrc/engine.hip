@@ -583,7 +583,7 @@ __device__ void detect_tiles(const EngineArgs& a, TileLds<T>& sm, unsigned long 
         const FieldIter s = state_at(a.fd[fi], E, E0);
         cached = fi;
         cached_kind = (s.done || sparse_items(a.fd[fi], s, E) >= 0) ? -1
-                    : (s.started || !a.fd[fi].dirs_given) ? KIND_NEXT : KIND_FIRST_GIVEN;
+                    : s.started ? KIND_NEXT : KIND_FIRST_GIVEN;
       }
       const int kind = cached_kind;
       if (kind < 0) continue;
@@ -796,34 +796,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
 
 // Directions of f for every field of a batch whose caller gave none, before
 // the engine runs: a plain (non-cooperative) grid over the tiles of all
-// fields, at the stencil's own occupancy.  The same pass validates fhat
-// against f (the first round's check) and adds the counts to the counters of
-// round 0, so the engine's first round of these fields reads neither f nor
-// the bounds.
+// fields, at the stencil's own occupancy.
 template <class T>
 __global__ __launch_bounds__(256) void k_dirs_fields(const FieldDesc* fd, int nf,
                                                      int64_t total_tiles) {
   __shared__ TileLds<T> sm;
-  __shared__ unsigned long long red[4];
   for (int64_t tt = blockIdx.x; tt < total_tiles; tt += gridDim.x) {
     const FieldDesc& d = fd[field_of_tile(fd, nf, tt)];
     if (d.dirs_given) continue;
     const T* f = (const T*)d.f;
-    const T* fhat = (const T*)d.g;
-    const T xi = (T)d.xi_t;
-    TileCounts tc;
     if (d.geo.ndim == 3)
-      tc = tile3<T, KIND_DIRS_CHECK>(sm, red, f, fhat, d.dirs, nullptr, xi, d.geo,
-                                     tt - d.tile_base);
+      tile3<T, KIND_DIRS>(sm, nullptr, f, f, d.dirs, nullptr, T(0), d.geo, tt - d.tile_base);
     else
-      tc = tile2<T, KIND_DIRS_CHECK>(sm, red, f, fhat, d.dirs, nullptr, xi, d.geo,
-                                     tt - d.tile_base);
-    if (threadIdx.x == 0) {
-      const gptr<FieldCtr> c0 = &as_global(d.st)->c[0];
-      const unsigned bnf = unpack3(tc, 1), bnb = unpack3(tc, 2);
-      if (bnf) relaxed_add(&c0->bad_nf, bnf);
-      if (bnb) relaxed_add(&c0->bad_b, bnb);
-    }
+      tile2<T, KIND_DIRS>(sm, nullptr, f, f, d.dirs, nullptr, T(0), d.geo, tt - d.tile_base);
   }
 }
 

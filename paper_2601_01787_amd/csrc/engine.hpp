@@ -51,10 +51,7 @@ struct FieldDesc {
   int64_t tile_base;  // first global tile index
   int64_t seg_base;   // first global apply segment
   int64_t words;      // bitmap words
-  int32_t dirs_given; // caller supplied the directions of f; otherwise the
-                      // directions pass computes them, validates fhat and
-                      // counts into round 0's counters (the run starts at
-                      // epoch 0), and the first round only compares
+  int32_t dirs_given; // caller supplied the directions of f
   int32_t list_cap;   // capacity of the target list
 };
 

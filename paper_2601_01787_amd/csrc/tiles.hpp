@@ -122,8 +122,6 @@ inline TileGeo make_tile_geo(int ndim, int64_t nx, int64_t ny, int64_t nz, int c
 // What a tile pass does with the directions it computes.
 enum TileKind {
   KIND_DIRS = 0,        // write the direction bytes of h
-  KIND_DIRS_CHECK = 1,  // the same, plus the first round's validation of the
-                        // field passed as f (fhat) against h (f)
   KIND_FIRST_GIVEN = 2, // first round: validation of g against f, mismatch
                         // detection of g against the given directions of f
   KIND_NEXT = 3         // later rounds: mismatch detection of g
@@ -318,10 +316,7 @@ __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_
   const gptr<uint32_t> bm = as_global(bm_in);
   constexpr int PER = (PLANE + 255) / 256;
   constexpr bool kReadDirs = (KIND == KIND_NEXT || KIND == KIND_FIRST_GIVEN);
-  constexpr bool kWrite = (KIND == KIND_DIRS || KIND == KIND_DIRS_CHECK);
-  // the second field's value at each vertex: f for the first round's
-  // validation, fhat when the directions pass validates
-  constexpr bool kGivenF = (KIND == KIND_FIRST_GIVEN || KIND == KIND_DIRS_CHECK);
+  constexpr bool kGivenF = (KIND == KIND_FIRST_GIVEN);
   constexpr int kSets = SETS;
   const int tid = threadIdx.x, tx = tid & (TX - 1), ty = tid / TX;
   const int32_t t32 = (int32_t)tile;
@@ -406,13 +401,8 @@ __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_
                     T fv, T centre) {
     const Ext<T> e = merge_up(lob, merge_up(up, with_bits(upn, 4)));
     const int ca = e.ca, cd = e.cd;
-    if (kWrite) {
+    if (KIND == KIND_DIRS) {
       (dirs + ((int64_t)G.sxy * v + corner))[rel] = (uint8_t)(ca | (cd << 4));
-      if (KIND == KIND_DIRS_CHECK) {
-        const int bc = bound_class<T>(centre, fv, xi);
-        nf += bc == 1;
-        nb += bc == 2;
-      }
     } else {
       const int fa = d & 15, fd = d >> 4;
       if (kGivenF) {
@@ -473,7 +463,6 @@ __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_
   }
   lds_barrier();  // the next tile of this block reuses the LDS buffers
   if (KIND == KIND_DIRS) return 0;
-  if (KIND == KIND_DIRS_CHECK) return block_sum(pack3(0u, nf, nb), red);
   flush_flags(sm.flags, fbx, G, (z1 - z0 + 2) * (TY + 2), bm);
   return block_sum(pack3(mism, nf, nb), red);
 }
@@ -491,8 +480,7 @@ __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_
   const gptr<uint32_t> bm = as_global(bm_in);
   constexpr int PER = (RW + 255) / 256;
   constexpr bool kReadDirs = (KIND == KIND_NEXT || KIND == KIND_FIRST_GIVEN);
-  constexpr bool kWrite = (KIND == KIND_DIRS || KIND == KIND_DIRS_CHECK);
-  constexpr bool kGivenF = (KIND == KIND_FIRST_GIVEN || KIND == KIND_DIRS_CHECK);
+  constexpr bool kGivenF = (KIND == KIND_FIRST_GIVEN);
   constexpr int kSets = SETS;
   const int tid = threadIdx.x;
   const int32_t t32 = (int32_t)tile;
@@ -575,13 +563,8 @@ __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_
       const int32_t v = r - 1;
       const Ext<T> e = merge_up(gbox, merge_up(gu, with_bits(su, 2)));
       const int ca = e.ca, cd = e.cd;
-      if (kWrite) {
+      if (KIND == KIND_DIRS) {
         (dirs + ((int64_t)G.nx * v + corner))[rel] = (uint8_t)(ca | (cd << 4));
-        if (KIND == KIND_DIRS_CHECK) {
-          const int bc = bound_class<T>(gc, f_cur, xi);
-          nf += bc == 1;
-          nb += bc == 2;
-        }
       } else {
         const int fa = d_cur & 15, fd = d_cur >> 4;
         if (kGivenF) {
@@ -632,7 +615,6 @@ __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_
   }
   lds_barrier();  // the next tile of this block reuses the LDS buffers
   if (KIND == KIND_DIRS) return 0;
-  if (KIND == KIND_DIRS_CHECK) return block_sum(pack3(0u, nf, nb), red);
   flush_flags(sm.flags, fbx, G, y1 - y0 + 2, bm);
   return block_sum(pack3(mism, nf, nb), red);
 }
