@@ -251,7 +251,9 @@ def bench_serving(dev, rates, n_requests, pool_per_class, seed):
     (128^3, 256^3, 512^3 Perlin; 1024^2, 4096^2 Gaussian peaks; binary32) with
     relative bounds from {1e-2, 1e-3, 1e-4}.  The continuous-batching server
     and a FIFO server of plain per-request launches replay the same arrival
-    sequence; every served result is compared with the request's alone result."""
+    sequence; every served result is compared with the request's alone result.
+    The batching server admits by HBM footprint and caps the vertices in
+    flight (its default work budget)."""
     import numpy as np
     import torch
 

@@ -37,6 +37,10 @@ class Request:
         self.footprint = None
 
 
+# Vertices admitted at once: one 512^3 field plus a few small ones.
+DEFAULT_WORK_BUDGET = 160 << 20
+
+
 def footprint(f):
     """Device bytes a request holds while admitted: its f, fhat and g, and its
     field workspace (flag bitmap, direction bytes, tile flags, state)."""
@@ -45,12 +49,20 @@ def footprint(f):
 
 class BatchingServer:
     """Admits requests by HBM footprint into a serving session and steps the
-    session until every request is done."""
+    session until every request is done.
+
+    Every field of a step advances in the same rounds, so a round lasts as
+    long as the largest field's round; `work_budget` (vertices) caps the
+    vertices admitted at once so that large fields do not hold every small
+    one back for their whole run (a request larger than the budget is
+    admitted when the session is empty).  None disables the cap."""
 
     def __init__(self, device, hbm_budget, max_fields=64, rounds_per_step=4,
-                 dtype=torch.float32, max_iters=1 << 40):
+                 dtype=torch.float32, max_iters=1 << 40, work_budget=DEFAULT_WORK_BUDGET):
         self.device = torch.device(device)
         self.budget = int(hbm_budget)
+        self.work_budget = work_budget
+        self.work = 0
         self.rounds = int(rounds_per_step)
         self.max_iters = max_iters
         self.session = Session(dtype, max_fields, self.device)
@@ -60,7 +72,10 @@ class BatchingServer:
         self.steps = 0
 
     def can_admit(self, req):
-        return len(self.active) < self.max_fields and self.in_use + req.footprint <= self.budget
+        if len(self.active) >= self.max_fields or self.in_use + req.footprint > self.budget:
+            return False
+        return (self.work_budget is None or not self.active
+                or self.work + req.f.numel() <= self.work_budget)
 
     def admit(self, req, now):
         req.g = req.fhat.clone()
@@ -71,6 +86,7 @@ class BatchingServer:
         req.handle = self.session.add(req.f, req.g, req.xi, req.ws, max_iters=self.max_iters)
         req.admitted = now
         self.in_use += req.footprint
+        self.work += req.f.numel()
         self.active[req.handle] = req
 
     def step(self):
@@ -87,6 +103,7 @@ class BatchingServer:
                 req.stats = st
                 self.session.remove(h)
                 self.in_use -= req.footprint
+                self.work -= req.f.numel()
                 del self.active[h]
                 req.ws = None
                 finished.append(req)
@@ -97,7 +114,7 @@ class BatchingServer:
 
 
 def run_open_loop(server_kind, requests, device, hbm_budget, max_fields=64, rounds_per_step=4,
-                  check=None):
+                  check=None, work_budget=DEFAULT_WORK_BUDGET):
     """Replay `requests` (sorted by arrival time, seconds from start) against
     a server in real time.  Returns the served requests.  `check(req)` (if
     given) is called on every finished request."""
@@ -108,7 +125,8 @@ def run_open_loop(server_kind, requests, device, hbm_budget, max_fields=64, roun
     for r in arrivals:
         r.footprint = footprint(r.f)
     if server_kind == "batched":
-        srv = BatchingServer(dev, hbm_budget, max_fields, rounds_per_step)
+        srv = BatchingServer(dev, hbm_budget, max_fields, rounds_per_step,
+                             work_budget=work_budget)
     torch.cuda.synchronize(dev)
     t0 = time.perf_counter()
     while arrivals or pending or (server_kind == "batched" and srv.active):
