@@ -174,6 +174,29 @@ int pmsz_batched_workspace_size(int32_t n, const pmsz_field* fields, size_t* byt
 int pmsz_correct_batched(int32_t n, const pmsz_field* fields, void* ws, size_t ws_bytes,
                          int64_t max_iters, pmsz_stats* stats, void* stream);
 
+/* Tile shapes.  The correction sweeps each field in tiles of 64 x 4 columns
+ * (3D) or 256-wide strips (2D) of `h` planes / rows, h between 2 and 32,
+ * chosen to give about `tiles_target` tiles per field (default 2048).  The
+ * tile height changes neither results nor statistics, only speed (the
+ * iteration of Sec. IV-A is the same; the tiles only decide which vertices a
+ * detect pass reads).  The target is kept per (ndim, dtype) for the whole
+ * process and read when a correction, batch or session field is planned.
+ * pmsz_set_tiles_target: 0 restores the default.  Host-only, thread-safe.
+ * pmsz_tune_tiles: the autotuner.  Corrects the batch `fields` (g holds fhat
+ * and is NOT modified; copies are corrected in ws) once per candidate target,
+ * `reps` times each, measures the device time of each run (directions pass +
+ * engine, HIP events), writes the best time per candidate into ms (host,
+ * n_candidates; may be NULL), sets the fastest target for the batch's (ndim,
+ * dtype) and returns it in *best.  All fields must share ndim and dtype.
+ * ws: device, 256-byte aligned, pmsz_tune_workspace_size() bytes.
+ * Synchronises with `stream`. */
+int pmsz_set_tiles_target(int32_t ndim, int32_t dtype, int32_t tiles_target);
+int pmsz_get_tiles_target(int32_t ndim, int32_t dtype, int32_t* tiles_target);
+int pmsz_tune_workspace_size(int32_t n, const pmsz_field* fields, size_t* bytes);
+int pmsz_tune_tiles(int32_t n, const pmsz_field* fields, const int32_t* candidates,
+                    int32_t n_candidates, int32_t reps, void* ws, size_t ws_bytes, double* ms,
+                    int32_t* best, void* stream);
+
 /* Decomposed domain (Sec. IV-B, domain decomposition, ghost layer
  * synchronisation and relaxed synchronisation), run on one GPU: the grid is
  * cut into blocks[0] x blocks[1] x blocks[2] blocks (blocks[2] == 1 in 2D);

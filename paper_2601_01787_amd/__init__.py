@@ -33,7 +33,8 @@ EXPORTS = ("pmsz_workspace_size", "pmsz_directions", "pmsz_correct",
            "pmsz_session_add", "pmsz_session_step", "pmsz_session_sync", "pmsz_session_result",
            "pmsz_session_remove", "pmsz_session_destroy", "pmsz_edits_workspace_size",
            "pmsz_edits_max_bytes", "pmsz_encode_edits", "pmsz_decode_edits",
-           "pmsz_blocks_workspace_size", "pmsz_correct_blocks",
+           "pmsz_blocks_workspace_size", "pmsz_correct_blocks", "pmsz_set_tiles_target",
+           "pmsz_get_tiles_target", "pmsz_tune_workspace_size", "pmsz_tune_tiles",
            "pmsz_status_string", "pmsz_last_error")
 
 
@@ -142,6 +143,11 @@ def load():
                                     ctypes.POINTER(i64), vp]
     L.pmsz_decode_edits.argtypes = [G, vp, sz, vp, vp, sz, vp]
     L.pmsz_blocks_workspace_size.argtypes = [G, vp, ctypes.POINTER(sz)]
+    L.pmsz_set_tiles_target.argtypes = [i32, i32, i32]
+    L.pmsz_get_tiles_target.argtypes = [i32, i32, ctypes.POINTER(i32)]
+    L.pmsz_tune_workspace_size.argtypes = [i32, ctypes.POINTER(Field), ctypes.POINTER(sz)]
+    L.pmsz_tune_tiles.argtypes = [i32, ctypes.POINTER(Field), vp, i32, i32, vp, sz, vp,
+                                  ctypes.POINTER(i32), vp]
     L.pmsz_correct_blocks.argtypes = [G, vp, vp, dbl, vp, i32, i64, i64, vp, sz,
                                       ctypes.POINTER(BlocksStats), vp]
     L.pmsz_last_rounds.argtypes = [ctypes.POINTER(Round), ctypes.c_int64,
@@ -299,6 +305,49 @@ def correct_blocks(f, fhat, xi, blocks, *, per_round=False, max_phases=1 << 20,
                                       ctypes.byref(st), _stream(f))
     _raise_if(code, allowed=(0, 2, 3, 4, 5))
     return g, st.as_dict()
+
+
+TILE_TARGETS = (32, 64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384)
+
+
+def set_tiles_target(ndim, dtype, target):
+    """Tiles-per-field target of the tile-height policy for (ndim, dtype)
+    (torch.float32 / torch.float64); 0 restores the default."""
+    _raise_if(load().pmsz_set_tiles_target(int(ndim), F32 if dtype == torch.float32 else F64,
+                                           int(target)))
+
+
+def get_tiles_target(ndim, dtype):
+    t = ctypes.c_int32()
+    _raise_if(load().pmsz_get_tiles_target(int(ndim), F32 if dtype == torch.float32 else F64,
+                                           ctypes.byref(t)))
+    return t.value
+
+
+def tune_tiles(fields, candidates=TILE_TARGETS, reps=2):
+    """Autotune the tile height for a batch of (f, fhat, xi) (fhat is left
+    unchanged): times the correction for every candidate tiles-per-field
+    target, keeps the fastest for the batch's (ndim, dtype) and returns
+    (best target, {target: device ms})."""
+    n = len(fields)
+    arr = (Field * n)()
+    for i, (f, fhat, xi) in enumerate(fields):
+        _dev(f, "f")
+        _dev(fhat, "fhat")
+        arr[i] = Field(grid_of(f), f.data_ptr(), fhat.data_ptr(), float(xi))
+    need = ctypes.c_size_t()
+    _raise_if(load().pmsz_tune_workspace_size(n, arr, ctypes.byref(need)))
+    dev = fields[0][0].device
+    buf = torch.empty(need.value + 256, dtype=torch.uint8, device=dev)
+    off = (-buf.data_ptr()) % 256
+    cand = (ctypes.c_int32 * len(candidates))(*candidates)
+    ms = (ctypes.c_double * len(candidates))()
+    best = ctypes.c_int32()
+    _raise_if(load().pmsz_tune_tiles(n, arr, cand, len(candidates), int(reps),
+                                     ctypes.c_void_p(buf.data_ptr() + off), need.value, ms,
+                                     ctypes.byref(best),
+                                     ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)))
+    return best.value, {int(c): ms[i] for i, c in enumerate(candidates)}
 
 
 def last_timing():

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 
 #include <unordered_map>
@@ -46,6 +47,7 @@ inline int hip_check(hipError_t e) {
 }
 
 constexpr size_t kAlign = 256;
+constexpr int64_t DEFAULT_TUNE_ITERS = int64_t(1) << 40;  // tuning runs go to convergence
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
 int check_grid(const pmsz_grid* g) {
@@ -110,8 +112,21 @@ struct BatchPlan {
   std::vector<size_t> field_off, dirs_off, prop_off;
 };
 
+// Tile height policy per (ndim, dtype): the tuned tiles-per-field target
+// (0 = the default).  Read when a field is planned, so a field keeps the
+// geometry it was planned with.
+std::mutex g_tiles_mu;
+int32_t g_tiles_target[2][2] = {{0, 0}, {0, 0}};
+
+int32_t tiles_target(int ndim, int dtype) {
+  std::lock_guard<std::mutex> lk(g_tiles_mu);
+  const int32_t t = g_tiles_target[ndim == 3][dtype == PMSZ_F64];
+  return t > 0 ? t : kDefaultTilesTarget;
+}
+
 // Descriptor of one field with everything but its device pointers.
-int describe_field(const pmsz_field& fld, int64_t max_iters, int dirs_given, FieldDesc& d) {
+int describe_field(const pmsz_field& fld, int64_t max_iters, int dirs_given, FieldDesc& d,
+                   int32_t target = 0) {
   const pmsz_grid& g = fld.grid;
   int r = check_grid(&g);
   if (r) return r;
@@ -119,7 +134,9 @@ int describe_field(const pmsz_field& fld, int64_t max_iters, int dirs_given, Fie
   memset(&d, 0, sizeof(d));
   d.f = fld.f;
   d.g = fld.g;
-  d.geo = make_tile_geo(g.ndim, g.nx, g.ny, g.nz, engine_chunk(g.ndim, g.nx, g.ny, g.nz));
+  d.geo = make_tile_geo(g.ndim, g.nx, g.ny, g.nz,
+                        engine_chunk(g.ndim, g.nx, g.ny, g.nz,
+                                     target > 0 ? target : tiles_target(g.ndim, g.dtype)));
   d.xi_t = xi_in_type(g.dtype, fld.xi);
   d.max_iters = max_iters;
   d.words = bitmap_words(d.geo.n);
@@ -128,7 +145,7 @@ int describe_field(const pmsz_field& fld, int64_t max_iters, int dirs_given, Fie
 }
 
 int plan_batch(int32_t n, const pmsz_field* fields, const uint8_t* const* dirs_given,
-               int64_t max_iters, BatchPlan& P, int edit_mode = 0) {
+               int64_t max_iters, BatchPlan& P, int edit_mode = 0, int32_t target = 0) {
   P.fd.resize(n);
   P.field_off.resize(n);
   P.dirs_off.resize(n);
@@ -139,7 +156,7 @@ int plan_batch(int32_t n, const pmsz_field* fields, const uint8_t* const* dirs_g
     if (fields[i].grid.dtype != fields[0].grid.dtype)
       return fail(PMSZ_ERR_INVALID_ARG, "all fields of a batch must share one dtype");
     FieldDesc& d = P.fd[i];
-    int r = describe_field(fields[i], max_iters, (dirs_given && dirs_given[i]) ? 1 : 0, d);
+    int r = describe_field(fields[i], max_iters, (dirs_given && dirs_given[i]) ? 1 : 0, d, target);
     if (r) return r;
     d.tile_base = P.total_tiles;
     d.seg_base = P.total_segs;
@@ -730,6 +747,99 @@ int pmsz_correct_batched(int32_t n, const pmsz_field* fields, void* ws, size_t w
   return run_batch(fields[0].grid.dtype, P, nullptr, ws, stats, (hipStream_t)stream);
 }
 
+
+int pmsz_set_tiles_target(int32_t ndim, int32_t dtype, int32_t target) {
+  if ((ndim != 2 && ndim != 3) || (dtype != PMSZ_F32 && dtype != PMSZ_F64) || target < 0)
+    return fail(PMSZ_ERR_INVALID_ARG, "bad ndim, dtype or target");
+  std::lock_guard<std::mutex> lk(g_tiles_mu);
+  g_tiles_target[ndim == 3][dtype == PMSZ_F64] = target;
+  return PMSZ_OK;
+}
+
+int pmsz_get_tiles_target(int32_t ndim, int32_t dtype, int32_t* target) {
+  if ((ndim != 2 && ndim != 3) || (dtype != PMSZ_F32 && dtype != PMSZ_F64) || !target)
+    return fail(PMSZ_ERR_INVALID_ARG, "bad ndim, dtype or NULL target");
+  *target = tiles_target(ndim, dtype);
+  return PMSZ_OK;
+}
+
+namespace {
+// Scratch copies of the fields' fhat for the tuner, then the batch workspace.
+int tune_layout(int32_t n, const pmsz_field* fields, std::vector<size_t>& off, size_t* total) {
+  if (n < 1 || !fields) return fail(PMSZ_ERR_INVALID_ARG, "empty batch");
+  off.resize(n);
+  size_t at = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    int r = check_grid(&fields[i].grid);
+    if (r) return r;
+    if (fields[i].grid.ndim != fields[0].grid.ndim || fields[i].grid.dtype != fields[0].grid.dtype)
+      return fail(PMSZ_ERR_INVALID_ARG, "tuned fields must share ndim and dtype");
+    const size_t vs = fields[i].grid.dtype == PMSZ_F64 ? 8 : 4;
+    off[i] = at;
+    at += align_up((size_t)(fields[i].grid.nx * fields[i].grid.ny * fields[i].grid.nz) * vs);
+  }
+  BatchPlan P;
+  int r = plan_batch(n, fields, nullptr, 0, P);
+  if (r) return r;
+  *total = at + P.total;
+  return PMSZ_OK;
+}
+}  // namespace
+
+int pmsz_tune_workspace_size(int32_t n, const pmsz_field* fields, size_t* bytes) {
+  if (!bytes) return fail(PMSZ_ERR_INVALID_ARG, "bytes is NULL");
+  std::vector<size_t> off;
+  return tune_layout(n, fields, off, bytes);
+}
+
+int pmsz_tune_tiles(int32_t n, const pmsz_field* fields, const int32_t* candidates,
+                    int32_t n_candidates, int32_t reps, void* ws, size_t ws_bytes, double* ms,
+                    int32_t* best, void* stream) {
+  if (!fields || !candidates || n_candidates < 1 || reps < 1 || !ws || !best)
+    return fail(PMSZ_ERR_INVALID_ARG, "NULL argument or empty candidate list");
+  if ((uintptr_t)ws % kAlign) return fail(PMSZ_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  for (int32_t c = 0; c < n_candidates; ++c)
+    if (candidates[c] < 1) return fail(PMSZ_ERR_INVALID_ARG, "candidate targets must be >= 1");
+  for (int32_t i = 0; i < n; ++i)
+    if (!fields[i].f || !fields[i].g) return fail(PMSZ_ERR_INVALID_ARG, "field %d: NULL array", i);
+  std::vector<size_t> off;
+  size_t total = 0;
+  int r = tune_layout(n, fields, off, &total);
+  if (r) return r;
+  if (ws_bytes < total) return fail(PMSZ_ERR_OOM, "workspace %zu bytes, need %zu", ws_bytes, total);
+  hipStream_t s = (hipStream_t)stream;
+  char* base = (char*)ws;
+  std::vector<pmsz_field> scratch(fields, fields + n);
+  for (int32_t i = 0; i < n; ++i) scratch[i].g = base + off[i];
+  std::vector<pmsz_stats> st((size_t)n);
+  const size_t vs = fields[0].grid.dtype == PMSZ_F64 ? 8 : 4;
+  double best_ms = 0.0;
+  int32_t best_t = 0;
+  for (int32_t c = 0; c < n_candidates; ++c) {
+    BatchPlan P;
+    if ((r = plan_batch(n, scratch.data(), nullptr, DEFAULT_TUNE_ITERS, P, 0, candidates[c])))
+      return r;
+    double t_min = 0.0;
+    for (int32_t k = 0; k < reps; ++k) {
+      for (int32_t i = 0; i < n; ++i) {
+        const pmsz_grid& g = fields[i].grid;
+        HIP_TRY(hipMemcpyAsync(scratch[i].g, fields[i].g, (size_t)(g.nx * g.ny * g.nz) * vs,
+                               hipMemcpyDeviceToDevice, s));
+      }
+      r = run_batch(fields[0].grid.dtype, P, nullptr, base + (total - P.total), st.data(), s);
+      if (r != PMSZ_OK && r != PMSZ_ERR_NOT_CONVERGED && r != PMSZ_ERR_STALLED) return r;
+      const double t = t_timing.last.dirs_ms + t_timing.last.engine_ms;
+      if (k == 0 || t < t_min) t_min = t;
+    }
+    if (ms) ms[c] = t_min;
+    if (c == 0 || t_min < best_ms) {
+      best_ms = t_min;
+      best_t = candidates[c];
+    }
+  }
+  *best = best_t;
+  return pmsz_set_tiles_target(fields[0].grid.ndim, fields[0].grid.dtype, best_t);
+}
 
 int pmsz_blocks_workspace_size(const pmsz_grid* grid, const int32_t* blocks, size_t* bytes) {
   int r = check_grid(grid);

@@ -125,22 +125,30 @@ inline size_t ws_align(size_t v) { return (v + 255) / 256 * 256; }
 inline FieldLayout field_layout(const TileGeo& G, bool dirs_given) {
   FieldLayout L;
   L.state = 0;
+  // activity bytes sized for the shortest tiles (2 planes / rows), so that a
+  // field's workspace fits any tile height the tuner may pick
+  const int64_t depth = G.ndim == 3 ? G.nz : G.ny;
+  const size_t max_tiles = (size_t)G.tiles_x * (G.ndim == 3 ? G.tiles_y : 1) * ((depth + 1) / 2);
   L.act = ws_align(sizeof(FieldState));
-  L.bm = L.act + ws_align(2 * (size_t)tile_count(G));
+  L.bm = L.act + ws_align(2 * max_tiles);
   L.list = L.bm + ws_align(((size_t)G.n + 31) / 32 * 4);
   L.dirs = L.list + ws_align((size_t)list_capacity(G) * 4);
   L.total = L.dirs + (dirs_given ? 0 : ws_align((size_t)G.n));
   return L;
 }
 
-// Tile rows per tile for the engine: enough tiles to spread a small field over
-// the chip, 32 planes / rows otherwise.
-inline int engine_chunk(int ndim, int64_t nx, int64_t ny, int64_t nz) {
+// Tile height (planes per 3D tile, rows per 2D strip) for the engine: about
+// `tiles_target` tiles per field, between 2 and 32 planes / rows.  The target
+// is the autotuned knob (default 2048: enough tiles to spread one small field
+// over the chip); results do not depend on it.
+constexpr int32_t kDefaultTilesTarget = 2048;
+inline int engine_chunk(int ndim, int64_t nx, int64_t ny, int64_t nz,
+                        int32_t tiles_target = kDefaultTilesTarget) {
   const int64_t cols = ndim == 3 ? ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY) : (nx + RX - 1) / RX;
   const int64_t depth = ndim == 3 ? nz : ny;
-  int64_t c = depth * cols / 2048;
+  int64_t c = depth * cols / (tiles_target > 0 ? tiles_target : kDefaultTilesTarget);
   if (c < 2) c = 2;
-  if (c > 32) c = 32;
+  if (c > kMaxChunk) c = kMaxChunk;
   return (int)c;
 }
 

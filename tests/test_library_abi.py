@@ -78,3 +78,23 @@ def test_blocks_workspace_size_host_only():
         gg = pmsz.Grid(3, pmsz.F32, 64, 64, 64) if bad[2] < 2 else pmsz.Grid(2, pmsz.F32, 64, 64, 1)
         assert lib.pmsz_blocks_workspace_size(ctypes.byref(gg), (ctypes.c_int32 * 3)(*bad),
                                               ctypes.byref(n)) == 1
+
+
+def test_tiles_target_host_only():
+    """The tile-height policy: per (ndim, dtype), 0 restores the default, bad
+    arguments are rejected, and workspace sizes do not depend on it."""
+    import paper_2601_01787_amd as pmsz
+    lib = pmsz.load()
+    t = ctypes.c_int32()
+    assert lib.pmsz_get_tiles_target(3, pmsz.F32, ctypes.byref(t)) == 0 and t.value == 2048
+    g = pmsz.Grid(3, pmsz.F32, 300, 200, 100)
+    before = pmsz.workspace_size(g, pmsz.WS_CORRECT)
+    assert lib.pmsz_set_tiles_target(3, pmsz.F32, 64) == 0
+    assert lib.pmsz_get_tiles_target(3, pmsz.F32, ctypes.byref(t)) == 0 and t.value == 64
+    assert lib.pmsz_get_tiles_target(2, pmsz.F32, ctypes.byref(t)) == 0 and t.value == 2048
+    assert pmsz.workspace_size(g, pmsz.WS_CORRECT) == before
+    assert lib.pmsz_set_tiles_target(3, pmsz.F32, 0) == 0
+    assert lib.pmsz_get_tiles_target(3, pmsz.F32, ctypes.byref(t)) == 0 and t.value == 2048
+    assert lib.pmsz_set_tiles_target(4, pmsz.F32, 64) == 1
+    assert lib.pmsz_set_tiles_target(3, 9, 64) == 1
+    assert lib.pmsz_set_tiles_target(3, pmsz.F32, -1) == 1
