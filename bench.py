@@ -141,6 +141,34 @@ def bench_batched(dev, n_fields, seed):
                              "batched_ms_default": round(t_batch * 1e3, 2)}}
 
 
+def bench_small(dev, calls):
+    """The 64^3 binary32 Perlin field (4 octaves, eps 1e-3, L2-resident):
+    latency of one whole correction call (host planning, descriptor upload,
+    directions pass and the one-launch loop, synchronised) and the device time
+    per round."""
+    import torch
+
+    import paper_2601_01787_amd as pmsz
+    import synth
+    f, fhat, xi = synth.small_perlin_case(device=dev)
+    ws = pmsz.workspace(pmsz.grid_of(f), pmsz.WS_CORRECT, dev)
+    gs = [fhat.clone() for _ in range(calls + 2)]
+    for g in gs[:2]:
+        pmsz.correct(f, g, xi, inplace=True, ws=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g in gs[2:]:
+        _, st = pmsz.correct(f, g, xi, inplace=True, ws=ws)
+    torch.cuda.synchronize()
+    us = (time.perf_counter() - t0) * 1e6 / calls
+    tm = pmsz.last_timing()
+    dev_us = (tm["dirs_ms"] + tm["engine_ms"]) * 1e3
+    return {"workload": "perlin 64^3 f32, 4 octaves, 4 cells, eps 1e-3, seed 1234",
+            "us_per_call": round(us, 1), "device_us": round(dev_us, 1),
+            "rounds": tm["rounds"], "device_us_per_round": round(tm["engine_ms"] * 1e3 / max(tm["rounds"], 1), 1),
+            "iterations": st["iterations"], "status": st["status"]}
+
+
 def bench_large(dev, steps):
     """1024 x 1024 x 768 binary64 Gaussian random field (k^-3), relative bound
     1e-5: one pmsz_correct per step on resident inputs, each step on its own
@@ -454,6 +482,8 @@ def main():
         log("batched vs plain on", args.batch_fields, "2D fields")
         out["batched"] = bench_batched(dev, args.batch_fields, 256)
         torch.cuda.empty_cache()
+    log("small field latency")
+    out["small_64"] = bench_small(dev, 50)
     if args.large_steps:
         log("large binary64 workload:", args.large_steps, "steps")
         out["large_f64"] = bench_large(dev, args.large_steps)

@@ -84,3 +84,32 @@ def test_blocks_reject_bad_input_and_leave_g():
     assert same_bits(host(g), fhat)
     with pytest.raises(pmsz.PmszError):
         pmsz.correct_blocks(dev(f), dev(fhat), xi, (17, 1, 1))
+
+
+def test_blocks_full_size_perlin_512():
+    """The 512^3 workload in 2 x 2 x 2 blocks, a size the oracle's block driver
+    cannot run within a test: properties that hold at any size (directions of
+    f restored everywhere, checked by the GPU verify and by the oracle at
+    sampled vertices; every value within [lb, fhat]) and fewer exchanges for
+    the relaxed schedule than for the per-round one."""
+    from test_gpu_large import sample_indices
+    f, fhat, xi = synth.large_perlin_case(device="cuda:0")
+    d = pmsz.directions(f)
+    idx = sample_indices(tuple(f.shape), 4000, 512)
+    fh, fhh = host(f), host(fhat)
+    lb, _ = oracle.bounds(fh, xi)
+    dh = host(d).reshape(-1)
+    assert np.array_equal(oracle.directions_at(fh, idx), dh[idx])
+    phases = {}
+    for per_round in (False, True):
+        g, st = pmsz.correct_blocks(f, fhat, xi, (2, 2, 2), per_round=per_round)
+        assert st["status"] == "OK", st
+        gh = host(g)
+        assert np.array_equal(oracle.directions_at(gh, idx), dh[idx])
+        assert bool(np.all(gh >= lb)) and bool(np.all(gh <= fhh))
+        rep = pmsz.verify(f, g, fhat, xi)
+        assert rep["asc_mismatch"] == 0 and rep["desc_mismatch"] == 0
+        assert rep["bound_violations"] == 0 and rep["wrong_label"] == 0
+        phases[per_round] = st["phases"]
+        del g, gh
+    assert phases[False] < phases[True]
