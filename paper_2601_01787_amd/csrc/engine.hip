@@ -94,6 +94,75 @@ __device__ __forceinline__ void grid_sync(EngineCtl* ctl, unsigned nblocks, unsi
   __syncthreads();
 }
 
+// Barrier after the start of a launch.  Release (making this block's writes
+// visible to other XCDs) costs an L2 write-back of the whole XCD, so only the
+// last block of each XCD to arrive performs it, after every block of that
+// XCD has its writes completed in L2 (each wave waits for its stores before
+// the block arrives).  Acquire (an L2 and L1 invalidate) stays per block: a
+// block's CU cache is private to it.
+struct XcdBar {
+  unsigned xcc;      // XCD this block runs on
+  unsigned members;  // blocks of the launch on it
+  unsigned nx;       // XCDs with blocks of the launch
+};
+
+__device__ __forceinline__ unsigned xcd_of_block() {
+  // hardware register XCC_ID, bits 3:0
+  return __builtin_amdgcn_s_getreg((3 << 11) | 20) & (unsigned)(kXcdSlots - 1);
+}
+
+__device__ __forceinline__ void xcd_sync(EngineCtl* ctl, const XcdBar& xb, unsigned& gen) {
+  __builtin_amdgcn_s_waitcnt(0);  // this wave's stores are complete in L2
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned target = gen + 1;
+    bool last = false;
+    const unsigned arrived = __hip_atomic_fetch_add(&ctl->xbar[xb.xcc].v, 1u, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == xb.members - 1) {
+      __hip_atomic_store(&ctl->xbar[xb.xcc].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      // every block of this XCD has arrived: write its L2 back once
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      const unsigned top =
+          __hip_atomic_fetch_add(&ctl->xtop.v, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+      if (top == xb.nx - 1) {
+        __hip_atomic_store(&ctl->xtop.v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&ctl->bar_gen.v, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        last = true;
+      }
+    }
+    if (!last) {
+      const unsigned long long t0 = wall_clock64();
+      while (relaxed_load(&ctl->bar_gen.v) != target) {
+        __builtin_amdgcn_s_sleep(1);
+        if (wall_clock64() - t0 > 400000000ull) {  // 100 MHz counter: 4 s
+          __hip_atomic_store(&ctl->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    gen = target;
+  }
+  __syncthreads();
+}
+
+// Census of the launch's blocks per XCD (the XCD counters start cleared),
+// ending with a full barrier.
+__device__ __forceinline__ XcdBar xcd_census(EngineCtl* ctl, unsigned& gen) {
+  XcdBar xb;
+  xb.xcc = xcd_of_block();
+  if (threadIdx.x == 0)
+    __hip_atomic_fetch_add(&ctl->census[xb.xcc], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  grid_sync(ctl, gridDim.x, gen);
+  xb.members = __hip_atomic_load(&ctl->census[xb.xcc], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  xb.nx = 0;
+  for (int i = 0; i < kXcdSlots; ++i)
+    xb.nx += __hip_atomic_load(&ctl->census[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) ? 1u
+                                                                                            : 0u;
+  return xb;
+}
+
 __device__ __forceinline__ bool engine_failed(EngineCtl* ctl) {
   return __hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
 }
@@ -654,8 +723,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
       if (!s.started && !s.done)
         as_global(d.act)[(E0 & 1) * tile_count(d.geo) + (tt - d.tile_base)] = 1;
     }
-    grid_sync(ctl, G, gen);
   }
+  // blocks per XCD (its closing barrier also orders the marks above)
+  const XcdBar xb = xcd_census(ctl, gen);
 
   for (long long r = 0; a.max_rounds < 0 || r < a.max_rounds; ++r) {
     if (engine_failed(ctl)) break;
@@ -729,7 +799,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     if (any_tiles)
       detect_tiles<T, sets_for<T, KIND_NEXT>()>(a, sm, red, s_tiles, s_scan, E, E0, blockIdx.x,
                                                 G);
-    grid_sync(ctl, G, gen);
+    xcd_sync(ctl, xb, gen);
     if (engine_failed(ctl)) break;
     if (tracer && r < kTraceRounds) a.trace[kTraceSlots * r + 1] = wall_clock64();
 
@@ -765,7 +835,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
         if (ed_) atomicAdd(&ctl->edits[q], ed_);
       }
     }
-    grid_sync(ctl, G, gen);
+    xcd_sync(ctl, xb, gen);
     if (engine_failed(ctl)) break;
     if (tracer && r < kTraceRounds) {
       unsigned long long* t = a.trace + kTraceSlots * r;
@@ -856,6 +926,12 @@ static hipError_t launch_t(const EngineArgs& a, hipStream_t s, int* grid_out) {
     if (e != hipSuccess) return e;
     dev_cached = dev;
   }
+  // the XCD barrier state starts cleared in every launch
+  e = engine_fill(&a.ctl->xbar[0],
+                  (size_t)((const char*)(a.ctl->census_pad + (64 - kXcdSlots)) -
+                           (const char*)&a.ctl->xbar[0]),
+                  0u, s);
+  if (e != hipSuccess) return e;
   int64_t want = a.total_tiles > a.total_segs ? a.total_tiles : a.total_segs;
   if (want < 1) want = 1;
   int64_t cap = (int64_t)per_cu * cus;

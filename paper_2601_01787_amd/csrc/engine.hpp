@@ -56,9 +56,13 @@ struct FieldDesc {
 };
 
 // Grid barrier words, each on its own 256-byte line: arrivals are spread over
-// kBarGroups group counters whose last arrivals meet at a top counter, and
-// the waiting blocks poll a generation word that no arrival touches.
+// counters whose last arrivals meet at a top counter, and the waiting blocks
+// poll a generation word that no arrival touches.  The start-of-launch
+// barrier groups blocks by block index (kBarGroups groups); every later one
+// groups them by the XCD they run on (up to kXcdSlots), so that one block per
+// XCD writes that XCD's L2 back.
 constexpr int kBarGroups = 32;
+constexpr int kXcdSlots = 16;
 struct alignas(256) BarWord {
   unsigned v;
   unsigned pad[63];
@@ -67,6 +71,11 @@ struct alignas(256) BarWord {
 struct EngineCtl {
   BarWord bar_gen;
   BarWord bar[kBarGroups + 1];  // group counters, then the top counter
+  // per-launch XCD barrier state, cleared before every launch
+  BarWord xbar[kXcdSlots];      // arrivals per XCD
+  BarWord xtop;                 // XCDs arrived
+  unsigned census[kXcdSlots];   // blocks of the launch on each XCD
+  unsigned census_pad[64 - kXcdSlots];
   unsigned long long epoch;     // rounds run since the workspace was initialised
   unsigned long long rounds;    // rounds run by the last launch
   unsigned long long edits[3];  // value changes per round (mod 3), all fields
