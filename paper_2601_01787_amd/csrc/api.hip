@@ -353,7 +353,10 @@ struct BlocksPlan {
   int64_t R = 0;
   std::vector<int64_t> org, ext, core;  // 3R, 3R, 6R
   std::vector<size_t> off_f, off_g, off_d;
-  size_t tab = 0, ctr = 0, batch = 0, total = 0;
+  size_t tab = 0, ctr = 0, hold = 0, planes_off = 0, batch = 0, total = 0;
+  std::vector<int32_t> holders;  // per axis and coordinate: up to 3 blocks, -1 padded
+  std::vector<int32_t> planes;   // (axis, coordinate) of every shared layer
+  int64_t max_plane = 0;         // vertices of the largest such layer
   std::vector<pmsz_field> fields;
   std::vector<const uint8_t*> dirs;
   BatchPlan P;
@@ -381,7 +384,41 @@ int plan_blocks(const pmsz_grid& grid, const int32_t* blocks, double xi, int64_t
   B.dirs.resize(B.R);
   B.tab = 0;
   B.ctr = align_up(sizeof(BlockCopy) * (size_t)B.R);
-  size_t at = B.ctr + align_up(sizeof(unsigned long long));
+  B.hold = B.ctr + align_up(sizeof(unsigned long long));
+  // holders of every coordinate along each axis, x then y then z
+  B.holders.assign(3 * (size_t)(n[0] + n[1] + n[2]), -1);
+  {
+    size_t base_i = 0;
+    for (int a = 0; a < 3; ++a) {
+      const int64_t b = B.nb[a];
+      for (int64_t k = 0; k < b; ++k) {
+        const int64_t s0 = k * n[a] / b, s1 = (k + 1) * n[a] / b;
+        const int64_t lo = s0 > 0 ? s0 - 1 : 0, hi = s1 < n[a] ? s1 + 1 : n[a];
+        for (int64_t c = lo; c < hi; ++c) {
+          int32_t* h = &B.holders[base_i + 3 * (size_t)c];
+          int j = 0;
+          while (j < 3 && h[j] >= 0) ++j;
+          if (j < 3) h[j] = (int32_t)k;  // blocks visited in ascending order
+        }
+      }
+      base_i += 3 * (size_t)n[a];
+    }
+    // layers held by more than one block along their axis
+    base_i = 0;
+    B.planes.clear();
+    B.max_plane = 0;
+    for (int a = 0; a < 3; ++a) {
+      for (int64_t c = 0; c < n[a]; ++c)
+        if (B.holders[base_i + 3 * (size_t)c + 1] >= 0) {
+          B.planes.push_back(a);
+          B.planes.push_back((int32_t)c);
+          B.max_plane = std::max(B.max_plane, n[0] * n[1] * n[2] / n[a]);
+        }
+      base_i += 3 * (size_t)n[a];
+    }
+  }
+  B.planes_off = B.hold + align_up(B.holders.size() * sizeof(int32_t));
+  size_t at = B.planes_off + align_up((B.planes.size() + 2) * sizeof(int32_t));
   for (int64_t id = 0; id < B.R; ++id) {
     const int64_t k[3] = {id % B.nb[0], (id / B.nb[0]) % B.nb[1], id / ((int64_t)B.nb[0] * B.nb[1])};
     int64_t cells = 1;
@@ -882,10 +919,17 @@ int pmsz_correct_blocks(const pmsz_grid* grid, const void* f, void* g, double xi
       tab[id].g = base + B.off_g[id];
     }
     void* stage;
-    if ((r = staging(t_stage, sizeof(BlockCopy) * tab.size(), &stage))) return r;
-    memcpy(stage, tab.data(), sizeof(BlockCopy) * tab.size());
-    HIP_TRY(hipMemcpyAsync(base + B.tab, stage, sizeof(BlockCopy) * tab.size(),
-                           hipMemcpyHostToDevice, s));
+    const size_t tb = sizeof(BlockCopy) * tab.size(), hb = sizeof(int32_t) * B.holders.size(),
+                 pb = sizeof(int32_t) * B.planes.size();
+    if ((r = staging(t_stage, tb + hb + pb, &stage))) return r;
+    memcpy(stage, tab.data(), tb);
+    memcpy((char*)stage + tb, B.holders.data(), hb);
+    if (pb) memcpy((char*)stage + tb + hb, B.planes.data(), pb);
+    HIP_TRY(hipMemcpyAsync(base + B.tab, stage, tb, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync(base + B.hold, (char*)stage + tb, hb, hipMemcpyHostToDevice, s));
+    if (pb)
+      HIP_TRY(hipMemcpyAsync(base + B.planes_off, (char*)stage + tb + hb, pb,
+                             hipMemcpyHostToDevice, s));
     HIP_TRY(hipStreamSynchronize(s));  // the staging buffer is reused below
   }
   // copies of f and fhat, and the directions of each copy of f
@@ -923,8 +967,16 @@ int pmsz_correct_blocks(const pmsz_grid* grid, const void* f, void* g, double xi
     unsigned long long lowered = 0;
     if ((r = hip_check(engine_fill(ctr, sizeof(unsigned long long), 0u, s)))) break;
     if ((r = hip_check(hipEventRecord(ev[0], s)))) break;
+    // owners' cores into g, then the shared vertices take their minimum
+    for (int64_t id = 0; id < B.R && r == PMSZ_OK; ++id)
+      r = hip_check(blocks_scatter_core(grid->dtype, base + B.off_g[id], &B.ext[3 * id],
+                                        &B.core[6 * id], &B.org[3 * id], g, G, s));
+    if (r != PMSZ_OK) break;
     if ((r = hip_check(blocks_exchange(grid->dtype, g, G, B.nb,
-                                       (const BlockCopy*)(base + B.tab), ctr, s))))
+                                       (const BlockCopy*)(base + B.tab),
+                                       (const int32_t*)(base + B.hold),
+                                       (const int32_t*)(base + B.planes_off),
+                                       (int32_t)(B.planes.size() / 2), B.max_plane, ctr, s))))
       break;
     if ((r = hip_check(hipEventRecord(ev[1], s)))) break;
     if ((r = hip_check(hipMemcpyAsync(&lowered, ctr, sizeof(lowered), hipMemcpyDeviceToHost, s))))

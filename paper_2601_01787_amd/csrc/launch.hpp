@@ -54,8 +54,12 @@ struct BlockCopy {
 };
 hipError_t blocks_gather(int dtype, const void* src, const Geo& G, const int64_t o[3],
                          const int64_t l[3], void* dst, hipStream_t s);
+hipError_t blocks_scatter_core(int dtype, const void* src, const int64_t l[3], const int64_t c[6],
+                               const int64_t o[3], void* dst, const Geo& G, hipStream_t s);
 hipError_t blocks_exchange(int dtype, void* g, const Geo& G, const int32_t nb[3],
-                           const BlockCopy* tab, unsigned long long* lowered, hipStream_t s);
+                           const BlockCopy* tab, const int32_t* hold, const int32_t* planes,
+                           int32_t n_planes, int64_t max_plane, unsigned long long* lowered,
+                           hipStream_t s);
 
 // edits.hip
 size_t edits_workspace_bytes(int64_t n, int64_t cap);
