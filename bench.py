@@ -362,6 +362,8 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-pool", type=int, default=4,
                     help="pre-generated fields per request class")
+    ap.add_argument("--small-calls", type=int, default=50,
+                    help="calls of the 64^3 latency leg (0 to skip)")
     ap.add_argument("--blocks", default="2x2x2,4x4x4",
                     help="block grids of the decomposed-domain leg ('' to skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -482,8 +484,9 @@ def main():
         log("batched vs plain on", args.batch_fields, "2D fields")
         out["batched"] = bench_batched(dev, args.batch_fields, 256)
         torch.cuda.empty_cache()
-    log("small field latency")
-    out["small_64"] = bench_small(dev, 50)
+    if args.small_calls:
+        log("small field latency")
+        out["small_64"] = bench_small(dev, args.small_calls)
     if args.large_steps:
         log("large binary64 workload:", args.large_steps, "steps")
         out["large_f64"] = bench_large(dev, args.large_steps)

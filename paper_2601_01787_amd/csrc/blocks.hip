@@ -126,9 +126,9 @@ __global__ __launch_bounds__(256) void k_exchange(T* __restrict__ g_out, int32_t
       const int32_t x = xyz[0], y = xyz[1], z = xyz[2];
       int32_t kx[3], ky[3], kz[3];
       for (int j = 0; j < 3; ++j) {
-        kx[j] = hx[3 * x + j];
-        ky[j] = hy[3 * y + j];
-        kz[j] = hz[3 * z + j];
+        kx[j] = hx[3 * (int64_t)x + j];
+        ky[j] = hy[3 * (int64_t)y + j];
+        kz[j] = hz[3 * (int64_t)z + j];
       }
       // shared on an earlier axis: that axis' plane handles it
       if (axis >= 1 && kx[1] >= 0) continue;
