@@ -116,6 +116,37 @@ def test_round_limit_gives_the_same_iterate(k):
     assert same_bits(host(g), g_ref)
 
 
+@pytest.mark.parametrize("k", [1, 3])
+def test_resume_from_an_iterate_gives_the_same_result(k):
+    """The iteration depends on (f, g^k) only: stopping after k rounds and
+    correcting g^k as a new fhat ends at the same field, with the rounds of
+    the two runs adding up to those of one run."""
+    f, fhat, xi = random_case((24, 31, 45), np.float32, 21)
+    g_all, st_all = pmsz.correct(dev(f), dev(fhat), xi)
+    g_k, st_k = pmsz.correct(dev(f), dev(fhat), xi, max_iters=k)
+    assert st_k["status"] == "NOT_CONVERGED"
+    g_end, st_end = pmsz.correct(dev(f), g_k, xi)
+    assert st_end["status"] == st_all["status"] == "OK"
+    assert st_k["iterations"] + st_end["iterations"] == st_all["iterations"]
+    assert st_k["steps_applied"] + st_end["steps_applied"] == st_all["steps_applied"]
+    assert same_bits(host(g_end), host(g_all))
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_crafted_stall_case_on_gpu(dtype):
+    """Two distinct values whose lower bounds merge (reading A9): the run
+    ends STALLED at the merged bound, as in the oracle."""
+    a = dtype(1e-20)
+    f = np.array([[np.nextafter(a, dtype(1)), a]], dtype=dtype)
+    lb, _ = oracle.bounds(f, 1.0)
+    fhat = np.array([[lb[0, 0], 0.0]], dtype=dtype)
+    g_ref, st_ref = oracle.correct(f, fhat, 1.0)
+    g, st = pmsz.correct(dev(f), dev(fhat), 1.0)
+    assert st_ref["status"] == "STALLED"
+    assert [st[k] for k in STAT_KEYS] == [st_ref[k] for k in STAT_KEYS]
+    assert same_bits(host(g), g_ref)
+
+
 def _hand_cases():
     with open(os.path.join(GOLDEN, "hand_examples.json")) as fh:
         return json.load(fh)["cases"]

@@ -120,3 +120,52 @@ def test_open_loop_server_results_match_alone():
     assert len(done) == len(reqs) and not bad
     summary = serve.latency_summary(done)
     assert summary["requests"] == len(reqs) and summary["p50_ms"] > 0
+
+
+def test_cancelled_field_leaves_the_others_unchanged():
+    """A field removed before it finishes (a cancelled request) stops at a
+    valid iterate (within its bounds, never above fhat), and the fields that
+    shared its steps end exactly as they do alone."""
+    import oracle
+    cases = _cases()
+    alone = _alone(cases)
+    ses = pmsz.Session(torch.float32, 8, torch.device(DEV))
+    live, bufs = {}, []
+    for i, (f, fh, xi) in enumerate(cases):
+        g = fh.clone()
+        n = pmsz.field_workspace_size(pmsz.grid_of(f))
+        buf = torch.empty(n + 256, dtype=torch.uint8, device=DEV)
+        off = (-buf.data_ptr()) % 256
+        bufs.append(buf)
+        live[ses.add(f, g, xi, buf[off:off + n])] = (i, g)
+    victim = max(range(len(cases)), key=lambda i: alone[i][1]["iterations"])
+    ses.step(1)
+    ses.sync()
+    for h, (i, g) in list(live.items()):
+        if i == victim:
+            st, done = ses.result(h)
+            assert not done
+            ses.remove(h)
+            del live[h]
+            f, fh, xi = cases[i]
+            lb, _ = oracle.bounds(f.cpu().numpy(), xi)
+            gh = g.cpu().numpy()
+            assert bool(np.all(gh >= lb)) and bool(np.all(gh <= fh.cpu().numpy()))
+    finished = {}
+    for _ in range(10000):
+        if not live:
+            break
+        ses.step(2)
+        ses.sync()
+        for h, (i, g) in list(live.items()):
+            st, done = ses.result(h)
+            if done:
+                finished[i] = (g, st)
+                ses.remove(h)
+                del live[h]
+    ses.close()
+    assert victim not in finished and len(finished) == len(cases) - 1
+    for i, (g_b, st_b) in finished.items():
+        g_a, st_a = alone[i]
+        assert torch.equal(g_a, g_b), i
+        assert [st_a[k] for k in KEYS] == [st_b[k] for k in KEYS], (i, st_a, st_b)

@@ -441,6 +441,31 @@ def test_special_cases():
     assert oracle.validate(f, f, -1.0) == "INVALID_ARG"
 
 
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+def test_crafted_stall_case(dtype):
+    """Reading A9: rounding can merge the lower bounds of two distinct values.
+    f = (b, a) with b the next value above a (the maximum at the smaller
+    index), xi = 1: both lower bounds are the smallest value at or above
+    a - 1 (a is tiny), so once the spurious maximum (vertex 1) reaches it, the
+    index tie-break still makes vertex 1 the maximum and vertex 0 the minimum,
+    both rules keep flagging vertex 1, which sits at its bound: STALLED, with
+    g at the merged bound on both vertices."""
+    a = dtype(1e-20)
+    f = np.array([[np.nextafter(a, dtype(1)), a]], dtype=dtype)
+    lb, _ = oracle.bounds(f, 1.0)
+    assert lb[0, 0] == lb[0, 1] and lb[0, 0] > dtype(-1)
+    fhat = np.array([[lb[0, 0], 0.0]], dtype=dtype)
+    g, st = oracle.correct(f, fhat, 1.0)
+    assert st["status"] == "STALLED"
+    assert st["flagged_final"] == 1 and st["stalled_flags"] == 1
+    assert g[0, 0] == lb[0, 0] and g[0, 1] == lb[0, 1]
+    # the independent loop agrees, value for value
+    adj = brute.adjacency(2, 2, 1)
+    g_slow, k_slow, st_slow = brute.slow_correct(f, fhat, oracle.xi_t(dtype, 1.0), adj)
+    assert st_slow == "STALLED" and k_slow == st["iterations"]
+    assert np.array_equal(g_slow.view(np.uint8), g.view(np.uint8))
+
+
 # ---------------------------------------------- targeted-edit variant --------
 # Each flagged vertex is lowered to the highest value at which it no longer
 # beats its rival (the worked examples of Sec. IV-A lower a spurious maximum to
