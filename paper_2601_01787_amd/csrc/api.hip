@@ -250,7 +250,7 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
     d.prop = P.edit_mode ? (void*)(base + P.prop + P.prop_off[i]) : nullptr;
   }
   const size_t up = sizeof(FieldDesc) * (size_t)n;
-  const size_t down = sizeof(EngineCtl) + kTraceBytes + sizeof(FieldIter) * (size_t)n;
+  const size_t down = kCtlHostBytes + kTraceBytes + sizeof(FieldIter) * (size_t)n;
   void* stage;
   int r = staging(t_stage, up > down ? up : down, &stage);
   if (r) return r;
@@ -285,16 +285,16 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
   HIP_TRY(hipEventRecord(tm.ev[2], s));
   // the staging buffer is reused for the results: the upload above is
   // stream-ordered before this copy, so it has been consumed
-  HIP_TRY(hipMemcpyAsync(stage, ctl, sizeof(EngineCtl), hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync((char*)stage + sizeof(EngineCtl), a.trace, kTraceBytes,
+  HIP_TRY(hipMemcpyAsync(stage, ctl, kCtlHostBytes, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync((char*)stage + kCtlHostBytes, a.trace, kTraceBytes,
                          hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync((char*)stage + sizeof(EngineCtl) + kTraceBytes, out,
+  HIP_TRY(hipMemcpyAsync((char*)stage + kCtlHostBytes + kTraceBytes, out,
                          sizeof(FieldIter) * (size_t)n, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   const EngineCtl* hc = (const EngineCtl*)stage;
-  const unsigned long long* tr = (const unsigned long long*)((char*)stage + sizeof(EngineCtl));
+  const unsigned long long* tr = (const unsigned long long*)((char*)stage + kCtlHostBytes);
   const FieldIter* hs =
-      (const FieldIter*)((char*)stage + sizeof(EngineCtl) + kTraceBytes);
+      (const FieldIter*)((char*)stage + kCtlHostBytes + kTraceBytes);
   if (hc->error) return fail(PMSZ_ERR_DEVICE, "grid barrier timed out in the correction engine");
   float el[2];
   for (int k = 0; k < 2; ++k) HIP_TRY(hipEventElapsedTime(&el[k], tm.ev[k], tm.ev[k + 1]));
@@ -1117,7 +1117,7 @@ int pmsz_session_step(pmsz_session* S, int64_t max_rounds) {
   void *up, *down;
   int r = staging(S->up, sizeof(FieldDesc) * (size_t)n, &up);
   if (r) return r;
-  r = staging(S->down, sizeof(EngineCtl) + sizeof(FieldIter) * (size_t)n, &down);
+  r = staging(S->down, kCtlHostBytes + sizeof(FieldIter) * (size_t)n, &down);
   if (r) return r;
   memcpy(up, fd.data(), sizeof(FieldDesc) * (size_t)n);
   HIP_TRY(hipMemcpyAsync(S->ws + S->desc_off, up, sizeof(FieldDesc) * (size_t)n,
@@ -1134,8 +1134,8 @@ int pmsz_session_step(pmsz_session* S, int64_t max_rounds) {
   a.trace = nullptr;
   int grid = 0;
   HIP_TRY(engine_launch(S->dtype, a, S->stream, &grid));
-  HIP_TRY(hipMemcpyAsync(down, S->ws, sizeof(EngineCtl), hipMemcpyDeviceToHost, S->stream));
-  HIP_TRY(hipMemcpyAsync((char*)down + sizeof(EngineCtl), a.out, sizeof(FieldIter) * (size_t)n,
+  HIP_TRY(hipMemcpyAsync(down, S->ws, kCtlHostBytes, hipMemcpyDeviceToHost, S->stream));
+  HIP_TRY(hipMemcpyAsync((char*)down + kCtlHostBytes, a.out, sizeof(FieldIter) * (size_t)n,
                          hipMemcpyDeviceToHost, S->stream));
   HIP_TRY(hipEventRecord(S->ev, S->stream));
   S->last.tiles = tiles;
@@ -1151,7 +1151,7 @@ int pmsz_session_sync(pmsz_session* S, int32_t* n_done) {
     HIP_TRY(hipEventSynchronize(S->ev));
     S->pending = false;
     const EngineCtl* hc = (const EngineCtl*)S->down.p;
-    const FieldIter* hs = (const FieldIter*)((char*)S->down.p + sizeof(EngineCtl));
+    const FieldIter* hs = (const FieldIter*)((char*)S->down.p + kCtlHostBytes);
     if (hc->error) return fail(PMSZ_ERR_DEVICE, "grid barrier timed out in the correction engine");
     S->epoch = hc->epoch;
     S->last.rounds = (int64_t)hc->rounds;

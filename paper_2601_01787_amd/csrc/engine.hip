@@ -98,17 +98,40 @@ __device__ __forceinline__ void grid_sync(EngineCtl* ctl, unsigned nblocks, unsi
 // visible to other XCDs) costs an L2 write-back of the whole XCD, so only the
 // last block of each XCD to arrive performs it, after every block of that
 // XCD has its writes completed in L2 (each wave waits for its stores before
-// the block arrives).  Acquire (an L2 and L1 invalidate) stays per block: a
-// block's CU cache is private to it.
+// the block arrives).  Acquire (an invalidate of the compute unit's cache and
+// of the XCD's L2) is needed once per compute unit: the blocks resident on
+// one unit share its cache, so the first of them past the generation flip
+// invalidates and the others wait until it has.  The L1-only invalidate
+// does nothing outside thread-group-split mode, and an invalidate per block
+// queues 128 of them per XCD (measured: 10.7 us per barrier at 1024 blocks
+// against 6.2 us with one per unit).
 struct XcdBar {
   unsigned xcc;      // XCD this block runs on
   unsigned members;  // blocks of the launch on it
   unsigned nx;       // XCDs with blocks of the launch
+  unsigned cu;       // compute-unit slot: XCD x 256 + HW_ID bits 15:8
 };
 
 __device__ __forceinline__ unsigned xcd_of_block() {
   // hardware register XCC_ID, bits 3:0
   return __builtin_amdgcn_s_getreg((3 << 11) | 20) & (unsigned)(kXcdSlots - 1);
+}
+__device__ __forceinline__ unsigned cu_of_block(unsigned xcc) {
+  // hardware register HW_ID, bits 15:8 (CU_ID, SH_ID, SE_ID)
+  return xcc * 256u + (__builtin_amdgcn_s_getreg((7 << 11) | (8 << 6) | 4) & 255u);
+}
+
+// Bounded spin until *p == target: after ~4 s the block records an error and
+// the launch winds down instead of hanging.
+__device__ __forceinline__ void spin_until(EngineCtl* ctl, const unsigned* p, unsigned target) {
+  const unsigned long long t0 = wall_clock64();
+  while (relaxed_load(p) != target) {
+    __builtin_amdgcn_s_sleep(1);
+    if (wall_clock64() - t0 > 400000000ull) {  // 100 MHz counter: 4 s
+      __hip_atomic_store(&ctl->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+  }
 }
 
 __device__ __forceinline__ void xcd_sync(EngineCtl* ctl, const XcdBar& xb, unsigned& gen) {
@@ -131,17 +154,19 @@ __device__ __forceinline__ void xcd_sync(EngineCtl* ctl, const XcdBar& xb, unsig
         last = true;
       }
     }
-    if (!last) {
-      const unsigned long long t0 = wall_clock64();
-      while (relaxed_load(&ctl->bar_gen.v) != target) {
-        __builtin_amdgcn_s_sleep(1);
-        if (wall_clock64() - t0 > 400000000ull) {  // 100 MHz counter: 4 s
-          __hip_atomic_store(&ctl->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          break;
-        }
-      }
+    if (!last) spin_until(ctl, &ctl->bar_gen.v, target);
+    // one invalidate per compute unit; generations only grow within a launch
+    // and the slots are cleared before it, so a claim never matches a stale one
+    const unsigned old = __hip_atomic_exchange(&ctl->cu_claim[xb.cu], target, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+    if (old != target) {
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      __builtin_amdgcn_s_waitcnt(0);  // the invalidate has completed
+      __hip_atomic_store(&ctl->cu_done[xb.cu], target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      spin_until(ctl, &ctl->cu_done[xb.cu], target);
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     gen = target;
   }
   __syncthreads();
@@ -152,6 +177,7 @@ __device__ __forceinline__ void xcd_sync(EngineCtl* ctl, const XcdBar& xb, unsig
 __device__ __forceinline__ XcdBar xcd_census(EngineCtl* ctl, unsigned& gen) {
   XcdBar xb;
   xb.xcc = xcd_of_block();
+  xb.cu = cu_of_block(xb.xcc);
   if (threadIdx.x == 0)
     __hip_atomic_fetch_add(&ctl->census[xb.xcc], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   grid_sync(ctl, gridDim.x, gen);
@@ -926,11 +952,8 @@ static hipError_t launch_t(const EngineArgs& a, hipStream_t s, int* grid_out) {
     if (e != hipSuccess) return e;
     dev_cached = dev;
   }
-  // the XCD barrier state starts cleared in every launch
-  e = engine_fill(&a.ctl->xbar[0],
-                  (size_t)((const char*)(a.ctl->census_pad + (64 - kXcdSlots)) -
-                           (const char*)&a.ctl->xbar[0]),
-                  0u, s);
+  // the XCD and compute-unit barrier state starts cleared in every launch
+  e = engine_fill(&a.ctl->xbar[0], sizeof(EngineCtl) - offsetof(EngineCtl, xbar), 0u, s);
   if (e != hipSuccess) return e;
   int64_t want = a.total_tiles > a.total_segs ? a.total_tiles : a.total_segs;
   if (want < 1) want = 1;

@@ -7,6 +7,8 @@
 // field, a batch run to completion, and resumable serving steps.
 #pragma once
 
+#include <stddef.h>
+
 #include "tiles.hpp"
 
 namespace pmsz {
@@ -60,9 +62,12 @@ struct FieldDesc {
 // poll a generation word that no arrival touches.  The start-of-launch
 // barrier groups blocks by block index (kBarGroups groups); every later one
 // groups them by the XCD they run on (up to kXcdSlots), so that one block per
-// XCD writes that XCD's L2 back.
+// XCD writes that XCD's L2 back, and elects one block per compute unit
+// (kCuSlots: XCD x the 8-bit unit id of the hardware register HW_ID) to
+// invalidate that unit's caches.
 constexpr int kBarGroups = 32;
 constexpr int kXcdSlots = 16;
+constexpr int kCuSlots = kXcdSlots * 256;
 struct alignas(256) BarWord {
   unsigned v;
   unsigned pad[63];
@@ -71,11 +76,7 @@ struct alignas(256) BarWord {
 struct EngineCtl {
   BarWord bar_gen;
   BarWord bar[kBarGroups + 1];  // group counters, then the top counter
-  // per-launch XCD barrier state, cleared before every launch
-  BarWord xbar[kXcdSlots];      // arrivals per XCD
-  BarWord xtop;                 // XCDs arrived
-  unsigned census[kXcdSlots];   // blocks of the launch on each XCD
-  unsigned census_pad[64 - kXcdSlots];
+  // results of a launch (the host reads back the first kCtlHostBytes bytes)
   unsigned long long epoch;     // rounds run since the workspace was initialised
   unsigned long long rounds;    // rounds run by the last launch
   unsigned long long edits[3];  // value changes per round (mod 3), all fields
@@ -84,7 +85,15 @@ struct EngineCtl {
   unsigned long long flagged[3];  // flagged vertices per round (mod 3), all fields
   int error;                    // a grid barrier timed out
   int pad;
+  // per-launch barrier state, cleared before every launch (from xbar to the end)
+  BarWord xbar[kXcdSlots];      // arrivals per XCD
+  BarWord xtop;                 // XCDs arrived
+  unsigned census[kXcdSlots];   // blocks of the launch on each XCD
+  unsigned census_pad[64 - kXcdSlots];
+  unsigned cu_claim[kCuSlots];  // last barrier generation claimed on each unit
+  unsigned cu_done[kCuSlots];   // last generation whose invalidate completed
 };
+constexpr size_t kCtlHostBytes = offsetof(EngineCtl, xbar);
 
 struct EngineArgs {
   const FieldDesc* fd;
