@@ -213,7 +213,7 @@ __device__ __forceinline__ int field_of_seg(const FieldDesc* fd, int nf, int64_t
 
 // The loop decision of Sec. IV-A: state at the start of the next round from
 // the state at the start of this round and this round's counters.
-__device__ __forceinline__ FieldIter next_state(FieldIter s, const FieldCtr& c,
+__device__ __forceinline__ FieldIter next_state(FieldIter s, const CtrSum& c,
                                                 int64_t max_iters) {
   if (s.done) return s;
   const bool first = !s.started;
@@ -272,19 +272,64 @@ __device__ __forceinline__ void store_iter(gptr<FieldIter> p, const FieldIter& s
   p->pad = s.pad;
 }
 __device__ __forceinline__ void clear_ctr(gptr<FieldCtr> c) {
-  c->mism = c->nflag = c->at_lb = c->bad_nf = c->bad_b = c->swept = c->nlist = 0;
+  for (int k = 0; k < kCtrSlots; ++k) {
+    const gptr<CtrSlot> x = &c->s[k];
+    x->mism = x->nflag = x->at_lb = x->bad_nf = x->bad_b = x->swept = x->nlist = 0;
+  }
 }
 
-// Counters of a finished round (read after the barrier that completed them).
-__device__ __forceinline__ FieldCtr load_ctr(gptr<const FieldCtr> c) {
-  FieldCtr r;
-  r.mism = relaxed_load(&c->mism);
-  r.nflag = relaxed_load(&c->nflag);
-  r.at_lb = relaxed_load(&c->at_lb);
-  r.bad_nf = relaxed_load(&c->bad_nf);
-  r.bad_b = relaxed_load(&c->bad_b);
-  r.swept = relaxed_load(&c->swept);
+// Counter slot of this block.
+__device__ __forceinline__ int ctr_slot() { return (int)(blockIdx.x % (unsigned)kCtrSlots); }
+
+// Counters of a finished round, summed over the slots.  They are read only
+// after the grid barrier that completed them, whose acquire invalidated this
+// unit's caches, so plain loads see the final values; plain loads also let
+// the unit's cache serve the blocks that share it (every block of the grid
+// reads the same few lines after each barrier, and one L2 channel serves
+// each line).
+__device__ __forceinline__ CtrSum load_ctr(gptr<const FieldCtr> c) {
+  CtrSum r{0, 0, 0, 0, 0, 0, 0};
+#pragma unroll 4  // (fully unrolled, the 56 loads in flight spill registers)
+  for (int k = 0; k < kCtrSlots; ++k) {
+    const gptr<const CtrSlot> x = &c->s[k];
+    r.mism += x->mism;
+    r.nflag += x->nflag;
+    r.at_lb += x->at_lb;
+    r.bad_nf += x->bad_nf;
+    r.bad_b += x->bad_b;
+    r.swept += x->swept;
+    r.nlist += x->nlist;
+  }
   return r;
+}
+// Mismatches of a finished round (the apply pass's only test in later rounds).
+__device__ __forceinline__ unsigned long long load_mism(gptr<const FieldCtr> c) {
+  unsigned long long m = 0;
+#pragma unroll
+  for (int k = 0; k < kCtrSlots; ++k) m += c->s[k].mism;
+  return m;
+}
+
+// Round totals over all fields, summed over the slots (read after the barrier
+// that completed them, like the counters).
+__device__ __forceinline__ RoundTot load_tot(const EngineCtl* ctl, int q) {
+  RoundTot r{0, 0, 0, 0, {0, 0, 0, 0}};
+  const gptr<const RoundTot> t = as_global(&ctl->tot[q][0]);
+#pragma unroll
+  for (int k = 0; k < kCtrSlots; ++k) {
+    r.edits += t[k].edits;
+    r.swept += t[k].swept;
+    r.sparse += t[k].sparse;
+    r.flagged += t[k].flagged;
+  }
+  return r;
+}
+__device__ __forceinline__ unsigned long long load_edits(const EngineCtl* ctl, int q) {
+  const gptr<const RoundTot> t = as_global(&ctl->tot[q][0]);
+  unsigned long long e = 0;
+#pragma unroll
+  for (int k = 0; k < kCtrSlots; ++k) e += t[k].edits;
+  return e;
 }
 
 // State of a field at the start of round E.
@@ -319,14 +364,24 @@ __device__ __forceinline__ TileBox box_of(const TileGeo& G, int32_t t) {
 }
 
 // Plain byte stores into the field's activity bytes of the next round: every
-// writer stores the same value.
+// writer stores the same value.  The box spans at most two tiles per axis
+// (tile boundaries lie at least two vertices apart), so its tiles are the
+// eight corner combinations, duplicates included; all eight bytes are loaded
+// before any store, so the loads overlap instead of forming a chain of
+// dependent round trips (a store may alias a later load of the same array).
 __device__ __forceinline__ void mark_box(const FieldDesc& d, const TileBox& b, gptr<uint8_t> nxt) {
-  for (int32_t bz = b.z0; bz <= b.z1; ++bz)
-    for (int32_t by = b.y0; by <= b.y1; ++by)
-      for (int32_t bx = b.x0; bx <= b.x1; ++bx) {
-        const int32_t T = bx + d.geo.tiles_x * (by + d.geo.tiles_y * bz);
-        if (!nxt[T]) nxt[T] = 1;
-      }
+  int32_t idx[8];
+  uint8_t cur[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const int32_t bx = (k & 1) ? b.x1 : b.x0, by = (k & 2) ? b.y1 : b.y0,
+                  bz = (k & 4) ? b.z1 : b.z0;
+    idx[k] = bx + d.geo.tiles_x * (by + d.geo.tiles_y * bz);
+    cur[k] = nxt[idx[k]];
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k)
+    if (!cur[k]) nxt[idx[k]] = 1;
 }
 
 // Exclusive prefix sum over the block; *total receives the sum (all threads).
@@ -363,12 +418,23 @@ __device__ __forceinline__ int block_scan(int v, int* sh, int* total) {
 // ---------------------------------------------------------------------------
 
 // Examinations needed by round E of a field in a sparse round, or -1 when the
-// round sweeps its active tiles (first round, or too many targets listed).
+// round sweeps its active tiles (first round, or a slot's slice of the target
+// list overflowed).  cnt (nullable) receives the targets listed per slot.
 __device__ __forceinline__ long long sparse_items(const FieldDesc& d, const FieldIter& s,
-                                                  unsigned long long E) {
+                                                  unsigned long long E, uint32_t* cnt = nullptr) {
   if (!s.started || s.done) return -1;
-  const unsigned long long n = relaxed_load(&as_global((const FieldState*)d.st)->c[(E + 2) % 3].nlist);
-  if (n > (unsigned long long)d.list_cap) return -1;
+  const gptr<const FieldCtr> c = &as_global((const FieldState*)d.st)->c[(E + 2) % 3];
+  const unsigned long long cap = (unsigned long long)list_slice(d.list_cap);
+  unsigned long long n = 0;
+  bool over = false;
+#pragma unroll
+  for (int k = 0; k < kCtrSlots; ++k) {
+    const unsigned long long nk = c->s[k].nlist;
+    over |= nk > cap;
+    n += nk;
+    if (cnt) cnt[k] = (uint32_t)nk;
+  }
+  if (over) return -1;
   return (long long)n * (d.geo.ndim == 3 ? 15 : 7);
 }
 
@@ -430,20 +496,32 @@ __device__ __forceinline__ void gather_dirs(const TileGeo& G, gptr<const T> g, i
 }
 
 // Examination m of a sparse round: neighbour m % per of the target m / per
-// listed by the previous round's apply pass.  Returns the targets the
-// examined vertex flags (-1: none) and its number of mismatches.
+// listed by the previous round's apply pass (cnt: targets per list slice).
+// Returns the targets the examined vertex flags (-1: none) and its number of
+// mismatches.
 struct Exam {
   int32_t ta, td;  // ascending-rule and descending-rule targets
   unsigned n;      // mismatches found (0, 1 or 2)
 };
 
 template <class T>
-__device__ __forceinline__ Exam sparse_examine(const FieldDesc& d, uint32_t m) {
+__device__ __forceinline__ Exam sparse_examine(const FieldDesc& d, uint32_t m,
+                                               const uint32_t* cnt) {
   const TileGeo& G = d.geo;
   const bool three = G.ndim == 3;
   const uint32_t k = three ? m / 15u : m / 7u;
   const uint32_t j = m - k * (three ? 15u : 7u);
-  const int32_t t = (int32_t)as_global(d.list)[k];
+  // the slice holding the k-th listed target
+  uint32_t kk = k, at = 0;
+  const uint32_t slice = (uint32_t)list_slice(d.list_cap);
+#pragma unroll
+  for (int i = 0; i < kCtrSlots - 1; ++i) {
+    const uint32_t ci = cnt[i];
+    const bool past = at == (uint32_t)i * slice && kk >= ci;
+    kk -= past ? ci : 0u;
+    at += past ? slice : 0u;
+  }
+  const int32_t t = (int32_t)as_global(d.list)[at + kk];
   // the vertex itself, then its neighbours: 3D codes 1..7, 9..15; 2D 1..3, 9..11
   const int code = three ? (j < 8 ? (int)j : (int)j + 1) : (j < 4 ? (int)j : (int)j + 5);
   // the neighbour's offset
@@ -555,6 +633,8 @@ __device__ __forceinline__ void apply_segment(const FieldDesc& d, int32_t w0, in
                                               unsigned long long& edits) {
   constexpr int kPer = 16;
   const int tid = threadIdx.x;
+  const int slot = ctr_slot();
+  const long long slice = list_slice(d.list_cap);
   // thread t owns words w0 + t + 256 k: each load instruction reads 256
   // consecutive words across the block
   const gptr<uint32_t> bm = as_global(d.bm);
@@ -592,11 +672,11 @@ __device__ __forceinline__ void apply_segment(const FieldDesc& d, int32_t w0, in
       }
     }
     const int n = total - base < kApplyCap ? total - base : kApplyCap;
-    // room in the field's target list for this pass (next round's sparse
-    // examination); entries past the capacity are dropped, and the count
-    // then sends the next round to a tile sweep
-    if (edit && tid == 0)
-      *lbase_sh = (long long)__hip_atomic_fetch_add(&cq->nlist, (unsigned long long)n,
+    // room in this block's slice of the field's target list for this pass
+    // (next round's sparse examination); entries past the slice are
+    // dropped, and the count then sends the next round to a tile sweep
+    if (edit && tid == 0 && n > 0)
+      *lbase_sh = (long long)__hip_atomic_fetch_add(&cq->s[slot].nlist, (unsigned long long)n,
                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     lds_barrier();
     const long long lbase = edit ? *lbase_sh : 0;
@@ -622,7 +702,7 @@ __device__ __forceinline__ void apply_segment(const FieldDesc& d, int32_t w0, in
       at_lb += above ? 0u : 1u;
       if (edit) {
         mark_box(d, box_of(d.geo, t), nxt);
-        if (lbase + j < d.list_cap) tlist[lbase + j] = (uint32_t)t;
+        if (lbase + j < slice) tlist[(int64_t)slot * slice + lbase + j] = (uint32_t)t;
       }
     }
     lds_barrier();
@@ -634,7 +714,7 @@ __device__ __forceinline__ void apply_segment(const FieldDesc& d, int32_t w0, in
 // read and cleared 256 at a time, one per thread, and the active ones
 // listed); SETS planes are in flight per tile march.
 // A block's detect counts for one field, added once per field change.
-__device__ __forceinline__ void flush_counts(gptr<FieldCtr> c, unsigned long long m,
+__device__ __forceinline__ void flush_counts(gptr<CtrSlot> c, unsigned long long m,
                                              unsigned long long nf, unsigned long long nb,
                                              unsigned long long sw, unsigned long long* all_sw) {
   if (m) relaxed_add(&c->mism, m);
@@ -685,8 +765,8 @@ __device__ void detect_tiles(const EngineArgs& a, TileLds<T>& sm, unsigned long 
       const FieldDesc& d = a.fd[fi];
       if (tid == 0 && fi != cur) {
         if (cur >= 0) {
-          flush_counts(&as_global(a.fd[cur].st)->c[q], acc_m, acc_nf, acc_nb, acc_sw,
-                       &ctl->swept[q]);
+          flush_counts(&as_global(a.fd[cur].st)->c[q].s[ctr_slot()], acc_m, acc_nf, acc_nb,
+                       acc_sw, &ctl->tot[q][ctr_slot()].swept);
         }
         acc_m = acc_nf = acc_nb = acc_sw = 0;
         cur = fi;
@@ -717,7 +797,8 @@ __device__ void detect_tiles(const EngineArgs& a, TileLds<T>& sm, unsigned long 
     __syncthreads();  // s_tiles is rewritten by the next batch
   }
   if (tid == 0 && cur >= 0) {
-    flush_counts(&as_global(a.fd[cur].st)->c[q], acc_m, acc_nf, acc_nb, acc_sw, &ctl->swept[q]);
+    flush_counts(&as_global(a.fd[cur].st)->c[q].s[ctr_slot()], acc_m, acc_nf, acc_nb, acc_sw,
+                 &ctl->tot[q][ctr_slot()].swept);
   }
 }
 
@@ -727,6 +808,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
   __shared__ unsigned long long red[4];
   __shared__ uint16_t s_tiles[256];
   __shared__ long long s_pre[256];
+  __shared__ uint32_t s_slot[256 * kCtrSlots];
   __shared__ long long s_lbase;
   __shared__ uint32_t s_list[kApplyCap];
   __shared__ int s_scan[4];
@@ -767,11 +849,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
         if (E > E0) store_iter(&st->s[p], state_at(d, E, E0));
         clear_ctr(&st->c[qn]);
       }
-      if (tid == 0) {
-        ctl->edits[qn] = 0;
-        ctl->swept[qn] = 0;
-        ctl->sparse[qn] = 0;
-        ctl->flagged[qn] = 0;
+      if (tid < kCtrSlots) {
+        ctl->tot[qn][tid].edits = 0;
+        ctl->tot[qn][tid].swept = 0;
+        ctl->tot[qn][tid].sparse = 0;
+        ctl->tot[qn][tid].flagged = 0;
       }
     }
 
@@ -787,26 +869,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
       if (fi < a.nf) {
         const FieldDesc& d = a.fd[fi];
         const FieldIter s = state_at(d, E, E0);
-        items = sparse_items(d, s, E);
+        items = sparse_items(d, s, E, s_slot + tid * kCtrSlots);
         if (items < 0) {
           sweeps = !s.done;
           items = 0;
         }
         if (items > 0 && blockIdx.x == 0) {
-          relaxed_add(&as_global(d.st)->c[q].swept, (unsigned long long)items);
-          atomicAdd(&ctl->swept[q], (unsigned long long)items);
-          atomicAdd(&ctl->sparse[q], (unsigned long long)items);
+          relaxed_add(&as_global(d.st)->c[q].s[0].swept, (unsigned long long)items);
+          atomicAdd(&ctl->tot[q][0].swept, (unsigned long long)items);
+          atomicAdd(&ctl->tot[q][0].sparse, (unsigned long long)items);
         }
       }
       any_tiles |= __syncthreads_or(sweeps);
       const long long total = block_prefix(items, s_pre);
       const int nfc = a.nf - f0 < 256 ? a.nf - f0 : 256;
       FieldAcc mism;
-      auto mism_ptr = [&](int f) { return &as_global(a.fd[f].st)->c[q].mism; };
+      auto mism_ptr = [&](int f) { return &as_global(a.fd[f].st)->c[q].s[ctr_slot()].mism; };
       for (long long m = (long long)blockIdx.x * 256 + tid; m < total; m += (long long)G * 256) {
         const int lo = prefix_find(s_pre, nfc, m);
         const int fx = f0 + lo;
-        const Exam ex = sparse_examine<T>(a.fd[fx], (uint32_t)(m - (lo ? s_pre[lo - 1] : 0)));
+        const Exam ex = sparse_examine<T>(a.fd[fx], (uint32_t)(m - (lo ? s_pre[lo - 1] : 0)),
+                                          s_slot + lo * kCtrSlots);
         acc_add(mism, fx, ex.n, mism_ptr);
         // fire-and-forget flags: the apply pass reads them after the barrier
         const gptr<uint32_t> bm = as_global(a.fd[fx].bm);
@@ -837,8 +920,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
       const FieldIter s = load_iter(&as_global(d.st)->s[p]);  // persisted by block 0 before the barrier
       const gptr<FieldCtr> cq = &as_global(d.st)->c[q];
       const gptr<uint8_t> nxt = as_global(d.act) + (p ^ 1) * tile_count(d.geo);
-      const unsigned long long mism = relaxed_load(&cq->mism);
-      const bool bad = !s.started && (relaxed_load(&cq->bad_nf) || relaxed_load(&cq->bad_b));
+      const unsigned long long mism = load_mism(cq);
+      bool bad = false;
+      if (!s.started) {
+        const CtrSum cs = load_ctr(cq);
+        bad = cs.bad_nf || cs.bad_b;
+      }
       if (s.done || bad || mism == 0) continue;
       const bool edit = (long long)s.k < d.max_iters;
       const int32_t w0 = (int32_t)((sg - d.seg_base) * kSegWords);
@@ -853,25 +940,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
       if (tid == 0) {
         const unsigned long long nf_ = unpack3(tot, 0), al_ = unpack3(tot, 1),
                                  ed_ = unpack3(tot, 2);
+        const int slot = ctr_slot();
         if (nf_) {
-          relaxed_add(&cq->nflag, nf_);
-          atomicAdd(&ctl->flagged[q], nf_);
+          relaxed_add(&cq->s[slot].nflag, nf_);
+          atomicAdd(&ctl->tot[q][slot].flagged, nf_);
         }
-        if (al_) relaxed_add(&cq->at_lb, al_);
-        if (ed_) atomicAdd(&ctl->edits[q], ed_);
+        if (al_) relaxed_add(&cq->s[slot].at_lb, al_);
+        if (ed_) atomicAdd(&ctl->tot[q][slot].edits, ed_);
       }
     }
     xcd_sync(ctl, xb, gen);
     if (engine_failed(ctl)) break;
     if (tracer && r < kTraceRounds) {
       unsigned long long* t = a.trace + kTraceSlots * r;
+      const RoundTot rt = load_tot(ctl, q);
       t[2] = wall_clock64();
-      t[3] = relaxed_load(&ctl->swept[q]);
-      t[4] = relaxed_load(&ctl->flagged[q]);
-      t[5] = relaxed_load(&ctl->edits[q]);
-      t[6] = relaxed_load(&ctl->sparse[q]);
+      t[3] = rt.swept;
+      t[4] = rt.flagged;
+      t[5] = rt.edits;
+      t[6] = rt.sparse;
     }
-    const unsigned long long edited = relaxed_load(&ctl->edits[q]);
+    const unsigned long long edited = load_edits(ctl, q);
     ++E;
     if (edited == 0) break;
   }

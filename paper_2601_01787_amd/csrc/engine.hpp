@@ -24,10 +24,23 @@ struct FieldIter {
 };
 
 // Counters of one round.  Triple-buffered by round index mod 3: round E adds
-// to c[E%3], reads c[(E-1)%3], and clears c[(E+1)%3].
-struct FieldCtr {
+// to c[E%3], reads c[(E-1)%3], and clears c[(E+1)%3].  Each counter is spread
+// over kCtrSlots slots on separate 128-byte lines (block b adds to slot
+// b % kCtrSlots) and a count is the sum over the slots: atomics on one line
+// serialise at about 11 ns each, so one line shared by 1024 blocks cost
+// 10-40 us per round.
+constexpr int kCtrSlots = 8;
+struct alignas(128) CtrSlot {
   unsigned long long mism, nflag, at_lb, bad_nf, bad_b, swept;
-  unsigned long long nlist;  // targets the apply pass appended to the target list
+  unsigned long long nlist;  // targets this slot's blocks appended to the target list
+  unsigned long long pad;
+};
+struct FieldCtr {
+  CtrSlot s[kCtrSlots];
+};
+// Sums over the slots.
+struct CtrSum {
+  unsigned long long mism, nflag, at_lb, bad_nf, bad_b, swept, nlist;
 };
 
 struct FieldState {
@@ -44,7 +57,8 @@ struct FieldDesc {
   FieldState* st;     // iteration state and counters of this field
   uint8_t* act;       // per tile and round parity: examine in that round
                       // (act[p * tiles + tile])
-  uint32_t* list;     // targets of the last apply pass (list_cap entries)
+  uint32_t* list;     // targets of the last apply pass (list_cap entries, in
+                      // kCtrSlots slices of list_cap / kCtrSlots, one per slot)
   void* prop;         // targeted edit: per-vertex proposal keys; nullptr for
                       // the halving edit
   TileGeo geo;
@@ -73,16 +87,20 @@ struct alignas(256) BarWord {
   unsigned pad[63];
 };
 
+struct alignas(128) RoundTot {
+  unsigned long long edits;    // value changes
+  unsigned long long swept;    // vertices examined
+  unsigned long long sparse;   // of which by sparse examination
+  unsigned long long flagged;  // flagged vertices
+  unsigned long long pad[4];
+};
+
 struct EngineCtl {
   BarWord bar_gen;
   BarWord bar[kBarGroups + 1];  // group counters, then the top counter
   // results of a launch (the host reads back the first kCtlHostBytes bytes)
   unsigned long long epoch;     // rounds run since the workspace was initialised
   unsigned long long rounds;    // rounds run by the last launch
-  unsigned long long edits[3];  // value changes per round (mod 3), all fields
-  unsigned long long swept[3];  // vertices examined per round (mod 3), all fields
-  unsigned long long sparse[3]; // of which by sparse examination
-  unsigned long long flagged[3];  // flagged vertices per round (mod 3), all fields
   int error;                    // a grid barrier timed out
   int pad;
   // per-launch barrier state, cleared before every launch (from xbar to the end)
@@ -92,6 +110,8 @@ struct EngineCtl {
   unsigned census_pad[64 - kXcdSlots];
   unsigned cu_claim[kCuSlots];  // last barrier generation claimed on each unit
   unsigned cu_done[kCuSlots];   // last generation whose invalidate completed
+  // totals over all fields per round (mod 3), spread over slots like FieldCtr
+  RoundTot tot[3][kCtrSlots];
 };
 constexpr size_t kCtlHostBytes = offsetof(EngineCtl, xbar);
 
@@ -129,10 +149,13 @@ hipError_t engine_zero(void* p, size_t bytes, hipStream_t s);
 // Fill `bytes` bytes (multiple of 4, 4-byte aligned) with the 32-bit word v.
 hipError_t engine_fill(void* p, size_t bytes, uint32_t v, hipStream_t s);
 
-// Target list: when a round flags at most this many vertices, the next
-// round examines the Freudenthal neighbours of exactly those vertices
-// instead of sweeping tiles.
+// Target list: the apply pass lists its targets, each block in the slice of
+// its counter slot (list_capacity / kCtrSlots entries); when no slice
+// overflowed, the next round examines the Freudenthal neighbours of exactly
+// those vertices instead of sweeping tiles.
 inline int32_t list_capacity(const TileGeo& G) { return G.n / 256 + 1024; }
+// Entries of one counter slot's slice of the target list.
+__host__ __device__ inline int32_t list_slice(int32_t cap) { return cap / kCtrSlots; }
 
 // Per-field workspace: [FieldState][activity bytes x 2][bitmap][target list]
 // [directions].
