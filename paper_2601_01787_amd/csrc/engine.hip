@@ -567,8 +567,9 @@ __device__ __forceinline__ Exam sparse_examine(const FieldDesc& d, uint32_t m,
   return ex;
 }
 
-// Per-thread running count for one field at a time; `flush` adds a wave's
-// counts with one atomic when its lanes agree on the field.
+// Per-thread running count for one field at a time, added to the field's
+// counter when the thread moves to another field; `acc_flush` then adds the
+// rest with one atomic per block when all threads agree on the field.
 struct FieldAcc {
   int f = -1;
   unsigned long long n = 0;
@@ -582,14 +583,33 @@ __device__ __forceinline__ void acc_add(FieldAcc& acc, int fi, unsigned long lon
   }
   acc.n += v;
 }
+// Whole block.  sf (4 ints) and sn (4 counts) are LDS scratch; the caller
+// synchronises the block before reusing them.
 template <class Ptr>
-__device__ __forceinline__ void acc_flush(FieldAcc& acc, Ptr ptr) {  // whole waves
-  const int f0 = __shfl(acc.f, 0, 64);
-  if (__all(acc.f == f0 || acc.n == 0)) {
-    const unsigned long long w = wave_sum(acc.n);
-    if ((threadIdx.x & 63) == 0 && w) relaxed_add(ptr(f0), w);
-  } else if (acc.n) {
-    relaxed_add(ptr(acc.f), acc.n);
+__device__ __forceinline__ void acc_flush(FieldAcc& acc, Ptr ptr, int* sf,
+                                          unsigned long long* sn) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int f0 = acc.n ? acc.f : -1;
+  for (int off = 32; off > 0; off >>= 1) f0 = max(f0, __shfl_xor(f0, off, 64));
+  const bool agree = __all(acc.f == f0 || acc.n == 0);
+  if (!agree && acc.n) relaxed_add(ptr(acc.f), acc.n);
+  const unsigned long long w = wave_sum(agree ? acc.n : 0ull);
+  if (lane == 0) {
+    sf[wave] = (agree && w) ? f0 : -1;
+    sn[wave] = w;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < 4; ++i) {
+      if (sf[i] < 0) continue;
+      unsigned long long t = sn[i];
+      for (int j = i + 1; j < 4; ++j)
+        if (sf[j] == sf[i]) {
+          t += sn[j];
+          sf[j] = -1;
+        }
+      relaxed_add(ptr(sf[i]), t);
+    }
   }
   acc.f = -1;
   acc.n = 0;
@@ -900,7 +920,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
           __hip_atomic_fetch_or(bm + (ex.td >> 5), 1u << (ex.td & 31), __ATOMIC_RELAXED,
                                 __HIP_MEMORY_SCOPE_AGENT);
       }
-      acc_flush(mism, mism_ptr);
+      acc_flush(mism, mism_ptr, s_scan, red);
       __syncthreads();  // s_pre is rewritten by the next group
     }
     // Tiles: skipped when every running field is in a sparse round (marks
