@@ -289,7 +289,7 @@ __device__ __forceinline__ int ctr_slot() { return (int)(blockIdx.x % (unsigned)
 // each line).
 __device__ __forceinline__ CtrSum load_ctr(gptr<const FieldCtr> c) {
   CtrSum r{0, 0, 0, 0, 0, 0, 0};
-#pragma unroll 4  // (fully unrolled, the 56 loads in flight spill registers)
+#pragma unroll
   for (int k = 0; k < kCtrSlots; ++k) {
     const gptr<const CtrSlot> x = &c->s[k];
     r.mism += x->mism;
@@ -616,18 +616,29 @@ __device__ __forceinline__ void acc_flush(FieldAcc& acc, Ptr ptr, int* sf,
 }
 
 // Inclusive prefix sums of one value per thread into s_pre; returns the
-// total (all threads).
+// total (all threads).  Scans within each wave with shuffles, then adds the
+// totals of the waves before it.
 __device__ __forceinline__ long long block_prefix(long long v, long long* s_pre) {
-  const int tid = threadIdx.x;
-  s_pre[tid] = v;
-  __syncthreads();
-  for (int o = 1; o < 256; o <<= 1) {
-    const long long u = tid >= o ? s_pre[tid - o] : 0;
-    __syncthreads();
-    s_pre[tid] += u;
-    __syncthreads();
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  long long x = v;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const long long y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
   }
-  return s_pre[255];
+  if (lane == 63) s_pre[wave] = x;
+  __syncthreads();
+  long long before = 0, all = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const long long t = s_pre[w];
+    before += w < wave ? t : 0;
+    all += t;
+  }
+  __syncthreads();
+  s_pre[tid] = before + x;
+  __syncthreads();
+  return all;
 }
 // First entry of s_pre[0..n) exceeding m.
 __device__ __forceinline__ int prefix_find(const long long* s_pre, int n, long long m) {
