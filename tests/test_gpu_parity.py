@@ -183,6 +183,37 @@ def test_validation_failures_leave_g_untouched():
     assert st["status"] == "OK" and st["iterations"] == 0
 
 
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_validation_at_the_exact_bounds(dtype):
+    """fhat exactly at every vertex's lower (or upper) bound is valid, and one
+    value past the bound at any single vertex is out of bound; the bounds are
+    the oracle's exact roundings, over magnitudes from subnormal to large and
+    bounds from sub-ulp to huge, and the GPU's status equals the oracle's."""
+    rng = np.random.default_rng(31)
+    shape = (3, 5, 70)
+    n = int(np.prod(shape))
+    lo_e, hi_e = (-140, 100) if dtype == np.float32 else (-1060, 1000)
+    f = (rng.choice([-1.0, 1.0], n) * rng.uniform(0.5, 1.0, n) *
+         np.exp2(rng.integers(lo_e, hi_e, n).astype(np.float64))).astype(dtype).reshape(shape)
+    xis = (1e-42, 1e-3, 1e30) if dtype == np.float32 else (1e-320, 1e-3, 1e300)
+    for xi in xis:
+        lb, ub = oracle.bounds(f, xi)
+        for edge, step in ((lb, -np.inf), (ub, np.inf)):
+            assert oracle.validate(f, edge, xi) != "INPUT_BOUND"
+            _, st = pmsz.correct(dev(f), dev(edge), xi, max_iters=0)
+            assert st["status"] not in ("INPUT_BOUND", "NONFINITE"), (xi, st)
+            for i in rng.choice(n, 12, replace=False):
+                past = edge.copy().reshape(-1)
+                past[i] = np.nextafter(past[i], dtype(step))
+                if not np.isfinite(past[i]):
+                    continue
+                past = past.reshape(shape)
+                want = oracle.validate(f, past, xi)
+                assert want == "INPUT_BOUND", (xi, i, want)
+                _, st = pmsz.correct(dev(f), dev(past), xi, max_iters=0)
+                assert st["status"] == want, (xi, int(i), st)
+
+
 def test_subnormal_values():
     """Bounds and edits in the binary32 subnormal range (no flush to zero)."""
     rng = np.random.default_rng(17)
