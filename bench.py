@@ -85,7 +85,33 @@ def cpu_baseline(f, fhat, xi, planes):
             "sample": "first %d z-planes (%dx%dx%d, %d vertices) of the same field, corrected "
                       "as their own field: %d rounds, %.1f s" % (
                           planes, planes, fs.shape[1], fs.shape[2], fs.size,
-                          st["iterations"], dt)}
+                          st["iterations"], dt),
+            "small_64": cpu_small()}
+
+
+def cpu_small():
+    """The oracle on the whole 64^3 binary32 Perlin field (the latency
+    workload), on every host thread and on one, per correction."""
+    import oracle
+    import synth
+    f, fhat, xi = synth.small_perlin_case(device="cpu")
+    f, fhat = f.numpy(), fhat.numpy()
+    all_threads = oracle.threads()
+    out = {"threads": all_threads}
+    try:
+        for key, n in (("ms_all_threads", all_threads), ("ms_one_thread", 1)):
+            oracle.set_threads(n)
+            oracle.correct(f, fhat.copy(), xi)  # warm-up
+            reps = 3
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                _, st = oracle.correct(f, fhat.copy(), xi)
+            out[key] = round((time.perf_counter() - t0) * 1e3 / reps, 2)
+        out["status"] = st["status"]
+        out["iterations"] = st["iterations"]
+    finally:
+        oracle.set_threads(all_threads)
+    return out
 
 
 def bench_batched(dev, n_fields, seed):
