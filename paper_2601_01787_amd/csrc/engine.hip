@@ -424,7 +424,7 @@ __device__ __forceinline__ long long sparse_items(const FieldDesc& d, const Fiel
                                                   unsigned long long E, uint32_t* cnt = nullptr) {
   if (!s.started || s.done) return -1;
   const gptr<const FieldCtr> c = &as_global((const FieldState*)d.st)->c[(E + 2) % 3];
-  const unsigned long long cap = (unsigned long long)list_slice(d.list_cap);
+  const unsigned long long cap = (unsigned long long)(d.list_cap / list_slices(d.words));
   unsigned long long n = 0;
   bool over = false;
 #pragma unroll
@@ -513,7 +513,7 @@ __device__ __forceinline__ Exam sparse_examine(const FieldDesc& d, uint32_t m,
   const uint32_t j = m - k * (three ? 15u : 7u);
   // the slice holding the k-th listed target
   uint32_t kk = k, at = 0;
-  const uint32_t slice = (uint32_t)list_slice(d.list_cap);
+  const uint32_t slice = (uint32_t)(d.list_cap / list_slices(d.words));
 #pragma unroll
   for (int i = 0; i < kCtrSlots - 1; ++i) {
     const uint32_t ci = cnt[i];
@@ -664,8 +664,10 @@ __device__ __forceinline__ void apply_segment(const FieldDesc& d, int32_t w0, in
                                               unsigned long long& edits) {
   constexpr int kPer = 16;
   const int tid = threadIdx.x;
-  const int slot = ctr_slot();
-  const long long slice = list_slice(d.list_cap);
+  // list slice of this segment (its counter slot for the list length)
+  const int nls = list_slices(d.words);
+  const int slot = (int)((w0 / kSegWords) % nls);
+  const long long slice = d.list_cap / nls;
   // thread t owns words w0 + t + 256 k: each load instruction reads 256
   // consecutive words across the block
   const gptr<uint32_t> bm = as_global(d.bm);

@@ -149,13 +149,23 @@ hipError_t engine_zero(void* p, size_t bytes, hipStream_t s);
 // Fill `bytes` bytes (multiple of 4, 4-byte aligned) with the 32-bit word v.
 hipError_t engine_fill(void* p, size_t bytes, uint32_t v, hipStream_t s);
 
-// Target list: the apply pass lists its targets, each block in the slice of
-// its counter slot (list_capacity / kCtrSlots entries); when no slice
-// overflowed, the next round examines the Freudenthal neighbours of exactly
-// those vertices instead of sweeping tiles.
-inline int32_t list_capacity(const TileGeo& G) { return G.n / 256 + 1024; }
-// Entries of one counter slot's slice of the target list.
-__host__ __device__ inline int32_t list_slice(int32_t cap) { return cap / kCtrSlots; }
+// Target list: the apply pass lists its targets, the pass over apply segment
+// k in slice k mod S of the list (S = min(kCtrSlots, the field's segments),
+// list_capacity / S entries each, counted in that counter slot); when no
+// slice overflowed, the next round examines the Freudenthal neighbours of
+// exactly those vertices instead of sweeping tiles.  A field of few segments
+// thus keeps the whole capacity in few slices.  The capacity sits near the
+// break-even point: examining one neighbour of a listed target costs about 15
+// (3D) to 16 (2D) times one vertex of a tile sweep (measured), and a target
+// has 15 (3D) or 7 (2D) of them, so sparse rounds pay below about N/222
+// (3D) or N/112 (2D) targets.
+inline int32_t list_capacity(const TileGeo& G) {
+  return (G.ndim == 3 ? G.n / 256 : G.n / 128) + 1024;
+}
+__host__ __device__ inline int32_t list_slices(int64_t words) {
+  const int64_t segs = (words + kSegWords - 1) / kSegWords;
+  return segs < kCtrSlots ? (int32_t)(segs > 0 ? segs : 1) : kCtrSlots;
+}
 
 // Per-field workspace: [FieldState][activity bytes x 2][bitmap][target list]
 // [directions].
