@@ -871,7 +871,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
   // that the grid's blocks share the segments of small fields
   int parts_log2 = 0;
   while (parts_log2 < 8 && a.total_segs << (parts_log2 + 1) <= (int64_t)G) ++parts_log2;
-  const int64_t parts = int64_t(1) << parts_log2;
 
   for (long long r = 0; a.max_rounds < 0 || r < a.max_rounds; ++r) {
     if (engine_failed(ctl)) break;
@@ -955,9 +954,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     // of one when the grid has more blocks than there are segments (small
     // fields: a segment's edits would otherwise run through one block's
     // threads in a few long chains).
-    for (int64_t u = blockIdx.x; u < a.total_segs * parts; u += G) {
-      const int64_t sg = u >> parts_log2;
-      const int32_t part = (int32_t)(u & (parts - 1));
+    // (Rounds after an all-sparse detect flag few vertices: whole segments.)
+    const int plog = any_tiles ? parts_log2 : 0;
+    for (int64_t u = blockIdx.x; u < (a.total_segs << plog); u += G) {
+      const int64_t sg = u >> plog;
+      const int32_t part = (int32_t)(u & ((int64_t(1) << plog) - 1));
       const int fi = field_of_seg(a.fd, a.nf, sg);
       const FieldDesc& d = a.fd[fi];
       const FieldIter s = load_iter(&as_global(d.st)->s[p]);  // persisted by block 0 before the barrier
@@ -971,7 +972,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
       }
       if (s.done || bad || mism == 0) continue;
       const bool edit = (long long)s.k < d.max_iters;
-      const int32_t span = (int32_t)(kSegWords >> parts_log2);
+      const int32_t span = (int32_t)(kSegWords >> plog);
       const int32_t w0 = (int32_t)((sg - d.seg_base) * kSegWords) + part * span;
       const int32_t w1 = (w0 + span < d.words) ? w0 + span : (int32_t)d.words;
       if (w0 >= w1) continue;  // a part past the end of the field's last segment
