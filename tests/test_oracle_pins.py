@@ -534,3 +534,90 @@ def test_targeted_invariants(ndim, dtype):
     assert np.array_equal(oracle.directions(g_final), dirs_f)
     _, st_half = oracle.correct(f, fhat, xi)
     assert st["iterations"] <= st_half["iterations"]
+
+
+# -------------------------------------------------- sampled-checker pins -----
+
+def _boundary_and_random(shape, rng, extra):
+    """Every vertex on a face, edge or corner of the box, plus `extra` random
+    interior ones."""
+    idx = np.arange(int(np.prod(shape))).reshape(shape)
+    on = np.zeros(shape, dtype=bool)
+    for ax in range(len(shape)):
+        sl = [slice(None)] * len(shape)
+        sl[ax] = 0
+        on[tuple(sl)] = True
+        sl[ax] = -1
+        on[tuple(sl)] = True
+    pick = idx[on].tolist() + rng.integers(0, idx.size, size=extra).tolist()
+    return np.array(pick, dtype=np.int64)
+
+
+@pytest.mark.parametrize("shape", [(7, 13), (1, 9), (5, 1), (4, 5, 6), (3, 1, 7), (2, 9, 1),
+                                   (6, 5, 11)])
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_directions_at_matches_the_whole_field(shape, dtype):
+    """orc_directions_at (the sampled checker of the large fields) at every
+    face, edge and corner vertex and at random interior ones: equal to the
+    direction bytes of the whole field and to the brute-force argmax / argmin
+    over the simplicial neighbourhood (Sec. IV-A n_max / n_min)."""
+    rng = np.random.default_rng(sum(shape) * 7 + (dtype == np.float64))
+    f = rng.integers(0, 6, size=shape).astype(dtype)  # tie-heavy
+    idx = _boundary_and_random(shape, rng, 40)
+    at = oracle.directions_at(f, idx)
+    full = oracle.directions(f).reshape(-1)
+    assert np.array_equal(at, full[idx])
+    adj = brute.adjacency(*grid_args(shape))
+    flat = f.reshape(-1)
+    for k, i in enumerate(idx.tolist()):
+        up, down = brute.steepest(flat, adj, i)
+        assert target(shape, i, int(at[k]) & 15) == up
+        assert target(shape, i, int(at[k]) >> 4) == down
+
+
+def _label_case(seed):
+    """A tiny 3D field f and a perturbed copy g whose ascending and descending
+    label errors differ in number."""
+    rng = np.random.default_rng(seed)
+    shape = (4, 5, 6)
+    f = rng.uniform(0.0, 1.0, size=shape)
+    g = f.copy()
+    flat = g.reshape(-1)
+    k = rng.integers(1, 4)
+    where = rng.choice(flat.size, size=k, replace=False)
+    flat[where] += rng.choice([-1.0, 1.0], size=k) * rng.uniform(0.2, 0.6, size=k)
+    return f, g
+
+
+def test_verify_label_split_and_edited_count_against_walks():
+    """Sec. III-A segmentations, Sec. V-D counts: wrong_max_label counts the
+    vertices whose ascending integral line ends at another maximum,
+    wrong_min_label those whose descending line ends at another minimum,
+    found here by explicit walks; vertices_edited counts the vertices where g
+    differs from fhat, first and last vertex included."""
+    found = 0
+    for seed in range(200):
+        f, g = _label_case(seed)
+        adj = brute.adjacency(*grid_args(f.shape))
+        ff, gg = f.reshape(-1), g.reshape(-1)
+        up = sum(brute.walk(ff, adj, i, True) != brute.walk(gg, adj, i, True)
+                 for i in range(ff.size))
+        dn = sum(brute.walk(ff, adj, i, False) != brute.walk(gg, adj, i, False)
+                 for i in range(ff.size))
+        if up == dn or min(up, dn) == 0:
+            continue
+        # fhat: g with a known set of vertices moved, both ends of the array
+        # among them; the others keep g's bits
+        fhat = g.copy()
+        moved = np.array([0, 7, 33, ff.size - 1])
+        fhat.reshape(-1)[moved] += 1e-3
+        rep = oracle.verify(f, g, fhat, 10.0)
+        assert rep["wrong_max_label"] == up
+        assert rep["wrong_min_label"] == dn
+        assert rep["vertices_edited"] == moved.size
+        rep2 = oracle.verify(f, g, g, 10.0)
+        assert rep2["vertices_edited"] == 0
+        found += 1
+        if found == 3:
+            break
+    assert found == 3, "no case with differing ascending / descending label errors"
