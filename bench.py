@@ -71,6 +71,26 @@ def kernel_split(tm, rounds, s):
             "k_engine": (tm["engine_ms"], 1, engine_bytes)}
 
 
+GOLDEN_512 = os.path.join(ROOT, "tests", "golden", "perlin512_f32.json")
+
+
+def check_against_golden(f, fhat, g, st):
+    """The timed result against the oracle's: sha256 of the input, of the
+    corrected field and every statistic, as written by the oracle-only script
+    beside the golden file."""
+    import numpy as np
+    gold = json.load(open(GOLDEN_512))
+
+    def sha(t):
+        return hashlib.sha256(t.cpu().numpy().view(np.uint8)).hexdigest()
+
+    same_in = sha(f) == gold["sha256_f"] and sha(fhat) == gold["sha256_fhat"]
+    same_g = sha(g) == gold["sha256_g"]
+    same_st = all(st[k] == gold["stats"][k] for k in gold["stats"])
+    return {"identical": bool(same_in and same_g and same_st), "inputs": same_in,
+            "sha256_g": same_g, "stats": same_st, "oracle": "tests/golden/perlin512_f32.json"}
+
+
 def cpu_baseline(f, fhat, xi, planes):
     """The oracle (untuned) on a bounded sample: the first `planes` z-planes of
     the same field, corrected as a field of their own."""
@@ -445,6 +465,10 @@ def main():
     value = n_vox / (ms_per_step * 1e-3) / 1e9
     for st in stats:
         assert st["status"] == "OK" and st["iterations"] == stats[0]["iterations"], st
+    parity = check_against_golden(f, fhat, gs[W + K - 1], stats[-1])
+    if not parity["identical"]:
+        log("the corrected 512^3 field differs from the oracle's:", parity)
+        sys.exit(1)
 
     tm = tims[-1]
     per_round = rounds_all[-1]
@@ -482,6 +506,7 @@ def main():
                                "one field per launch", "voxels": n_vox,
                    "parallelism": "1 GPU"},
         "roofline": roofline,
+        "parity": parity,
         "detail": {"iterations": stats[0]["iterations"], "edits": stats[0]["steps_applied"],
                    "mismatch_initial": stats[0]["mismatch_initial"], "rounds": tm["rounds"],
                    "swept_vertices": tm["swept"], "tiles": tm["tiles"], "grid": tm["grid"],

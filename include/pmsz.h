@@ -139,7 +139,10 @@ int pmsz_directions(const pmsz_grid* grid, const void* field, uint8_t* dirs, voi
  *     paper; this halving is the reading used here); k += 1.
  * f: device, original field.  g: device, in: fhat, out: the last iterate
  * (always within [lb, fhat]).  dirs_f: device direction bytes of f, or NULL
- * to compute them into the workspace.  ws: device workspace of at least
+ * to compute them into the workspace; given bytes are checked first (every
+ * code must be 0 or name a neighbour of its vertex inside the grid: no code
+ * 8, no z bit in 2D), and any invalid one returns PMSZ_ERR_INVALID_ARG with g
+ * untouched.  ws: device workspace of at least
  * pmsz_workspace_size(grid, PMSZ_WS_CORRECT) bytes, 256-byte aligned.
  * max_iters >= 0.  stats: host, filled on every return after argument checks
  * (status mirrors the return code).  Validation failures (NONFINITE,
@@ -271,9 +274,27 @@ int pmsz_decode_edits(const pmsz_grid* grid, const uint8_t* in, size_t n_bytes, 
  * dirs: device direction bytes.  max_label / min_label: device int32 arrays of
  * nx*ny*nz, written with the index of the maximum (resp. minimum) reached by
  * following n_max (resp. n_min); either may be NULL.  ws: device workspace of
- * pmsz_workspace_size(grid, PMSZ_WS_LABELS) bytes.  Synchronises. */
+ * pmsz_workspace_size(grid, PMSZ_WS_LABELS) bytes, 256-byte aligned.  The
+ * labels are found by pointer jumping in place on the device, passes queued
+ * in batches with one read-back per batch.  Bytes holding a code that does
+ * not name a neighbour inside the grid, or pointers that do not form a
+ * forest (never the case for bytes made by pmsz_directions), return
+ * PMSZ_ERR_INVALID_ARG; the label arrays are then unspecified.
+ * Synchronises. */
 int pmsz_labels(const pmsz_grid* grid, const uint8_t* dirs, int32_t* max_label,
                 int32_t* min_label, void* ws, size_t ws_bytes, void* stream);
+
+/* Work and device time of the last pmsz_labels on this thread (pmsz_verify
+ * runs it twice; the record is the second run's).  Host struct. */
+typedef struct {
+  int64_t vertices;    /* vertices labelled                                   */
+  int64_t passes_max;  /* pointer-jumping passes of the max labels (the last
+                          one found nothing to change; 0 when not requested)  */
+  int64_t passes_min;  /* the same for the min labels                         */
+  double ms;           /* device time from the first to the last kernel (HIP
+                          events on the caller's stream)                      */
+} pmsz_labels_info;
+int pmsz_last_labels(pmsz_labels_info* out);
 
 /* Evaluation counts of Sec. V-D, recomputed from (f, g) from scratch: bound
  * violations, direction mismatches, false / missed extrema, wrong labels,
@@ -362,6 +383,14 @@ typedef struct {
  * number recorded (<= 64) in *n.  Returns PMSZ_ERR_INVALID_ARG if n is NULL,
  * or if out is NULL while cap > 0. */
 int pmsz_last_rounds(pmsz_round* out, int64_t cap, int64_t* n);
+
+/* Frees the host resources the library keeps for reuse across calls (pinned
+ * staging buffers and HIP events of every thread).  They are never freed by
+ * destructors at thread or process exit, where the HIP runtime may already be
+ * gone; call this before the process ends, while the runtime is up and no
+ * other call of the library is running (the Python binding calls it from an
+ * exit hook).  Later calls allocate them again.  Always PMSZ_OK. */
+int pmsz_release(void);
 
 /* Name of a status code (static string). */
 const char* pmsz_status_string(int status);

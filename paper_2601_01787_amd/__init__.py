@@ -10,8 +10,10 @@ n_max / n_min (Sec. IV-A), ``correct`` runs the decrease-only edit loop
 (Eq. 1, Sec. IV-A rules), ``labels`` the ascending / descending segmentations
 (Sec. III-A), ``verify`` the evaluation counts of Sec. V-D.
 """
+import atexit
 import ctypes
 import os
+import sys
 
 import torch
 
@@ -35,7 +37,7 @@ EXPORTS = ("pmsz_workspace_size", "pmsz_directions", "pmsz_correct",
            "pmsz_edits_max_bytes", "pmsz_encode_edits", "pmsz_decode_edits",
            "pmsz_blocks_workspace_size", "pmsz_correct_blocks", "pmsz_set_tiles_target",
            "pmsz_get_tiles_target", "pmsz_tune_workspace_size", "pmsz_tune_tiles",
-           "pmsz_status_string", "pmsz_last_error")
+           "pmsz_last_labels", "pmsz_release", "pmsz_status_string", "pmsz_last_error")
 
 
 class PmszError(RuntimeError):
@@ -88,6 +90,14 @@ class Round(ctypes.Structure):
     _fields_ = [("detect_ms", ctypes.c_double), ("apply_ms", ctypes.c_double),
                 ("swept", ctypes.c_int64), ("flagged", ctypes.c_int64), ("edits", ctypes.c_int64),
                 ("sparse", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class LabelsInfo(ctypes.Structure):
+    _fields_ = [("vertices", ctypes.c_int64), ("passes_max", ctypes.c_int64),
+                ("passes_min", ctypes.c_int64), ("ms", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -163,13 +173,23 @@ def load():
                                       ctypes.POINTER(ctypes.c_int32)]
     L.pmsz_session_remove.argtypes = [vp, i32]
     L.pmsz_session_destroy.argtypes = [vp]
+    L.pmsz_last_labels.argtypes = [ctypes.POINTER(LabelsInfo)]
+    L.pmsz_release.argtypes = []
     L.pmsz_status_string.argtypes = [ctypes.c_int]
     L.pmsz_status_string.restype = ctypes.c_char_p
     L.pmsz_last_error.restype = ctypes.c_char_p
     for name in EXPORTS[:-2]:
         getattr(L, name).restype = ctypes.c_int
     _lib = L
+    # the library's pinned buffers and events are freed while the HIP runtime
+    # is still up (exit hooks run last-registered first, so before torch's)
+    atexit.register(_release)
     return L
+
+
+def _release():
+    if _lib is not None:
+        _lib.pmsz_release()
 
 
 def _raise_if(code, allowed=(0,)):
@@ -435,6 +455,10 @@ class Session:
             self._keep.clear()
 
     def __del__(self):
+        # at interpreter shutdown the HIP runtime may already be gone: a
+        # session not closed by then is left to the process exit
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -453,6 +477,13 @@ def labels(dirs):
                                  ctypes.c_void_p(mx.data_ptr()), ctypes.c_void_p(mn.data_ptr()),
                                  ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(dirs)))
     return mx, mn
+
+
+def last_labels():
+    """Passes and device time of the last pmsz_labels on this thread."""
+    info = LabelsInfo()
+    _raise_if(load().pmsz_last_labels(ctypes.byref(info)))
+    return info.as_dict()
 
 
 def verify(f, g, fhat, xi):

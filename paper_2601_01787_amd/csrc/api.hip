@@ -92,7 +92,7 @@ VerifyLayout verify_layout(const Geo& G) {
   L.lgx = L.lfn + align_up(4 * n);
   L.lgn = L.lgx + align_up(4 * n);
   L.flag = L.lgn + align_up(4 * n);
-  L.total = L.flag + kAlign;
+  L.total = L.flag + align_up(kLabelsWsBytes);
   return L;
 }
 
@@ -182,41 +182,98 @@ int plan_batch(int32_t n, const pmsz_field* fields, const uint8_t* const* dirs_g
   return PMSZ_OK;
 }
 
+// Host resources kept for reuse across calls: pinned staging buffers and HIP
+// events, per thread.  None is released by a destructor: a thread-local
+// destructor runs at thread or process exit, possibly after the HIP runtime
+// has been torn down (profilers and torch finalise it from their own exit
+// handlers), and a HIP call then faults inside exit().  Every resource is
+// listed in a process-wide registry instead, and pmsz_release() frees them
+// all while the runtime is still up; a thread whose resources were released
+// (the registry's generation moved on) allocates new ones on its next call.
+struct HostRes {
+  std::mutex mu;
+  std::vector<void*> pinned;
+  std::vector<hipEvent_t> events;
+  uint64_t gen = 1;
+};
+HostRes& host_res() {
+  static HostRes* r = new HostRes();  // never destroyed
+  return *r;
+}
+uint64_t res_gen() {
+  std::lock_guard<std::mutex> lk(host_res().mu);
+  return host_res().gen;
+}
+
 // Pinned staging for descriptors going up and states coming back; the calls
 // that use it synchronise before returning, so one buffer per thread serves.
 struct Staging {
   void* p = nullptr;
   size_t cap = 0;
-  ~Staging() {
-    if (p) (void)hipHostFree(p);
-  }
+  uint64_t gen = 0;
 };
 thread_local Staging t_stage;
 
 int staging(Staging& s, size_t bytes, void** out) {
+  if (s.gen != res_gen()) {  // released since it was allocated (or never allocated)
+    s.p = nullptr;
+    s.cap = 0;
+  }
   if (s.cap < bytes) {
-    if (s.p) (void)hipHostFree(s.p);
+    HostRes& R = host_res();
+    if (s.p) {
+      std::lock_guard<std::mutex> lk(R.mu);
+      R.pinned.erase(std::remove(R.pinned.begin(), R.pinned.end(), s.p), R.pinned.end());
+      (void)hipHostFree(s.p);
+    }
     s.p = nullptr;
     s.cap = 0;
     HIP_TRY(hipHostMalloc(&s.p, bytes, hipHostMallocDefault));
+    std::lock_guard<std::mutex> lk(R.mu);
+    R.pinned.push_back(s.p);
     s.cap = bytes;
+    s.gen = R.gen;
   }
   *out = s.p;
   return PMSZ_OK;
 }
 
+// Frees a staging buffer now (unless pmsz_release already did).
+void release_staging(Staging& s) {
+  HostRes& R = host_res();
+  std::lock_guard<std::mutex> lk(R.mu);
+  if (s.p && s.gen == R.gen) {
+    R.pinned.erase(std::remove(R.pinned.begin(), R.pinned.end(), s.p), R.pinned.end());
+    (void)hipHostFree(s.p);
+  }
+  s.p = nullptr;
+  s.cap = 0;
+}
+
 // Events around the engine launch and the figures of the last run.
 struct Timing {
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // directions, engine, end
+  uint64_t gen = 0;
   pmsz_timing last;
   pmsz_round rounds[kTraceRounds];
   int64_t nrounds = 0;
-  ~Timing() {
-    for (auto& e : ev)
-      if (e) (void)hipEventDestroy(e);
-  }
+  pmsz_labels_info labels;
 };
 thread_local Timing t_timing;
+
+// The thread's timing events, created on first use (and after a release).
+int timing_events(Timing& tm) {
+  HostRes& R = host_res();
+  if (tm.gen == res_gen() && tm.ev[0]) return PMSZ_OK;
+  for (auto& e : tm.ev) {
+    e = nullptr;
+    HIP_TRY(hipEventCreate(&e));
+    std::lock_guard<std::mutex> lk(R.mu);
+    R.events.push_back(e);
+    tm.gen = R.gen;
+  }
+  return PMSZ_OK;
+}
 
 void fill_stats(const FieldIter& it, pmsz_stats& o) {
   memset(&o, 0, sizeof(o));
@@ -272,8 +329,7 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
   a.max_rounds = -1;
   a.trace = (unsigned long long*)(base + P.trace);
   Timing& tm = t_timing;
-  if (!tm.ev[0])
-    for (auto& e : tm.ev) HIP_TRY(hipEventCreate(&e));
+  if ((r = timing_events(tm))) return r;
   int grid = 0;
   bool need_dirs = false;
   for (int32_t i = 0; i < n; ++i) need_dirs |= !P.fd[i].dirs_given;
@@ -499,29 +555,71 @@ static size_t session_ctl_bytes(int32_t cap) {
          align_up(sizeof(FieldIter) * (size_t)cap);
 }
 
-int label_pass(int32_t* lab, int64_t n, unsigned int* flag, hipStream_t s) {
-  unsigned int h = 1;
-  for (int round = 0; round < 64 && h; ++round) {
-    HIP_TRY(hipMemsetAsync(flag, 0, sizeof(unsigned int), s));
-    HIP_TRY(launch_labels_jump(lab, n, flag, s));
-    HIP_TRY(hipMemcpyAsync(&h, flag, sizeof(h), hipMemcpyDeviceToHost, s));
+// Pointer jumping to the fixed point on the device: passes are queued a
+// batch at a time (each returns at once when its predecessor changed
+// nothing) and only the batch's changed flags are read back.  *passes
+// receives the passes that ran, the last being the one that found nothing to
+// change.  Direction bytes that do not form a forest (possible only for
+// caller-supplied bytes) never settle: PMSZ_ERR_INVALID_ARG.
+int label_pass(int32_t* lab, int64_t n, unsigned int* flags, hipStream_t s, int64_t* passes) {
+  HIP_TRY(engine_zero(flags, 4 * kLabelMaxPasses, s));
+  unsigned int h[kLabelBatch];
+  for (int b = 0; b < kLabelMaxPasses; b += kLabelBatch) {
+    for (int p = b; p < b + kLabelBatch; ++p) HIP_TRY(launch_labels_jump(lab, n, flags, p, s));
+    HIP_TRY(hipMemcpyAsync(h, flags + b, sizeof(h), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    for (int p = 0; p < kLabelBatch; ++p)
+      if (!h[p]) {
+        *passes = b + p + 1;
+        return PMSZ_OK;
+      }
   }
-  if (h) return fail(PMSZ_ERR_DEVICE, "label propagation did not settle");
+  return fail(PMSZ_ERR_INVALID_ARG,
+              "label propagation did not settle in %d passes: the direction bytes do not form "
+              "a forest", kLabelMaxPasses);
+}
+
+// ws: kLabelsWsBytes of device workspace.  Invalid direction codes are
+// reported as PMSZ_ERR_INVALID_ARG (the label arrays are then unspecified).
+int labels_impl(const Geo& G, const uint8_t* dirs, int32_t* lmax, int32_t* lmin, void* ws,
+                hipStream_t s) {
+  unsigned long long* bad = (unsigned long long*)ws;
+  unsigned int* flags = (unsigned int*)((char*)ws + 256);
+  Timing& tm = t_timing;
+  int r = timing_events(tm);
+  if (r) return r;
+  memset(&tm.labels, 0, sizeof(tm.labels));
+  HIP_TRY(engine_zero(bad, 8, s));
+  HIP_TRY(hipEventRecord(tm.ev[0], s));
+  HIP_TRY(launch_labels_init(dirs, G, lmax, lmin, bad, s));
+  if (lmax && (r = label_pass(lmax, G.n, flags, s, &tm.labels.passes_max))) return r;
+  if (lmin && (r = label_pass(lmin, G.n, flags, s, &tm.labels.passes_min))) return r;
+  HIP_TRY(hipEventRecord(tm.ev[1], s));
+  unsigned long long nbad = 0;
+  HIP_TRY(hipMemcpyAsync(&nbad, bad, sizeof(nbad), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (nbad)
+    return fail(PMSZ_ERR_INVALID_ARG, "%llu direction bytes hold a code that is not a neighbour "
+                "of their vertex", nbad);
+  float ms = 0.f;
+  HIP_TRY(hipEventElapsedTime(&ms, tm.ev[0], tm.ev[1]));
+  tm.labels.ms = ms;
+  tm.labels.vertices = G.n;
   return PMSZ_OK;
 }
 
-int labels_impl(const Geo& G, const uint8_t* dirs, int32_t* lmax, int32_t* lmin,
-                unsigned int* flag, hipStream_t s) {
-  HIP_TRY(launch_labels_init(dirs, G, lmax, lmin, s));
-  if (lmax) {
-    int r = label_pass(lmax, G.n, flag, s);
-    if (r) return r;
-  }
-  if (lmin) {
-    int r = label_pass(lmin, G.n, flag, s);
-    if (r) return r;
-  }
+// Rejects caller-supplied direction bytes with a code that is not valid for
+// its vertex, before anything reads them as offsets.  scratch: 8 device bytes.
+int check_dirs(const Geo& G, const uint8_t* dirs, void* scratch, hipStream_t s) {
+  unsigned long long* bad = (unsigned long long*)scratch;
+  HIP_TRY(engine_zero(bad, 8, s));
+  HIP_TRY(launch_check_dirs(dirs, G, bad, s));
+  unsigned long long nbad = 0;
+  HIP_TRY(hipMemcpyAsync(&nbad, bad, sizeof(nbad), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (nbad)
+    return fail(PMSZ_ERR_INVALID_ARG, "dirs_f: %llu direction bytes hold a code that is not a "
+                "neighbour of their vertex", nbad);
   return PMSZ_OK;
 }
 
@@ -559,6 +657,23 @@ int pmsz_last_rounds(pmsz_round* out, int64_t cap, int64_t* n) {
   return PMSZ_OK;
 }
 
+int pmsz_last_labels(pmsz_labels_info* out) {
+  if (!out) return fail(PMSZ_ERR_INVALID_ARG, "NULL argument");
+  *out = t_timing.labels;
+  return PMSZ_OK;
+}
+
+int pmsz_release(void) {
+  HostRes& R = host_res();
+  std::lock_guard<std::mutex> lk(R.mu);
+  for (void* p : R.pinned) (void)hipHostFree(p);
+  for (hipEvent_t e : R.events) (void)hipEventDestroy(e);
+  R.pinned.clear();
+  R.events.clear();
+  ++R.gen;
+  return PMSZ_OK;
+}
+
 int pmsz_workspace_size(const pmsz_grid* grid, int op, size_t* bytes) {
   int r = check_grid(grid);
   if (r) return r;
@@ -576,7 +691,7 @@ int pmsz_workspace_size(const pmsz_grid* grid, int op, size_t* bytes) {
       break;
     }
     case PMSZ_WS_VERIFY: *bytes = verify_layout(G).total; break;
-    case PMSZ_WS_LABELS: *bytes = kAlign; break;
+    case PMSZ_WS_LABELS: *bytes = kLabelsWsBytes; break;
     default: return fail(PMSZ_ERR_INVALID_ARG, "unknown workspace kind %d", op);
   }
   return PMSZ_OK;
@@ -619,6 +734,11 @@ int pmsz_correct_mode(const pmsz_grid* grid, const void* f, void* g, double xi,
   if ((r = plan_batch(1, &one, given, max_iters, P, edit_mode))) return r;
   if (ws_bytes < P.total) return fail(PMSZ_ERR_OOM, "workspace %zu bytes, need %zu", ws_bytes, P.total);
   memset(stats, 0, sizeof(*stats));
+  // caller-supplied directions become neighbour offsets: check them first
+  if (dirs_f && (r = check_dirs(make_geo(*grid), dirs_f, ws, (hipStream_t)stream))) {
+    stats->status = r;
+    return r;
+  }
   return run_batch(grid->dtype, P, given, ws, stats, (hipStream_t)stream);
 }
 
@@ -708,9 +828,11 @@ int pmsz_labels(const pmsz_grid* grid, const uint8_t* dirs, int32_t* max_label,
   int r = check_grid(grid);
   if (r) return r;
   if (!dirs || !ws) return fail(PMSZ_ERR_INVALID_ARG, "NULL argument");
-  if (ws_bytes < kAlign) return fail(PMSZ_ERR_OOM, "labels workspace needs %zu bytes", kAlign);
+  if ((uintptr_t)ws % kAlign) return fail(PMSZ_ERR_INVALID_ARG, "workspace not 256-byte aligned");
+  if (ws_bytes < kLabelsWsBytes)
+    return fail(PMSZ_ERR_OOM, "labels workspace needs %zu bytes", kLabelsWsBytes);
   const Geo G = make_geo(*grid);
-  return labels_impl(G, dirs, max_label, min_label, (unsigned int*)ws, (hipStream_t)stream);
+  return labels_impl(G, dirs, max_label, min_label, ws, (hipStream_t)stream);
 }
 
 int pmsz_verify(const pmsz_grid* grid, const void* f, const void* g, const void* fhat,
@@ -731,12 +853,12 @@ int pmsz_verify(const pmsz_grid* grid, const void* f, const void* g, const void*
   uint8_t* dg = (uint8_t*)(b + L.dg);
   int32_t *lfx = (int32_t*)(b + L.lfx), *lfn = (int32_t*)(b + L.lfn);
   int32_t *lgx = (int32_t*)(b + L.lgx), *lgn = (int32_t*)(b + L.lgn);
-  unsigned int* flag = (unsigned int*)(b + L.flag);
-  HIP_TRY(hipMemsetAsync(vc, 0, sizeof(VerifyCounts), s));
+  void* lws = b + L.flag;
+  HIP_TRY(engine_zero(vc, sizeof(VerifyCounts), s));
   HIP_TRY(launch_dirs(grid->dtype, f, G, df, s));
   HIP_TRY(launch_dirs(grid->dtype, g, G, dg, s));
-  if ((r = labels_impl(G, df, lfx, lfn, flag, s))) return r;
-  if ((r = labels_impl(G, dg, lgx, lgn, flag, s))) return r;
+  if ((r = labels_impl(G, df, lfx, lfn, lws, s))) return r;
+  if ((r = labels_impl(G, dg, lgx, lgn, lws, s))) return r;
   HIP_TRY(launch_verify(grid->dtype, f, g, fhat, G.n, xi_in_type(grid->dtype, xi), df, dg, lfx,
                         lfn, lgx, lgn, vc, s));
   VerifyCounts h;
@@ -1197,9 +1319,8 @@ int pmsz_session_destroy(pmsz_session* S) {
   if (!S) return PMSZ_OK;
   if (S->pending) (void)hipEventSynchronize(S->ev);
   if (S->ev) (void)hipEventDestroy(S->ev);
-  if (S->up.p) (void)hipHostFree(S->up.p);
-  if (S->down.p) (void)hipHostFree(S->down.p);
-  S->up.p = S->down.p = nullptr;
+  release_staging(S->up);
+  release_staging(S->down);
   delete S;
   return PMSZ_OK;
 }

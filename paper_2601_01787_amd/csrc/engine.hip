@@ -24,6 +24,9 @@
 // block 0 persists it one round later, so no extra barrier is needed.  The
 // loop ends when a round edits nothing (every field done) or after
 // max_rounds rounds (resumable steps).
+#include <map>
+#include <mutex>
+
 #include "engine.hpp"
 
 namespace pmsz {
@@ -1074,19 +1077,38 @@ hipError_t engine_zero(void* p, size_t bytes, hipStream_t s) { return engine_fil
 
 // Cooperative grid: as many resident blocks as the chip holds, but no more
 // than there is work for (fewer arrivals make the barrier cheaper).
+// Resident blocks per compute unit and compute units of a device, looked up
+// once per (device, kernel) under a lock (calls may come from several host
+// threads).
+struct Occupancy {
+  int per_cu = -1, cus = -1;
+};
+template <class T>
+static hipError_t occupancy(int dev, Occupancy& out) {
+  static std::mutex mu;
+  static std::map<int, Occupancy> cache;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(dev);
+  if (it == cache.end()) {
+    Occupancy o;
+    hipError_t e = hipDeviceGetAttribute(&o.cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return e;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&o.per_cu, k_engine<T>, 256, 0);
+    if (e != hipSuccess) return e;
+    it = cache.emplace(dev, o).first;
+  }
+  out = it->second;
+  return hipSuccess;
+}
+
 template <class T>
 static hipError_t launch_t(const EngineArgs& a, hipStream_t s, int* grid_out) {
-  static int per_cu = -1, cus = -1, dev_cached = -1;
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
-  if (dev != dev_cached) {
-    e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e != hipSuccess) return e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_engine<T>, 256, 0);
-    if (e != hipSuccess) return e;
-    dev_cached = dev;
-  }
+  Occupancy occ;
+  if ((e = occupancy<T>(dev, occ)) != hipSuccess) return e;
+  const int per_cu = occ.per_cu, cus = occ.cus;
   // the XCD and compute-unit barrier state starts cleared in every launch
   e = engine_fill(&a.ctl->xbar[0], sizeof(EngineCtl) - offsetof(EngineCtl, xbar), 0u, s);
   if (e != hipSuccess) return e;

@@ -30,9 +30,21 @@ inline int64_t bitmap_words(int64_t n) { return (n + 31) / 32; }
 hipError_t launch_dirs(int dtype, const void* h, const Geo& G, uint8_t* dirs, hipStream_t s);
 
 // labels.hip
+// Pointer jumping: each pass follows up to kLabelHops links per vertex;
+// passes are queued kLabelBatch at a time between read-backs of their
+// changed flags, at most kLabelMaxPasses per label array.
+constexpr int kLabelHops = 8;
+constexpr int kLabelBatch = 8;
+constexpr int kLabelMaxPasses = 64;
+// Labels workspace: [bad-code counter (8 bytes), padded to 256][changed flag
+// per pass (kLabelMaxPasses words)].
+constexpr size_t kLabelsWsBytes = 256 + 4 * kLabelMaxPasses;
+hipError_t launch_check_dirs(const uint8_t* dirs, const Geo& G, unsigned long long* bad,
+                             hipStream_t s);
 hipError_t launch_labels_init(const uint8_t* dirs, const Geo& G, int32_t* lmax, int32_t* lmin,
+                              unsigned long long* bad, hipStream_t s);
+hipError_t launch_labels_jump(int32_t* lab, int64_t n, unsigned int* flags, int pass,
                               hipStream_t s);
-hipError_t launch_labels_jump(int32_t* lab, int64_t n, unsigned int* changed, hipStream_t s);
 
 // verify.hip
 struct VerifyCounts {

@@ -124,9 +124,18 @@ def run_open_loop(server_kind, requests, device, hbm_budget, max_fields=64, roun
     done = []
     for r in arrivals:
         r.footprint = footprint(r.f)
+    srv = None
     if server_kind == "batched":
         srv = BatchingServer(dev, hbm_budget, max_fields, rounds_per_step,
                              work_budget=work_budget)
+    try:
+        return _replay(server_kind, srv, arrivals, pending, done, dev, check)
+    finally:
+        if srv is not None:
+            srv.close()
+
+
+def _replay(server_kind, srv, arrivals, pending, done, dev, check):
     torch.cuda.synchronize(dev)
     t0 = time.perf_counter()
     while arrivals or pending or (server_kind == "batched" and srv.active):
@@ -162,8 +171,6 @@ def run_open_loop(server_kind, requests, device, hbm_budget, max_fields=64, roun
             wait = arrivals[0].arrival - (time.perf_counter() - t0)
             if wait > 0:
                 time.sleep(min(wait, 0.01))
-    if server_kind == "batched":
-        srv.close()
     return done
 
 

@@ -286,6 +286,12 @@ def test_full_size_perlin_512():
     for k in STAT_KEYS:
         assert st[k] == gold["stats"][k], (k, st, gold["stats"])
     assert sha(g) == gold["sha256_g"]
+    # the benchmarked call: directions computed inside the correction
+    g2, st2 = pmsz.correct(f, fhat, xi)
+    for k in STAT_KEYS:
+        assert st2[k] == gold["stats"][k], (k, st2, gold["stats"])
+    assert sha(g2) == gold["sha256_g"]
+    del g2
     mx, mn = pmsz.labels(d)
     idx = torch.tensor(gold["label_sample_idx"], device=DEV)
     assert host(mx.reshape(-1)[idx]).tolist() == gold["label_sample_max"]
@@ -293,3 +299,67 @@ def test_full_size_perlin_512():
     rep = pmsz.verify(f, g, fhat, xi)
     assert rep["wrong_label"] == 0 and rep["bound_violations"] == 0
     assert rep["asc_mismatch"] == 0 and rep["desc_mismatch"] == 0
+
+
+def _bad_dirs_cases():
+    """Direction bytes no direction pass makes, each at one vertex of a valid
+    array: code 8, a z-bit code in 2D, and codes stepping out of the grid at a
+    boundary vertex (both nibbles)."""
+    out = []
+    for shape, i, byte in (((5, 6, 70), 123, 0x08), ((5, 6, 70), 123, 0x80),
+                           ((40, 70), 77, 0x05), ((40, 70), 77, 0x40),
+                           ((5, 6, 70), 0, 0x09), ((5, 6, 70), 0, 0xA0),
+                           ((5, 6, 70), 5 * 6 * 70 - 1, 0x07), ((40, 70), 69, 0x01),
+                           ((40, 70), 40 * 70 - 70, 0x20)):
+        out.append((shape, i, byte))
+    return out
+
+
+@pytest.mark.parametrize("shape,i,byte", _bad_dirs_cases())
+def test_invalid_direction_bytes_are_rejected(shape, i, byte):
+    """Caller-supplied direction bytes become neighbour offsets: a byte that
+    does not name a neighbour inside the grid is reported as INVALID_ARG by
+    pmsz_correct (g untouched) and by pmsz_labels, before any offset is used."""
+    f, fhat, xi = random_case(shape, np.float32, 5)
+    d = pmsz.directions(dev(f))
+    bad = d.clone().reshape(-1)
+    bad[i] = byte
+    bad = bad.reshape(d.shape)
+    g = dev(fhat)
+    with pytest.raises(pmsz.PmszError) as e:
+        pmsz.correct(dev(f), g, xi, dirs_f=bad, inplace=True)
+    assert e.value.status == 1
+    assert same_bits(host(g), fhat)
+    with pytest.raises(pmsz.PmszError) as e:
+        pmsz.labels(bad)
+    assert e.value.status == 1
+    # the valid bytes still work
+    g, st = pmsz.correct(dev(f), dev(fhat), xi, dirs_f=d)
+    assert st["status"] == "OK"
+
+
+def test_labels_reject_pointer_cycles():
+    """Valid codes that do not form a forest (two vertices pointing at each
+    other) never settle: INVALID_ARG after the pass limit."""
+    f, _, _ = random_case((4, 6, 66), np.float32, 6)
+    d = pmsz.directions(dev(f)).reshape(-1)
+    d[10] = (d[10] & 0xF0) | 0x01   # n_max of 10 -> 11
+    d[11] = (d[11] & 0xF0) | 0x09   # n_max of 11 -> 10
+    with pytest.raises(pmsz.PmszError) as e:
+        pmsz.labels(d.reshape(4, 6, 66))
+    assert e.value.status == 1
+    info = pmsz.last_labels()
+    assert info["passes_max"] == 0
+
+
+def test_labels_pass_counts():
+    """Pointer jumping stops at the first pass that changes nothing: at most
+    the passes a doubling chase needs over the longest integral line."""
+    f, _, _ = random_case((16, 40, 70), np.float32, 7)
+    d = pmsz.directions(dev(f))
+    mx, mn = pmsz.labels(d)
+    info = pmsz.last_labels()
+    assert info["vertices"] == f.size
+    assert 1 <= info["passes_max"] <= 12 and 1 <= info["passes_min"] <= 12
+    rmx, rmn = oracle.labels(oracle.directions(f))
+    assert np.array_equal(host(mx), rmx) and np.array_equal(host(mn), rmn)
