@@ -37,7 +37,8 @@ EXPORTS = ("pmsz_workspace_size", "pmsz_directions", "pmsz_correct",
            "pmsz_edits_max_bytes", "pmsz_encode_edits", "pmsz_decode_edits",
            "pmsz_blocks_workspace_size", "pmsz_correct_blocks", "pmsz_set_tiles_target",
            "pmsz_get_tiles_target", "pmsz_tune_workspace_size", "pmsz_tune_tiles",
-           "pmsz_last_labels", "pmsz_release", "pmsz_status_string", "pmsz_last_error")
+           "pmsz_last_labels", "pmsz_release",
+           "pmsz_status_string", "pmsz_last_error")
 
 
 class PmszError(RuntimeError):

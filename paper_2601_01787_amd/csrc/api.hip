@@ -289,9 +289,20 @@ void fill_stats(const FieldIter& it, pmsz_stats& o) {
   }
 }
 
-// Run the engine to completion on a planned batch; fills stats[n].
+// Bytes of host staging run_batch needs for n fields (descriptors up, control
+// block, round trace and states down).
+size_t batch_stage_bytes(int32_t n) {
+  const size_t up = sizeof(FieldDesc) * (size_t)n;
+  const size_t down = kCtlHostBytes + kTraceBytes + sizeof(FieldIter) * (size_t)n;
+  return up > down ? up : down;
+}
+
+// Run the engine to completion on a planned batch; fills stats[n].  stage:
+// host staging of batch_stage_bytes(n) bytes, or NULL for this thread's
+// pinned buffer.  timed: record HIP events and the round trace into this
+// thread's timing record (the allocation-free path records neither).
 int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* ws,
-              pmsz_stats* stats, hipStream_t s) {
+              pmsz_stats* stats, hipStream_t s, void* stage = nullptr, bool timed = true) {
   const int32_t n = (int32_t)P.fd.size();
   char* base = (char*)ws;
   for (int32_t i = 0; i < n; ++i) {
@@ -307,10 +318,8 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
     d.prop = P.edit_mode ? (void*)(base + P.prop + P.prop_off[i]) : nullptr;
   }
   const size_t up = sizeof(FieldDesc) * (size_t)n;
-  const size_t down = kCtlHostBytes + kTraceBytes + sizeof(FieldIter) * (size_t)n;
-  void* stage;
-  int r = staging(t_stage, up > down ? up : down, &stage);
-  if (r) return r;
+  int r = PMSZ_OK;
+  if (!stage && (r = staging(t_stage, batch_stage_bytes(n), &stage))) return r;
   memcpy(stage, P.fd.data(), up);
   EngineCtl* ctl = (EngineCtl*)(base + P.ctl);
   FieldIter* out = (FieldIter*)(base + P.out);
@@ -327,23 +336,24 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
   a.total_tiles = P.total_tiles;
   a.total_segs = P.total_segs;
   a.max_rounds = -1;
-  a.trace = (unsigned long long*)(base + P.trace);
+  a.trace = timed ? (unsigned long long*)(base + P.trace) : nullptr;
   Timing& tm = t_timing;
-  if ((r = timing_events(tm))) return r;
+  if (timed && (r = timing_events(tm))) return r;
   int grid = 0;
   bool need_dirs = false;
   for (int32_t i = 0; i < n; ++i) need_dirs |= !P.fd[i].dirs_given;
   // directions of f, then the whole correction loop in one launch
-  HIP_TRY(hipEventRecord(tm.ev[0], s));
+  if (timed) HIP_TRY(hipEventRecord(tm.ev[0], s));
   if (need_dirs) HIP_TRY(engine_dirs(dtype, a.fd, n, P.total_tiles, s));
-  HIP_TRY(hipEventRecord(tm.ev[1], s));
+  if (timed) HIP_TRY(hipEventRecord(tm.ev[1], s));
   HIP_TRY(engine_launch(dtype, a, s, &grid));
-  HIP_TRY(hipEventRecord(tm.ev[2], s));
+  if (timed) HIP_TRY(hipEventRecord(tm.ev[2], s));
   // the staging buffer is reused for the results: the upload above is
   // stream-ordered before this copy, so it has been consumed
   HIP_TRY(hipMemcpyAsync(stage, ctl, kCtlHostBytes, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync((char*)stage + kCtlHostBytes, a.trace, kTraceBytes,
-                         hipMemcpyDeviceToHost, s));
+  if (timed)
+    HIP_TRY(hipMemcpyAsync((char*)stage + kCtlHostBytes, a.trace, kTraceBytes,
+                           hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync((char*)stage + kCtlHostBytes + kTraceBytes, out,
                          sizeof(FieldIter) * (size_t)n, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
@@ -352,6 +362,16 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
   const FieldIter* hs =
       (const FieldIter*)((char*)stage + kCtlHostBytes + kTraceBytes);
   if (hc->error) return fail(PMSZ_ERR_DEVICE, "grid barrier timed out in the correction engine");
+  if (!timed) {
+    int first = PMSZ_OK;
+    for (int32_t i = 0; i < n; ++i) {
+      if (!hs[i].done) return fail(PMSZ_ERR_DEVICE, "field %d did not finish", i);
+      fill_stats(hs[i], stats[i]);
+      if (hs[i].status != PMSZ_OK && first == PMSZ_OK) first = hs[i].status;
+    }
+    if (first != PMSZ_OK) return fail(first, "%s", pmsz_status_string(first));
+    return PMSZ_OK;
+  }
   float el[2];
   for (int k = 0; k < 2; ++k) HIP_TRY(hipEventElapsedTime(&el[k], tm.ev[k], tm.ev[k + 1]));
   memset(&tm.last, 0, sizeof(tm.last));
@@ -560,12 +580,15 @@ static size_t session_ctl_bytes(int32_t cap) {
 // nothing) and only the batch's changed flags are read back.  *passes
 // receives the passes that ran, the last being the one that found nothing to
 // change.  Direction bytes that do not form a forest (possible only for
-// caller-supplied bytes) never settle: PMSZ_ERR_INVALID_ARG.
-int label_pass(int32_t* lab, int64_t n, unsigned int* flags, hipStream_t s, int64_t* passes) {
+// caller-supplied bytes) either never settle (PMSZ_ERR_INVALID_ARG here) or
+// are counted in *bad by the passes (see k_labels_jump).
+int label_pass(int32_t* lab, int64_t n, const uint8_t* dirs, int shift, unsigned int* flags,
+               unsigned long long* bad, hipStream_t s, int64_t* passes) {
   HIP_TRY(engine_zero(flags, 4 * kLabelMaxPasses, s));
   unsigned int h[kLabelBatch];
   for (int b = 0; b < kLabelMaxPasses; b += kLabelBatch) {
-    for (int p = b; p < b + kLabelBatch; ++p) HIP_TRY(launch_labels_jump(lab, n, flags, p, s));
+    for (int p = b; p < b + kLabelBatch; ++p)
+      HIP_TRY(launch_labels_jump(lab, n, dirs, shift, flags, bad, p, s));
     HIP_TRY(hipMemcpyAsync(h, flags + b, sizeof(h), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     for (int p = 0; p < kLabelBatch; ++p)
@@ -592,15 +615,17 @@ int labels_impl(const Geo& G, const uint8_t* dirs, int32_t* lmax, int32_t* lmin,
   HIP_TRY(engine_zero(bad, 8, s));
   HIP_TRY(hipEventRecord(tm.ev[0], s));
   HIP_TRY(launch_labels_init(dirs, G, lmax, lmin, bad, s));
-  if (lmax && (r = label_pass(lmax, G.n, flags, s, &tm.labels.passes_max))) return r;
-  if (lmin && (r = label_pass(lmin, G.n, flags, s, &tm.labels.passes_min))) return r;
+  if (lmax && (r = label_pass(lmax, G.n, dirs, 0, flags, bad, s, &tm.labels.passes_max)))
+    return r;
+  if (lmin && (r = label_pass(lmin, G.n, dirs, 4, flags, bad, s, &tm.labels.passes_min)))
+    return r;
   HIP_TRY(hipEventRecord(tm.ev[1], s));
   unsigned long long nbad = 0;
   HIP_TRY(hipMemcpyAsync(&nbad, bad, sizeof(nbad), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   if (nbad)
     return fail(PMSZ_ERR_INVALID_ARG, "%llu direction bytes hold a code that is not a neighbour "
-                "of their vertex", nbad);
+                "of their vertex, or lie on a cycle of pointers", nbad);
   float ms = 0.f;
   HIP_TRY(hipEventElapsedTime(&ms, tm.ev[0], tm.ev[1]));
   tm.labels.ms = ms;

@@ -8,9 +8,9 @@
 // cycles).  Labels are found by pointer jumping in place: every pass replaces
 // L[i] by an ancestor further up the chain, chasing a few hops per pass.  Any
 // value a thread reads -- old or already updated -- is an ancestor of i, so
-// the fixed point is the root whatever the interleaving.  A pass in which no
-// label changed proves every label is a root: a label l with lab[l] == l is a
-// root, since a non-root's label always names another vertex.
+// the fixed point is the root whatever the interleaving.  In a forest a pass
+// in which no label changed proves every label is a root: a chase from a
+// non-root climbs at least one step.
 #include "launch.hpp"
 
 namespace pmsz {
@@ -64,29 +64,49 @@ __global__ __launch_bounds__(256) void k_labels_init(const uint8_t* __restrict__
   if ((threadIdx.x & 63) == 0 && nb) atomicAdd(bad, nb);
 }
 
-// Pass `pass` of pointer jumping.  flags[pass] is set when some label moved;
-// a pass whose predecessor moved nothing returns at once, so a batch of
-// passes can be queued without reading anything back in between.
-__global__ __launch_bounds__(256) void k_labels_jump(int32_t* lab, int64_t n, unsigned int* flags,
+// Pass `pass` of pointer jumping over the labels of the nibble `shift` (0:
+// n_max, 4: n_min) of `dirs`.  flags[pass] is set when some label moved; a
+// pass whose predecessor moved nothing returns at once, so a batch of passes
+// can be queued without reading anything back in between.
+// Caller-supplied bytes need not form a forest; a cycle is caught two ways,
+// counted in *bad: a chase that ends where it started without reaching a
+// root has gone round it, and a vertex that reads as a root (its label is
+// itself) while its code is not 0 was made one by in-place jumping round it.
+// A vertex on a cycle only ever labels itself with vertices of that cycle,
+// never with a true extremum, so the second test catches every cycle that
+// settles; one that never settles fails on the pass limit.
+__global__ __launch_bounds__(256) void k_labels_jump(int32_t* lab, int64_t n,
+                                                     const uint8_t* __restrict__ dirs, int shift,
+                                                     unsigned int* flags, unsigned long long* bad,
                                                      int pass) {
   if (pass > 0 && flags[pass - 1] == 0u) return;
   const int64_t stride = (int64_t)gridDim.x * 256;
   int any = 0;
+  unsigned long long cyc = 0;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
     const int32_t l0 = lab[i];
     int32_t l = l0;
+    bool root = false;
 #pragma unroll 1
     for (int hop = 0; hop < kLabelHops; ++hop) {
       const int32_t ll = lab[l];
-      if (ll == l) break;
+      if (ll == l) {
+        root = true;
+        cyc += ((dirs[l] >> shift) & 15) != 0;  // a false root
+        break;
+      }
       l = ll;
     }
     if (l != l0) {
       lab[i] = l;
       any = 1;
+    } else if (!root) {
+      ++cyc;
     }
   }
   if (__ballot(any) != 0ull && (threadIdx.x & 63) == 0) atomicOr(flags + pass, 1u);
+  cyc = wave_sum(cyc);
+  if ((threadIdx.x & 63) == 0 && cyc) atomicAdd(bad, cyc);
 }
 
 static unsigned grid_for(int64_t items) {
@@ -109,9 +129,11 @@ hipError_t launch_labels_init(const uint8_t* dirs, const Geo& G, int32_t* lmax, 
   return hipGetLastError();
 }
 
-hipError_t launch_labels_jump(int32_t* lab, int64_t n, unsigned int* flags, int pass,
+hipError_t launch_labels_jump(int32_t* lab, int64_t n, const uint8_t* dirs, int shift,
+                              unsigned int* flags, unsigned long long* bad, int pass,
                               hipStream_t s) {
-  hipLaunchKernelGGL(k_labels_jump, dim3(grid_for(n)), dim3(256), 0, s, lab, n, flags, pass);
+  hipLaunchKernelGGL(k_labels_jump, dim3(grid_for(n)), dim3(256), 0, s, lab, n, dirs, shift,
+                     flags, bad, pass);
   return hipGetLastError();
 }
 

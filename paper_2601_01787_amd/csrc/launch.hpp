@@ -43,7 +43,8 @@ hipError_t launch_check_dirs(const uint8_t* dirs, const Geo& G, unsigned long lo
                              hipStream_t s);
 hipError_t launch_labels_init(const uint8_t* dirs, const Geo& G, int32_t* lmax, int32_t* lmin,
                               unsigned long long* bad, hipStream_t s);
-hipError_t launch_labels_jump(int32_t* lab, int64_t n, unsigned int* flags, int pass,
+hipError_t launch_labels_jump(int32_t* lab, int64_t n, const uint8_t* dirs, int shift,
+                              unsigned int* flags, unsigned long long* bad, int pass,
                               hipStream_t s);
 
 // verify.hip

@@ -338,18 +338,23 @@ def test_invalid_direction_bytes_are_rejected(shape, i, byte):
     assert st["status"] == "OK"
 
 
-def test_labels_reject_pointer_cycles():
-    """Valid codes that do not form a forest (two vertices pointing at each
-    other) never settle: INVALID_ARG after the pass limit."""
+@pytest.mark.parametrize("cycle", [2, 3])
+def test_labels_reject_pointer_cycles(cycle):
+    """Valid codes that do not form a forest are INVALID_ARG: two vertices
+    pointing at each other (the chase comes back to its start), or three in a
+    ring (it never settles within the pass limit)."""
     f, _, _ = random_case((4, 6, 66), np.float32, 6)
     d = pmsz.directions(dev(f)).reshape(-1)
-    d[10] = (d[10] & 0xF0) | 0x01   # n_max of 10 -> 11
-    d[11] = (d[11] & 0xF0) | 0x09   # n_max of 11 -> 10
+    nx = 66
+    if cycle == 2:
+        ring = ((10, 0x01), (11, 0x09))           # 10 -> 11 -> 10
+    else:
+        ring = ((10, 0x01), (11, 0x02), (11 + nx, 0x0B))  # 10 -> 11 -> 11+nx -> 10
+    for v, code in ring:
+        d[v] = (d[v] & 0xF0) | code
     with pytest.raises(pmsz.PmszError) as e:
         pmsz.labels(d.reshape(4, 6, 66))
     assert e.value.status == 1
-    info = pmsz.last_labels()
-    assert info["passes_max"] == 0
 
 
 def test_labels_pass_counts():
