@@ -151,6 +151,24 @@ int pmsz_correct(const pmsz_grid* grid, const void* f, void* g, double xi,
                  const uint8_t* dirs_f, void* ws, size_t ws_bytes, int64_t max_iters,
                  pmsz_stats* stats, void* stream);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): pmsz_correct without a workspace argument.
+ * Same arguments, results and errors as pmsz_correct (halving edit), except
+ * that the workspace is the library's own static device array of 32 MiB
+ * (PMSZ_NOALLOC_SCRATCH_BYTES; each device that runs it holds one copy until
+ * the process ends).  A field whose pmsz_workspace_size(grid, PMSZ_WS_CORRECT)
+ * exceeds it is refused with PMSZ_ERR_OOM before anything runs (binary32
+ * 256^3 fits: 18.4 MiB; a 4096^2 2D field: 18.6 MiB).  The call allocates
+ * nothing: no hipMalloc, no pinned host memory, no events; its host staging
+ * lives on the caller's stack.  The stream must belong to the current device.
+ * Every call on one device shares that device's array and clears what must
+ * start at zero itself: calls that overlap on one device (two host threads,
+ * or two streams) race and give undefined results; serialise them. */
+#define PMSZ_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+int pmsz_correct_noalloc(const pmsz_grid* grid, const void* f, void* g, double xi,
+                         const uint8_t* dirs_f, int64_t max_iters, pmsz_stats* stats,
+                         void* stream);
+
 /* pmsz_correct with a choice of edit rule.  PMSZ_EDIT_HALVING is
  * pmsz_correct.  PMSZ_EDIT_TARGETED follows the worked examples of Sec. IV-A,
  * where a vertex is lowered to its rival's value "or slightly below": every

@@ -26,6 +26,8 @@ EDIT_MODES = {"halving": 0, "targeted": 1}
 STATUS = {0: "OK", 1: "INVALID_ARG", 2: "NONFINITE", 3: "INPUT_BOUND", 4: "NOT_CONVERGED",
           5: "STALLED", 6: "OOM", 7: "DEVICE"}
 DEFAULT_MAX_ITERS = 1 << 40
+# size of the static device scratch behind pmsz_correct_noalloc
+NOALLOC_SCRATCH_BYTES = 32 << 20
 
 # the last two return strings, the others a status code
 EXPORTS = ("pmsz_workspace_size", "pmsz_directions", "pmsz_correct",
@@ -37,7 +39,7 @@ EXPORTS = ("pmsz_workspace_size", "pmsz_directions", "pmsz_correct",
            "pmsz_edits_max_bytes", "pmsz_encode_edits", "pmsz_decode_edits",
            "pmsz_blocks_workspace_size", "pmsz_correct_blocks", "pmsz_set_tiles_target",
            "pmsz_get_tiles_target", "pmsz_tune_workspace_size", "pmsz_tune_tiles",
-           "pmsz_last_labels", "pmsz_release",
+           "pmsz_last_labels", "pmsz_release", "pmsz_correct_noalloc",
            "pmsz_status_string", "pmsz_last_error")
 
 
@@ -176,6 +178,7 @@ def load():
     L.pmsz_session_destroy.argtypes = [vp]
     L.pmsz_last_labels.argtypes = [ctypes.POINTER(LabelsInfo)]
     L.pmsz_release.argtypes = []
+    L.pmsz_correct_noalloc.argtypes = [G, vp, vp, dbl, vp, i64, ctypes.POINTER(Stats), vp]
     L.pmsz_status_string.argtypes = [ctypes.c_int]
     L.pmsz_status_string.restype = ctypes.c_char_p
     L.pmsz_last_error.restype = ctypes.c_char_p
@@ -276,6 +279,26 @@ def correct(f, fhat, xi, *, inplace=False, max_iters=DEFAULT_MAX_ITERS, dirs_f=N
                                     ctypes.c_void_p(g.data_ptr()), float(xi), dptr, emode,
                                     ctypes.c_void_p(ws.data_ptr()), ws.numel(), int(max_iters),
                                     ctypes.byref(st), _stream(f))
+    _raise_if(code, allowed=(0, 2, 3, 4, 5))
+    return g, st.as_dict()
+
+
+def correct_noalloc(f, fhat, xi, *, inplace=False, max_iters=DEFAULT_MAX_ITERS, dirs_f=None):
+    """correct() through pmsz_correct_noalloc: the library's own static
+    device scratch instead of a workspace (fields whose workspace fits
+    NOALLOC_SCRATCH_BYTES).  Allocates only the output when inplace=False."""
+    _dev(f, "f")
+    _dev(fhat, "fhat")
+    if fhat.shape != f.shape or fhat.dtype != f.dtype or fhat.device != f.device:
+        raise ValueError("f and fhat must match in shape, dtype and device")
+    g = fhat if inplace else fhat.clone()
+    st = Stats()
+    dptr = ctypes.c_void_p(_dev(dirs_f, "dirs_f").data_ptr()) if dirs_f is not None else None
+    with torch.cuda.device(f.device):
+        code = load().pmsz_correct_noalloc(ctypes.byref(grid_of(f)),
+                                           ctypes.c_void_p(f.data_ptr()),
+                                           ctypes.c_void_p(g.data_ptr()), float(xi), dptr,
+                                           int(max_iters), ctypes.byref(st), _stream(f))
     _raise_if(code, allowed=(0, 2, 3, 4, 5))
     return g, st.as_dict()
 

@@ -104,12 +104,28 @@ VerifyLayout verify_layout(const Geo& G) {
 // Every region starts on a 256-byte boundary; everything before the direction
 // bytes is cleared by one kernel before the launch.
 // ---------------------------------------------------------------------------
+// A plan's per-field arrays: one field is held inline, so that planning a
+// single field (the allocation-free entry point) touches no heap.
+template <class T>
+struct PlanVec {
+  T one{};
+  std::vector<T> many;
+  size_t n = 0;
+  void resize(size_t k) {
+    n = k;
+    if (k > 1) many.resize(k);
+  }
+  size_t size() const { return n; }
+  T* data() { return n > 1 ? many.data() : &one; }
+  T& operator[](size_t i) { return data()[i]; }
+};
+
 struct BatchPlan {
   size_t ctl = 0, desc = 0, out = 0, trace = 0, fields = 0, dirs = 0, prop = 0, total = 0;
   int64_t total_tiles = 0, total_segs = 0;
   int edit_mode = 0;  // 0 halving, 1 targeted (proposal arrays after dirs)
-  std::vector<FieldDesc> fd;
-  std::vector<size_t> field_off, dirs_off, prop_off;
+  PlanVec<FieldDesc> fd;
+  PlanVec<size_t> field_off, dirs_off, prop_off;
 };
 
 // Tile height policy per (ndim, dtype): the tuned tiles-per-field target
@@ -765,6 +781,89 @@ int pmsz_correct_mode(const pmsz_grid* grid, const void* f, void* g, double xi,
     return r;
   }
   return run_batch(grid->dtype, P, given, ws, stats, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free correction.  The workspace is a file-scope device array
+// (each device that runs the library holds its own copy until the process
+// ends).  In host code the array's name is only a host-side stand-in: its
+// device address is looked up once per device with hipGetSymbolAddress, with
+// that device current, and only that address is ever handed to kernels.
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+constexpr size_t kScratchBytes = PMSZ_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_at[kMaxDevices];  // device address of `scratch`, per device
+
+// Address of the current device's scratch array; the stream must belong to
+// that device.
+int scratch_address(hipStream_t s, void** out) {
+  int dev = -1;
+  hipDevice_t sdev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipStreamGetDevice(s, &sdev));
+  if (sdev != dev)
+    return fail(PMSZ_ERR_INVALID_ARG, "the stream belongs to device %d, the current device is %d",
+                (int)sdev, dev);
+  if (dev < 0 || dev >= kMaxDevices)
+    return fail(PMSZ_ERR_INVALID_ARG, "device %d: at most %d devices", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_at[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p || (uintptr_t)p % kAlign)
+      return fail(PMSZ_ERR_DEVICE, "scratch array of device %d has no aligned address", dev);
+    g_scratch_at[dev] = p;
+  }
+  *out = g_scratch_at[dev];
+  return PMSZ_OK;
+}
+
+// Host staging of one field's run (descriptor up; control block, round trace
+// and state down), on the caller's stack.
+constexpr size_t kOneFieldStage =
+    std::max(sizeof(FieldDesc), kCtlHostBytes + kTraceBytes + sizeof(FieldIter));
+
+}  // namespace
+
+extern "C" {
+
+int pmsz_correct_noalloc(const pmsz_grid* grid, const void* f, void* g, double xi,
+                         const uint8_t* dirs_f, int64_t max_iters, pmsz_stats* stats,
+                         void* stream) {
+  int r = check_grid(grid);
+  if (r) return r;
+  if (!f || !g || !stats) return fail(PMSZ_ERR_INVALID_ARG, "NULL argument");
+  if (!isfinite(xi) || xi < 0) return fail(PMSZ_ERR_INVALID_ARG, "xi must be finite and >= 0");
+  if (max_iters < 0) return fail(PMSZ_ERR_INVALID_ARG, "max_iters must be >= 0");
+  const hipStream_t s = (hipStream_t)stream;
+  pmsz_field one;
+  one.grid = *grid;
+  one.f = f;
+  one.g = g;
+  one.xi = xi;
+  const uint8_t* given[1] = {dirs_f};
+  BatchPlan P;
+  if ((r = plan_batch(1, &one, given, max_iters, P, PMSZ_EDIT_HALVING))) return r;
+  if (P.total > kScratchBytes)
+    return fail(PMSZ_ERR_OOM,
+                "this field needs %zu bytes of workspace; the allocation-free correction has %zu "
+                "(use pmsz_correct with a workspace)", P.total, kScratchBytes);
+  void* ws = nullptr;
+  if ((r = scratch_address(s, &ws))) return r;
+  memset(stats, 0, sizeof(*stats));
+  if (dirs_f && (r = check_dirs(make_geo(*grid), dirs_f, ws, s))) {
+    stats->status = r;
+    return r;
+  }
+  alignas(64) unsigned char stage[kOneFieldStage];
+  return run_batch(grid->dtype, P, given, ws, stats, s, stage, false);
 }
 
 int pmsz_edits_workspace_size(const pmsz_grid* grid, int64_t max_edits, size_t* bytes) {

@@ -59,6 +59,15 @@ def test_host_only_calls():
                             ctypes.byref(st), None)
     assert code == 1
     assert b"NULL" in lib.pmsz_last_error()
+    code = lib.pmsz_correct_noalloc(ctypes.byref(g), None, None, 0.1, None, 10,
+                                    ctypes.byref(st), None)
+    assert code == 1
+    # a field whose workspace exceeds the static scratch is refused before any
+    # device call (the pointers are never touched)
+    fake = ctypes.c_void_p(256)
+    code = lib.pmsz_correct_noalloc(ctypes.byref(g), fake, fake, 0.1, None, 10,
+                                    ctypes.byref(st), None)
+    assert code == 6 and b"allocation-free correction" in lib.pmsz_last_error()
 
 
 def test_blocks_workspace_size_host_only():
