@@ -72,14 +72,16 @@ def kernel_split(tm, rounds, s):
 
 
 GOLDEN_512 = os.path.join(ROOT, "tests", "golden", "perlin512_f32.json")
+GOLDEN_GRF = os.path.join(ROOT, "tests", "golden", "grf1024x1024x768_f64.json")
+GOLDEN_BATCH = os.path.join(ROOT, "tests", "golden", "batch256_f32.json")
 
 
-def check_against_golden(f, fhat, g, st):
+def check_against_golden(f, fhat, g, st, path=GOLDEN_512):
     """The timed result against the oracle's: sha256 of the input, of the
     corrected field and every statistic, as written by the oracle-only script
     beside the golden file."""
     import numpy as np
-    gold = json.load(open(GOLDEN_512))
+    gold = json.load(open(path))
 
     def sha(t):
         return hashlib.sha256(t.cpu().numpy().view(np.uint8)).hexdigest()
@@ -88,7 +90,8 @@ def check_against_golden(f, fhat, g, st):
     same_g = sha(g) == gold["sha256_g"]
     same_st = all(st[k] == gold["stats"][k] for k in gold["stats"])
     return {"identical": bool(same_in and same_g and same_st), "inputs": same_in,
-            "sha256_g": same_g, "stats": same_st, "oracle": "tests/golden/perlin512_f32.json"}
+            "sha256_g": same_g, "stats": same_st,
+            "oracle": os.path.relpath(path, ROOT)}
 
 
 def cpu_baseline(f, fhat, xi, planes):
@@ -145,10 +148,7 @@ def bench_batched(dev, n_fields, seed):
 
     import paper_2601_01787_amd as pmsz
     import synth
-    cases = []
-    for c in synth.batch_recipe(n_fields, seed):
-        f, fhat, xi = synth.make_2d_case(c["nx"], c["ny"], c["rel_eps"], c["seed"], device=dev)
-        cases.append((f, fhat, xi))
+    cases = synth.batch_cases(n_fields, seed, device=dev)
     vox = sum(f.numel() for f, _, _ in cases)
     torch.cuda.synchronize()
     # warm both paths on one field
@@ -174,9 +174,26 @@ def bench_batched(dev, n_fields, seed):
     target0 = pmsz.get_tiles_target(2, torch.float32)
     best, tune_ms = pmsz.tune_tiles(cases, reps=2)
     t_tuned, g_tuned, st_tuned = batched()
+    tm = pmsz.last_timing()
     same = same and all(torch.equal(a, b) for a, b in zip(g_plain, g_tuned)) and \
         st_tuned == st_plain
-    return {"fields": n_fields, "voxels": vox,
+    # the engine launch of the tuned batch against the HBM roofline
+    alg = algorithmic_bytes(tm["voxels"], tm["swept"], tm["edits"], 4)
+    roof = {"kernel": "k_engine<float>", "engine_ms": round(tm["engine_ms"], 4),
+            "dirs_ms": round(tm["dirs_ms"], 4), "algorithmic_bytes": alg,
+            "achieved_gbs": round(alg / (tm["engine_ms"] * 1e-3) / 1e9, 1),
+            "frac": round(alg / (tm["engine_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "swept_vertices": tm["swept"], "edits": tm["edits"], "rounds": tm["rounds"]}
+    # every field against the oracle's golden result (the recorded batch)
+    oracle_same = None
+    if n_fields == 256 and seed == 256 and os.path.exists(GOLDEN_BATCH):
+        import numpy as np
+        gold = json.load(open(GOLDEN_BATCH))["fields"]
+        oracle_same = all(
+            hashlib.sha256(g.cpu().numpy().view(np.uint8)).hexdigest() == ref["sha256_g"] and
+            all(st[k] == ref["stats"][k] for k in ref["stats"])
+            for g, st, ref in zip(g_tuned, st_tuned, gold))
+    return {"fields": n_fields, "voxels": vox, "roofline": roof, "oracle_identical": oracle_same,
             "plain_gvox_s": round(vox / t_plain / 1e9, 3),
             "batched_gvox_s": round(vox / t_tuned / 1e9, 3),
             "plain_ms": round(t_plain * 1e3, 2), "batched_ms": round(t_tuned * 1e3, 2),
@@ -248,7 +265,8 @@ def bench_large(dev, steps):
             "hbm_frac": round(alg / (dev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "iterations": st["iterations"], "edits": st["steps_applied"],
             "mismatch_initial": st["mismatch_initial"], "rounds": tm["rounds"],
-            "swept_vertices": tm["swept"], "status": st["status"]}
+            "swept_vertices": tm["swept"], "status": st["status"],
+            "parity": check_against_golden(f, fhat, g, st, GOLDEN_GRF)}
 
 
 def bench_targeted(f, fhat, xi, steps, g_halving):
@@ -297,6 +315,47 @@ def bench_targeted(f, fhat, xi, steps, g_halving):
             "halving_max_abs_err": rep_h["max_abs_err"],
             "directions_restored": rep_t["asc_mismatch"] == 0 and rep_t["desc_mismatch"] == 0,
             "edit_storage": storage}
+
+
+def bench_labels_verify(f, fhat, g, xi, reps):
+    """Segmentation labels (pmsz_labels) of f's and of the corrected field's
+    directions, and the evaluation counts (pmsz_verify), on the resident 512^3
+    workload.  Labels: device time from the library's events; algorithmic
+    bytes = per vertex 1 (direction byte) + 8 (two labels written) once, then
+    per pointer-jumping pass 12 (own label and the label it points at read,
+    own label written; 8 on the last pass, which writes nothing)."""
+    import torch
+
+    import paper_2601_01787_amd as pmsz
+    out = {}
+    n = f.numel()
+    for name, h in (("labels_f", f), ("labels_g", g)):
+        d = pmsz.directions(h)
+        pmsz.labels(d)  # warm-up
+        ms, info = [], None
+        for _ in range(reps):
+            pmsz.labels(d)
+            info = pmsz.last_labels()
+            ms.append(info["ms"])
+        passes = info["passes_max"] + info["passes_min"]
+        alg = n * 9 + n * 12 * max(passes - 2, 0) + n * 8 * min(passes, 2)
+        dev_ms = sorted(ms)[len(ms) // 2]
+        out[name] = {"ms": round(dev_ms, 4), "passes_max": info["passes_max"],
+                     "passes_min": info["passes_min"], "algorithmic_bytes": alg,
+                     "achieved_gbs": round(alg / (dev_ms * 1e-3) / 1e9, 1),
+                     "frac": round(alg / (dev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        del d
+    pmsz.verify(f, g, fhat, xi)  # warm-up
+    ms = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rep = pmsz.verify(f, g, fhat, xi)
+        ms.append((time.perf_counter() - t0) * 1e3)
+    wall = sorted(ms)[len(ms) // 2]
+    out["verify"] = {"ms_per_call": round(wall, 3), "gvox_s": round(n / wall / 1e6, 3),
+                     "report": rep}
+    return out
 
 
 def bench_blocks(f, fhat, xi, configs):
@@ -412,6 +471,8 @@ def main():
                     help="calls of the 64^3 latency leg (0 to skip)")
     ap.add_argument("--blocks", default="2x2x2,4x4x4",
                     help="block grids of the decomposed-domain leg ('' to skip)")
+    ap.add_argument("--labels-reps", type=int, default=3,
+                    help="timed repetitions of the labels and verify leg (0 skips it)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this size (counter calibration)")
     args = ap.parse_args()
@@ -524,6 +585,9 @@ def main():
     if args.targeted_steps:
         log("targeted-edit variant:", args.targeted_steps, "steps")
         out["targeted"] = bench_targeted(f, fhat, xi, args.targeted_steps, gs[-1])
+    if args.labels_reps:
+        log("labels and verify:", args.labels_reps, "reps")
+        out["labels_verify"] = bench_labels_verify(f, fhat, gs[-1], xi, args.labels_reps)
     del gs
     torch.cuda.empty_cache()
     if args.blocks:

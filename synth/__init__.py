@@ -9,10 +9,15 @@ arithmetic of the correction itself: it only makes (f, fhat, xi) triples.
 Determinism: every random draw comes from numpy's PCG64 on the host; the heavy
 arithmetic (Perlin lattice sums) runs in torch float64 with one IEEE operation
 per tensor op, so the same seed gives the same bits on the CPU and on a GPU.
+The Gaussian random field is synthesised on the host (numpy + scipy FFT) and
+then moved wherever it is needed.
 """
 import math
+import os
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
+import scipy.fft as sfft
 import torch
 
 # --------------------------------------------------------------------------
@@ -139,34 +144,71 @@ def quantise_proxy(f, eps, seed, chunk=1 << 24):
 # --------------------------------------------------------------------------
 
 
+# exp(-x) for x >= 0 from +, -, * and exact power-of-two scaling only, so
+# that the same inputs give the same bits on any host (a vectorised libm exp
+# may pick a different code path on another CPU): Cody-Waite reduction
+# x = k ln2 + r with ln2 split into a head with trailing zero bits and a tail,
+# then a degree-13 Taylor polynomial of exp(-r) for |r| <= ln2 / 2 (truncation
+# below 1e-17 relative).
+_LN2_HI = float.fromhex("0x1.62e42feep-1")
+_LN2_LO = float.fromhex("0x1.a39ef35793c76p-33")
+_INV_LN2 = float.fromhex("0x1.71547652b82fep+0")
+_EXP_COEF = [1.0 / math.factorial(n) for n in range(13, -1, -1)]
+
+
+def exp_neg(x):
+    x = np.asarray(x, dtype=np.float64)
+    k = np.floor(x * _INV_LN2 + 0.5)
+    r = (x - k * _LN2_HI) - k * _LN2_LO
+    y = -r
+    p = np.full_like(y, _EXP_COEF[0])
+    for c in _EXP_COEF[1:]:
+        p = p * y + c
+    return np.ldexp(p, -k.astype(np.int64))
+
+
 def gaussian_peaks2d(ny, nx, seed, device="cpu"):
     """Sum of 50..500 Gaussian bumps (sigma 2..20 px, amplitude 0.5..1, each
-    evaluated in a +-4 sigma window) plus 1% white noise; float32.  Peak
-    parameters come from PCG64; the white noise from torch's generator on
-    `device` (seeded), so a seed is reproducible on the same kind of device."""
+    evaluated in a +-4 sigma window) plus 1% white noise; float32, made on the
+    host in binary64 and then moved to `device`.  Every draw comes from PCG64
+    and the arithmetic uses only correctly rounded operations (exp_neg), so a
+    seed gives the same bits on any host.  A bump is the outer product of its
+    two one-dimensional profiles."""
     rng = np.random.default_rng(seed)
     k = int(rng.integers(50, 501))
     cx = rng.uniform(0, nx, k)
     cy = rng.uniform(0, ny, k)
     sig = rng.uniform(2.0, 20.0, k)
     amp = rng.uniform(0.5, 1.0, k)
-    h = torch.zeros((ny, nx), dtype=torch.float64, device=device)
+    win = []
     for j in range(k):
         r = 4.0 * sig[j]
         x0, x1 = max(0, int(math.floor(cx[j] - r))), min(nx, int(math.ceil(cx[j] + r)) + 1)
         y0, y1 = max(0, int(math.floor(cy[j] - r))), min(ny, int(math.ceil(cy[j] + r)) + 1)
-        if x0 >= x1 or y0 >= y1:
-            continue
-        xs = torch.arange(x0, x1, dtype=torch.float64, device=device) - cx[j]
-        ys = torch.arange(y0, y1, dtype=torch.float64, device=device) - cy[j]
-        d2 = ys.view(-1, 1) ** 2 + xs.view(1, -1) ** 2
-        h[y0:y1, x0:x1] += amp[j] * torch.exp(-d2 / (2.0 * sig[j] ** 2))
+        win.append((x0, x1, y0, y1))
+    # all one-dimensional profiles of the field in one evaluation
+    xs = np.concatenate([np.arange(w[0], w[1], dtype=np.float64) - cx[j]
+                         for j, w in enumerate(win)] + [np.zeros(0)])
+    ys = np.concatenate([np.arange(w[2], w[3], dtype=np.float64) - cy[j]
+                         for j, w in enumerate(win)] + [np.zeros(0)])
+    sx = np.concatenate([np.full(max(w[1] - w[0], 0), 2.0 * sig[j] ** 2)
+                         for j, w in enumerate(win)] + [np.zeros(0)])
+    sy = np.concatenate([np.full(max(w[3] - w[2], 0), 2.0 * sig[j] ** 2)
+                         for j, w in enumerate(win)] + [np.zeros(0)])
+    ex = exp_neg(xs * xs / sx)
+    ey = exp_neg(ys * ys / sy)
+    h = np.zeros((ny, nx), dtype=np.float64)
+    ox = oy = 0
+    for j, (x0, x1, y0, y1) in enumerate(win):
+        wx, wy = max(x1 - x0, 0), max(y1 - y0, 0)
+        if wx and wy:
+            h[y0:y1, x0:x1] += amp[j] * np.multiply.outer(ey[oy:oy + wy], ex[ox:ox + wx])
+        ox += wx
+        oy += wy
     rng_h = float(h.max() - h.min())
-    gen = torch.Generator(device=device)
-    gen.manual_seed(int(rng.integers(1 << 62)))
-    noise = torch.randn((ny, nx), generator=gen, dtype=torch.float64, device=device)
+    noise = np.random.default_rng(int(rng.integers(1 << 62))).standard_normal((ny, nx))
     h += noise * (0.01 * max(rng_h, 1e-12))
-    return h.to(torch.float32)
+    return torch.from_numpy(h.astype(np.float32)).to(device)
 
 
 def batch_recipe(n_fields, seed, lo=256, hi=4096):
@@ -191,31 +233,72 @@ def make_2d_case(nx, ny, rel_eps, seed, device="cpu"):
     return f, fhat, xi
 
 
+def batch_cases(n_fields, seed, device="cpu", workers=None):
+    """The uneven 2D batch of batch_recipe(n_fields, seed) as (f, fhat, xi)
+    triples on `device`; the fields are made on the host by a thread pool
+    (each field from its own seed, so the result does not depend on the
+    number of threads)."""
+    rec = batch_recipe(n_fields, seed)
+    workers = workers or min(16, os.cpu_count() or 1)
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        fs = list(ex.map(lambda c: gaussian_peaks2d(c["ny"], c["nx"], c["seed"]), rec))
+    out = []
+    for c, f in zip(rec, fs):
+        f = f.to(device)
+        xi = c["rel_eps"] * (float(f.max()) - float(f.min()))
+        out.append((f, quantise_proxy(f, xi, c["seed"]), xi))
+    return out
+
+
 # --------------------------------------------------------------------------
 # Gaussian random field with power spectrum k^-3 (FFT synthesis), float64.
 # --------------------------------------------------------------------------
 
 
-def grf3d(shape, seed, device="cpu"):
+def _normal_slabs(shape, seed, slab=16, workers=None):
+    """N(0, 1) values of the given (nz, ny, nx) shape, drawn slab by slab of
+    `slab` z-planes, each slab from its own PCG64 stream spawned from `seed`,
+    so that the values do not depend on how many threads draw them."""
     nz, ny, nx = shape
-    gen = torch.Generator(device=device)
-    gen.manual_seed(seed)
-    w = torch.randn((nz, ny, nx), generator=gen, dtype=torch.float64, device=device)
-    W = torch.fft.rfftn(w)
-    del w
-    kz = torch.fft.fftfreq(nz, d=1.0 / nz, device=device, dtype=torch.float64)
-    ky = torch.fft.fftfreq(ny, d=1.0 / ny, device=device, dtype=torch.float64)
-    kx = torch.fft.rfftfreq(nx, d=1.0 / nx, device=device, dtype=torch.float64)
+    out = np.empty(shape, dtype=np.float64)
+    seqs = np.random.SeedSequence(seed).spawn((nz + slab - 1) // slab)
+
+    def fill(k):
+        z0, z1 = k * slab, min(nz, (k + 1) * slab)
+        np.random.Generator(np.random.PCG64(seqs[k])).standard_normal(
+            size=(z1 - z0, ny, nx), out=out[z0:z1])
+
+    workers = workers or min(16, os.cpu_count() or 1)
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        list(ex.map(fill, range(len(seqs))))
+    return out
+
+
+def grf3d(shape, seed, workers=None):
+    """Gaussian random field with power spectrum |k|^-3 on the host, binary64,
+    normalised to [0, 1] (torch CPU tensor).  White noise -> rfftn -> scale by
+    |k|^-3/2 (integer wavenumbers, k = 0 removed) -> irfftn.  scipy's FFT
+    computes each 1-D transform the same way whatever the worker count, so a
+    seed gives the same bits on any x86-64 host with this software."""
+    nz, ny, nx = shape
+    workers = workers or min(16, os.cpu_count() or 1)
+    W = sfft.rfftn(_normal_slabs(shape, seed, workers=workers), workers=workers,
+                   overwrite_x=True)
+    kz = sfft.fftfreq(nz, d=1.0 / nz)
+    ky = sfft.fftfreq(ny, d=1.0 / ny)
+    kx = sfft.rfftfreq(nx, d=1.0 / nx)
     for z0 in range(0, nz, 64):
         z1 = min(nz, z0 + 64)
-        k2 = (kz[z0:z1].view(-1, 1, 1) ** 2 + ky.view(1, -1, 1) ** 2 + kx.view(1, 1, -1) ** 2)
-        amp = torch.where(k2 > 0, k2.clamp_min(1e-30) ** -0.75, torch.zeros_like(k2))
+        k2 = kz[z0:z1, None, None] ** 2 + ky[None, :, None] ** 2 + kx[None, None, :] ** 2
+        amp = np.zeros_like(k2)
+        np.power(k2, -0.75, out=amp, where=k2 > 0)
         W[z0:z1] *= amp
-    out = torch.fft.irfftn(W, s=(nz, ny, nx))
+    out = sfft.irfftn(W, s=(nz, ny, nx), workers=workers, overwrite_x=True)
     del W
     lo, hi = float(out.min()), float(out.max())
-    out.sub_(lo).mul_(1.0 / (hi - lo))
-    return out
+    out -= lo
+    out *= 1.0 / (hi - lo)
+    return torch.from_numpy(out)
 
 
 # --------------------------------------------------------------------------
@@ -245,7 +328,7 @@ def grf_case(shape=(768, 1024, 1024), rel_eps=1e-5, seed=1024, device="cpu"):
     """(f, fhat, xi) for a binary64 Gaussian random field with power spectrum
     k^-3, normalised to [0, 1]; xi = rel_eps * (max f - min f).  The default
     is the 1024 x 1024 x 768 large-field workload."""
-    f = grf3d(shape, seed, device=device)
+    f = grf3d(shape, seed).to(device)
     xi = rel_eps * (float(f.max()) - float(f.min()))
     fhat = quantise_proxy(f, xi, seed)
     return f, fhat, xi

@@ -86,13 +86,30 @@ def test_blocks_reject_bad_input_and_leave_g():
         pmsz.correct_blocks(dev(f), dev(fhat), xi, (17, 1, 1))
 
 
+def sample_indices(shape, n, seed):
+    """n random vertices of a (nz, ny, nx) grid, a third of them snapped onto
+    faces, edges and corners, plus the eight corners."""
+    nz, ny, nx = shape
+    rng = np.random.default_rng(seed)
+    pts = [rng.integers(0, nx, n), rng.integers(0, ny, n), rng.integers(0, nz, n)]
+    x, y, z = [np.asarray(p, dtype=np.int64) for p in pts]
+    k = n // 3
+    x[:k:2] = 0
+    y[1:k:3] = ny - 1
+    z[2:k:5] = nz - 1
+    x[3:k:7] = nx - 1
+    idx = x + nx * (y + ny * z)
+    corners = [cx + nx * (cy + ny * cz) for cx in (0, nx - 1) for cy in (0, ny - 1)
+               for cz in (0, nz - 1)]
+    return np.unique(np.concatenate([idx, np.asarray(corners, dtype=np.int64)]))
+
+
 def test_blocks_full_size_perlin_512():
     """The 512^3 workload in 2 x 2 x 2 blocks, a size the oracle's block driver
     cannot run within a test: properties that hold at any size (directions of
     f restored everywhere, checked by the GPU verify and by the oracle at
     sampled vertices; every value within [lb, fhat]) and fewer exchanges for
     the relaxed schedule than for the per-round one."""
-    from test_gpu_large import sample_indices
     f, fhat, xi = synth.large_perlin_case(device="cuda:0")
     d = pmsz.directions(f)
     idx = sample_indices(tuple(f.shape), 4000, 512)
