@@ -60,15 +60,24 @@ def measured_traffic(kernel):
 def kernel_split(tm, rounds, s):
     """Per kernel of one correction: (total ms, launches, algorithmic bytes).
     The directions kernel reads f and writes the direction bytes (s + 1 per
-    vertex).  The engine's first round reads fhat, f and the direction bytes
-    (2s + 1 per vertex); a later round reads g and the direction bytes and
+    vertex).  Round 0's detection reads fhat, f and the direction bytes
+    (2s + 1 per vertex); a later round's reads g and the direction bytes and
     writes flag bits (s + 1.125) per vertex examined, in tiles or by sparse
-    examination; an edit reads f and g and writes g (3s)."""
-    swept = [r["swept"] for r in rounds]
-    engine_bytes = (swept[0] * (2 * s + 1) if swept else 0) + \
-        sum(swept[1:]) * (s + 1.125) + tm["edits"] * 3 * s
-    return {"k_dirs_fields": (tm["dirs_ms"], 1, tm["voxels"] * (s + 1)),
-            "k_engine": (tm["engine_ms"], 1, engine_bytes)}
+    examination; an edit reads f and g and writes g (3s).  With split sweeps
+    the tile detection of rounds 0 and 1 is the sweep kernel's (two launches)
+    and the rest the engine's (two launches)."""
+    det = [r["swept"] * ((2 * s + 1) if i == 0 else (s + 1.125)) for i, r in enumerate(rounds)]
+    tiles = [(r["swept"] - r["sparse"]) * ((2 * s + 1) if i == 0 else (s + 1.125))
+             for i, r in enumerate(rounds)]
+    edits = tm["edits"] * 3 * s
+    out = {"k_dirs_fields": (tm["dirs_ms"], 1, tm["voxels"] * (s + 1))}
+    if tm.get("sweeps"):
+        swept_b = sum(tiles[:2])
+        out["k_sweep"] = (tm["sweep_ms"], tm["sweeps"], swept_b)
+        out["k_engine"] = (tm["engine_ms"], 2, sum(det) - swept_b + edits)
+    else:
+        out["k_engine"] = (tm["engine_ms"], 1, sum(det) + edits)
+    return out
 
 
 GOLDEN_512 = os.path.join(ROOT, "tests", "golden", "perlin512_f32.json")
@@ -179,10 +188,12 @@ def bench_batched(dev, n_fields, seed):
         st_tuned == st_plain
     # the engine launch of the tuned batch against the HBM roofline
     alg = algorithmic_bytes(tm["voxels"], tm["swept"], tm["edits"], 4)
-    roof = {"kernel": "k_engine<float>", "engine_ms": round(tm["engine_ms"], 4),
+    loop_ms = tm["engine_ms"] + tm["sweep_ms"]
+    roof = {"kernels": "k_sweep<float> + k_engine<float>" if tm["sweeps"] else "k_engine<float>",
+            "engine_ms": round(tm["engine_ms"], 4), "sweep_ms": round(tm["sweep_ms"], 4),
             "dirs_ms": round(tm["dirs_ms"], 4), "algorithmic_bytes": alg,
-            "achieved_gbs": round(alg / (tm["engine_ms"] * 1e-3) / 1e9, 1),
-            "frac": round(alg / (tm["engine_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "achieved_gbs": round(alg / (loop_ms * 1e-3) / 1e9, 1),
+            "frac": round(alg / (loop_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "swept_vertices": tm["swept"], "edits": tm["edits"], "rounds": tm["rounds"]}
     # every field against the oracle's golden result (the recorded batch)
     oracle_same = None
@@ -225,7 +236,7 @@ def bench_small(dev, calls):
     torch.cuda.synchronize()
     us = (time.perf_counter() - t0) * 1e6 / calls
     tm = pmsz.last_timing()
-    dev_us = (tm["dirs_ms"] + tm["engine_ms"]) * 1e3
+    dev_us = (tm["dirs_ms"] + tm["sweep_ms"] + tm["engine_ms"]) * 1e3
     return {"workload": "perlin 64^3 f32, 4 octaves, 4 cells, eps 1e-3, seed 1234",
             "us_per_call": round(us, 1), "device_us": round(dev_us, 1),
             "rounds": tm["rounds"], "device_us_per_round": round(tm["engine_ms"] * 1e3 / max(tm["rounds"], 1), 1),
@@ -256,12 +267,12 @@ def bench_large(dev, steps):
         tm = pmsz.last_timing()
     ms_step = sum(ms) / len(ms)
     alg = algorithmic_bytes(tm["voxels"], tm["swept"], tm["edits"], 8)
-    dev_ms = tm["dirs_ms"] + tm["engine_ms"]
+    dev_ms = tm["dirs_ms"] + tm["sweep_ms"] + tm["engine_ms"]
     return {"workload": "grf k^-3 1024x1024x768 f64, rel eps 1e-5, seed 1024",
             "voxels": f.numel(), "steps": steps, "ms_per_step": round(ms_step, 3),
             "gvox_s": round(f.numel() / ms_step / 1e6, 3),
             "device_ms": round(dev_ms, 3), "dirs_ms": round(tm["dirs_ms"], 3),
-            "engine_ms": round(tm["engine_ms"], 3),
+            "engine_ms": round(tm["engine_ms"], 3), "sweep_ms": round(tm["sweep_ms"], 3),
             "hbm_frac": round(alg / (dev_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "iterations": st["iterations"], "edits": st["steps_applied"],
             "mismatch_initial": st["mismatch_initial"], "rounds": tm["rounds"],
@@ -392,7 +403,7 @@ def bench_blocks(f, fhat, xi, configs):
     return out
 
 
-def bench_serving(dev, rates, n_requests, pool_per_class, seed):
+def bench_serving(dev, rates, n_requests, pool_per_class, seed, max_seconds=None):
     """Open-loop serving: Poisson arrivals at each rate; requests drawn from a
     pre-generated pool (generation stays out of the loop) over five classes
     (128^3, 256^3, 512^3 Perlin; 1024^2, 4096^2 Gaussian peaks; binary32) with
@@ -424,9 +435,12 @@ def bench_serving(dev, rates, n_requests, pool_per_class, seed):
     torch.cuda.synchronize()
     out = []
     for rate in rates:
-        arr = np.cumsum(rng.exponential(1.0 / rate, size=n_requests))
-        pick = rng.integers(len(pool), size=n_requests)
-        row = {"rate_req_s": rate, "requests": n_requests}
+        # n_requests, or as many as arrive in max_seconds
+        n_req = n_requests if max_seconds is None else min(n_requests, int(rate * max_seconds))
+        arr = np.cumsum(rng.exponential(1.0 / rate, size=n_req))
+        pick = rng.integers(len(pool), size=n_req)
+        row = {"rate_req_s": rate, "requests": n_req}
+        log("serving at %g req/s: %d requests" % (rate, n_req))
         for kind in ("batched", "fifo"):
             reqs = []
             for i, (t, k) in enumerate(zip(arr, pick)):
@@ -441,9 +455,9 @@ def bench_serving(dev, rates, n_requests, pool_per_class, seed):
                     bad.append(r.rid)
 
             done = serve.run_open_loop(kind, reqs, dev, hbm_budget=96 << 30, max_fields=64,
-                                       rounds_per_step=4, check=check)
+                                       rounds_per_step=0, check=check)
             s = serve.latency_summary(done)
-            s["identical"] = not bad and len(done) == n_requests
+            s["identical"] = not bad and len(done) == n_req
             row[kind] = s
         out.append(row)
     return out
@@ -465,6 +479,8 @@ def main():
     ap.add_argument("--serve-rates", default="50,200,500",
                     help="Poisson arrival rates (req/s) of the serving comparison ('' skips it)")
     ap.add_argument("--serve-requests", type=int, default=200)
+    ap.add_argument("--serve-seconds", type=float, default=None,
+                    help="cap each rate's arrivals at this many seconds (with --serve-requests)")
     ap.add_argument("--serve-pool", type=int, default=4,
                     help="pre-generated fields per request class")
     ap.add_argument("--small-calls", type=int, default=50,
@@ -503,7 +519,11 @@ def main():
         torch.cuda.synchronize()
         dst.copy_(src)  # a device-to-device copy: HIP's copy kernel reads and writes the size once
         torch.cuda.synchronize()
-        log("copy probe: %d MiB read, %d MiB written" % (args.copy_probe_mib, args.copy_probe_mib))
+        # read-only probes in the marches' load shapes: dword rows, byte rows
+        pmsz.probe_read(src, 0)
+        pmsz.probe_read(src, 1)
+        log("copy probe: %d MiB read, %d MiB written; read probes: %d MiB as dword rows, "
+            "%d MiB as byte rows" % ((args.copy_probe_mib,) * 4))
         del src, dst
 
     log("warmup", W)
@@ -609,7 +629,8 @@ def main():
     if args.serve_rates:
         rates = [float(x) for x in args.serve_rates.split(",") if x]
         log("serving: rates", rates, "x", args.serve_requests, "requests")
-        out["serving"] = bench_serving(dev, rates, args.serve_requests, args.serve_pool, 7)
+        out["serving"] = bench_serving(dev, rates, args.serve_requests, args.serve_pool, 7,
+                                       args.serve_seconds)
         torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) on", args.cpu_planes, "planes")

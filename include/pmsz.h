@@ -203,6 +203,13 @@ int pmsz_correct_batched(int32_t n, const pmsz_field* fields, void* ws, size_t w
  * detect pass reads).  The target is kept per (ndim, dtype) for the whole
  * process and read when a correction, batch or session field is planned.
  * pmsz_set_tiles_target: 0 restores the default.  Host-only, thread-safe.
+ * Tune cache: when the environment variable PMSZ_TUNE_CACHE names a file,
+ * the targets it records (a JSON object with the keys "2d_f32", "2d_f64",
+ * "3d_f32", "3d_f64"; absent keys and unreadable or malformed files keep the
+ * default) are installed before the first target is read or set in the
+ * process, and pmsz_tune_tiles rewrites the file with every current target
+ * (PMSZ_ERR_INVALID_ARG when it cannot be written; the tuned target is
+ * installed either way).
  * pmsz_tune_tiles: the autotuner.  Corrects the batch `fields` (g holds fhat
  * and is NOT modified; copies are corrected in ws) once per candidate target,
  * `reps` times each, measures the device time of each run (directions pass +
@@ -350,6 +357,23 @@ int pmsz_session_add(pmsz_session* s, const pmsz_field* field, int64_t max_iters
                      size_t field_ws_bytes, int32_t* handle);
 /* Enqueue one step (max_rounds >= 1).  At most one step may be in flight. */
 int pmsz_session_step(pmsz_session* s, int64_t max_rounds);
+/* pmsz_session_step with max_rounds < 1 meaning "until every field is done",
+ * and flags: PMSZ_STEP_STOP_ON_DONE ends the step after the round in which a
+ * field is first seen finished (its result can then be collected while the
+ * others continue in the next step).  A step also ends after the round in
+ * progress when pmsz_session_request_stop is called (at most two rounds
+ * later).  Results do not depend on where steps end. */
+#define PMSZ_STEP_STOP_ON_DONE 1
+int pmsz_session_step_ex(pmsz_session* s, int64_t max_rounds, int32_t flags);
+/* Asks the step in flight to end after its current round (a new request is
+ * waiting); thread-safe; spent by the next step's launch. */
+int pmsz_session_request_stop(pmsz_session* s);
+/* *running = 1 while the step in flight has not ended (non-blocking). */
+int pmsz_session_query(pmsz_session* s, int32_t* running);
+/* After a sync: the handles (up to cap) and stats of the fields that
+ * finished in that step; *n receives their number. */
+int pmsz_session_finished(pmsz_session* s, int32_t cap, int32_t* handles, pmsz_stats* stats,
+                          int32_t* n);
 /* Wait for the step in flight and collect its results; *n_done (nullable)
  * receives how many fields finished in it. */
 int pmsz_session_sync(pmsz_session* s, int32_t* n_done);
@@ -365,19 +389,22 @@ int pmsz_session_destroy(pmsz_session* s);
  * events recorded on the caller's stream around each launch, and the work it
  * did.  Used by the benchmark for roofline figures. */
 typedef struct {
-  double engine_ms;  /* the persistent correction kernel                       */
-  int64_t rounds;    /* detect/apply rounds it ran                            */
+  double engine_ms;  /* the persistent correction kernel (all its launches)   */
+  int64_t rounds;    /* detect/apply rounds run                               */
   int64_t swept;     /* vertices examined by detect passes, all rounds        */
   int64_t edits;     /* value changes, all fields                             */
   int64_t voxels;    /* vertices of the batch                                 */
   int64_t tiles;     /* tiles of the batch                                    */
   int32_t grid;      /* blocks of the cooperative launch                      */
-  int32_t reserved;
+  int32_t sweeps;    /* tile sweeps run as kernels of their own (0 or 2: the
+                        detection of rounds 0 and 1 of large batches)          */
   double first_round_ms; /* first round: validation, detect, apply            */
   double detect_ms;  /* detect phases of the later rounds (block 0's clock)    */
   double apply_ms;   /* apply phases of the later rounds                       */
   double dirs_ms;    /* directions of f, computed before the correction kernel
                         (0 when the caller gave them)                           */
+  double sweep_ms;   /* the sweep kernels; engine_ms covers the engine
+                        launches only                                           */
 } pmsz_timing;
 int pmsz_last_timing(pmsz_timing* out);
 
@@ -401,6 +428,17 @@ typedef struct {
  * number recorded (<= 64) in *n.  Returns PMSZ_ERR_INVALID_ARG if n is NULL,
  * or if out is NULL while cap > 0. */
 int pmsz_last_rounds(pmsz_round* out, int64_t cap, int64_t* n);
+
+/* Counter calibration (measurement aid, not part of the method): reads the
+ * `bytes` bytes at device address p exactly once, as rows of dwords (pattern
+ * 0: 256 contiguous bytes per 64-lane load, the shape of a plane row of
+ * binary32 values in the tile marches; bytes a multiple of 4) or rows of
+ * bytes (pattern 1: 64 contiguous bytes per load, the shape of a row of
+ * direction bytes), and stores in *sum (host) the sum of the dwords / bytes.
+ * A memory counter's reading for this launch, against `bytes`, calibrates
+ * that counter for the pattern.  Allocates 8 bytes of device memory for the
+ * call.  Synchronises with `stream`. */
+int pmsz_probe_read(const void* p, int64_t bytes, int32_t pattern, uint64_t* sum, void* stream);
 
 /* Frees the host resources the library keeps for reuse across calls (pinned
  * staging buffers and HIP events of every thread).  They are never freed by

@@ -28,6 +28,7 @@ STATUS = {0: "OK", 1: "INVALID_ARG", 2: "NONFINITE", 3: "INPUT_BOUND", 4: "NOT_C
 DEFAULT_MAX_ITERS = 1 << 40
 # size of the static device scratch behind pmsz_correct_noalloc
 NOALLOC_SCRATCH_BYTES = 32 << 20
+STEP_STOP_ON_DONE = 1
 
 # the last two return strings, the others a status code
 EXPORTS = ("pmsz_workspace_size", "pmsz_directions", "pmsz_correct",
@@ -35,11 +36,13 @@ EXPORTS = ("pmsz_workspace_size", "pmsz_directions", "pmsz_correct",
            "pmsz_correct_mode", "pmsz_verify", "pmsz_last_timing", "pmsz_last_rounds",
            "pmsz_session_workspace_size", "pmsz_field_workspace_size", "pmsz_session_create",
            "pmsz_session_add", "pmsz_session_step", "pmsz_session_sync", "pmsz_session_result",
-           "pmsz_session_remove", "pmsz_session_destroy", "pmsz_edits_workspace_size",
+           "pmsz_session_remove", "pmsz_session_destroy", "pmsz_session_step_ex",
+           "pmsz_session_request_stop", "pmsz_session_query", "pmsz_session_finished",
+           "pmsz_edits_workspace_size",
            "pmsz_edits_max_bytes", "pmsz_encode_edits", "pmsz_decode_edits",
            "pmsz_blocks_workspace_size", "pmsz_correct_blocks", "pmsz_set_tiles_target",
            "pmsz_get_tiles_target", "pmsz_tune_workspace_size", "pmsz_tune_tiles",
-           "pmsz_last_labels", "pmsz_release", "pmsz_correct_noalloc",
+           "pmsz_last_labels", "pmsz_release", "pmsz_correct_noalloc", "pmsz_probe_read",
            "pmsz_status_string", "pmsz_last_error")
 
 
@@ -81,12 +84,13 @@ class Report(ctypes.Structure):
 class Timing(ctypes.Structure):
     _fields_ = [("engine_ms", ctypes.c_double), ("rounds", ctypes.c_int64),
                 ("swept", ctypes.c_int64), ("edits", ctypes.c_int64), ("voxels", ctypes.c_int64),
-                ("tiles", ctypes.c_int64), ("grid", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tiles", ctypes.c_int64), ("grid", ctypes.c_int32), ("sweeps", ctypes.c_int32),
                 ("first_round_ms", ctypes.c_double), ("detect_ms", ctypes.c_double),
-                ("apply_ms", ctypes.c_double), ("dirs_ms", ctypes.c_double)]
+                ("apply_ms", ctypes.c_double), ("dirs_ms", ctypes.c_double),
+                ("sweep_ms", ctypes.c_double)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_ if k != "reserved"}
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class Round(ctypes.Structure):
@@ -171,6 +175,10 @@ def load():
     L.pmsz_session_add.argtypes = [vp, ctypes.POINTER(Field), i64, vp, sz,
                                    ctypes.POINTER(ctypes.c_int32)]
     L.pmsz_session_step.argtypes = [vp, i64]
+    L.pmsz_session_step_ex.argtypes = [vp, i64, i32]
+    L.pmsz_session_request_stop.argtypes = [vp]
+    L.pmsz_session_query.argtypes = [vp, ctypes.POINTER(i32)]
+    L.pmsz_session_finished.argtypes = [vp, i32, vp, vp, ctypes.POINTER(i32)]
     L.pmsz_session_sync.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
     L.pmsz_session_result.argtypes = [vp, i32, ctypes.POINTER(Stats),
                                       ctypes.POINTER(ctypes.c_int32)]
@@ -179,6 +187,7 @@ def load():
     L.pmsz_last_labels.argtypes = [ctypes.POINTER(LabelsInfo)]
     L.pmsz_release.argtypes = []
     L.pmsz_correct_noalloc.argtypes = [G, vp, vp, dbl, vp, i64, ctypes.POINTER(Stats), vp]
+    L.pmsz_probe_read.argtypes = [vp, i64, i32, ctypes.POINTER(ctypes.c_uint64), vp]
     L.pmsz_status_string.argtypes = [ctypes.c_int]
     L.pmsz_status_string.restype = ctypes.c_char_p
     L.pmsz_last_error.restype = ctypes.c_char_p
@@ -394,6 +403,18 @@ def tune_tiles(fields, candidates=TILE_TARGETS, reps=2):
     return best.value, {int(c): ms[i] for i, c in enumerate(candidates)}
 
 
+def probe_read(buf, pattern):
+    """Counter-calibration probe (pmsz_probe_read): reads the bytes of the
+    device tensor `buf` once as dword rows (pattern 0) or byte rows (1) and
+    returns their sum as dwords / bytes."""
+    _dev(buf, "buf")
+    out = ctypes.c_uint64()
+    _raise_if(load().pmsz_probe_read(ctypes.c_void_p(buf.data_ptr()),
+                                     buf.numel() * buf.element_size(), int(pattern),
+                                     ctypes.byref(out), _stream(buf)))
+    return out.value
+
+
 def last_timing():
     """Engine duration (HIP events on the caller's stream) and work of the last
     correction made on this thread."""
@@ -453,8 +474,35 @@ class Session:
         self._keep[h.value] = (f, g, ws)
         return h.value
 
-    def step(self, max_rounds):
-        _raise_if(load().pmsz_session_step(self._h, int(max_rounds)))
+    def step(self, max_rounds, stop_on_done=False):
+        """Launch a step (asynchronous): max_rounds rounds (< 1: until every
+        field is done); stop_on_done ends it after the round in which a field
+        is first seen finished."""
+        _raise_if(load().pmsz_session_step_ex(self._h, int(max_rounds),
+                                              STEP_STOP_ON_DONE if stop_on_done else 0))
+
+    def request_stop(self):
+        """Ask the step in flight to end after its current round."""
+        _raise_if(load().pmsz_session_request_stop(self._h))
+
+    def running(self):
+        """True while the step in flight has not ended (non-blocking)."""
+        r = ctypes.c_int32()
+        _raise_if(load().pmsz_session_query(self._h, ctypes.byref(r)))
+        return bool(r.value)
+
+    def finished(self):
+        """[(handle, stats)] of the fields that finished in the last synced
+        step."""
+        n = ctypes.c_int32()
+        L = load()
+        _raise_if(L.pmsz_session_finished(self._h, 0, None, None, ctypes.byref(n)))
+        if n.value == 0:
+            return []
+        hs = (ctypes.c_int32 * n.value)()
+        st = (Stats * n.value)()
+        _raise_if(L.pmsz_session_finished(self._h, n.value, hs, st, ctypes.byref(n)))
+        return [(hs[i], st[i].as_dict()) for i in range(n.value)]
 
     def sync(self):
         n = ctypes.c_int32()

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpmsz.so")
 SOURCES = ["stencil.hip", "engine.hip", "labels.hip", "verify.hip", "edits.hip", "blocks.hip",
-           "api.hip"]
+           "probe.hip", "api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("PMSZ_OFFLOAD_ARCH", "gfx950")
 

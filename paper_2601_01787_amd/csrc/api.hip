@@ -47,6 +47,9 @@ inline int hip_check(hipError_t e) {
 }
 
 constexpr size_t kAlign = 256;
+// Batches of at least this many vertices run the sweeps of rounds 0 and 1 as
+// their own kernels (run_batch).
+constexpr int64_t kSplitVoxels = int64_t(1) << 23;
 constexpr int64_t DEFAULT_TUNE_ITERS = int64_t(1) << 40;  // tuning runs go to convergence
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -134,7 +137,64 @@ struct BatchPlan {
 std::mutex g_tiles_mu;
 int32_t g_tiles_target[2][2] = {{0, 0}, {0, 0}};
 
+// The tune cache: a JSON object in the file the environment variable
+// PMSZ_TUNE_CACHE names, whose keys "2d_f32", "2d_f64", "3d_f32" and
+// "3d_f64" hold tiles-per-field targets (0: the default).  Read once, before
+// the first target is read or set in the process; rewritten whole by
+// pmsz_tune_tiles.  A missing or malformed file leaves the defaults.
+const char* const kTuneKeys[2][2] = {{"2d_f32", "2d_f64"}, {"3d_f32", "3d_f64"}};
+std::once_flag g_tune_cache_once;
+
+void read_tune_cache() {
+  const char* path = getenv("PMSZ_TUNE_CACHE");
+  if (!path || !*path) return;
+  FILE* fp = fopen(path, "rb");
+  if (!fp) return;
+  char buf[4096];
+  const size_t n = fread(buf, 1, sizeof(buf) - 1, fp);
+  fclose(fp);
+  buf[n] = 0;
+  std::lock_guard<std::mutex> lk(g_tiles_mu);
+  for (int a = 0; a < 2; ++a)
+    for (int b = 0; b < 2; ++b) {
+      char key[16];
+      snprintf(key, sizeof(key), "\"%s\"", kTuneKeys[a][b]);
+      const char* at = strstr(buf, key);
+      if (!at) continue;
+      at += strlen(key);
+      while (*at == ' ' || *at == '\t' || *at == '\n' || *at == '\r') ++at;
+      if (*at != ':') continue;
+      char* end = nullptr;
+      const long v = strtol(at + 1, &end, 10);
+      if (end != at + 1 && v >= 0 && v <= (1L << 30)) g_tiles_target[a][b] = (int32_t)v;
+    }
+}
+
+void ensure_tune_cache() { std::call_once(g_tune_cache_once, read_tune_cache); }
+
+// Writes every target to the cache file (when PMSZ_TUNE_CACHE is set), through
+// a temporary file and a rename.
+int write_tune_cache() {
+  const char* path = getenv("PMSZ_TUNE_CACHE");
+  if (!path || !*path) return PMSZ_OK;
+  int32_t t[2][2];
+  {
+    std::lock_guard<std::mutex> lk(g_tiles_mu);
+    memcpy(t, g_tiles_target, sizeof(t));
+  }
+  const std::string tmp = std::string(path) + ".tmp";
+  FILE* fp = fopen(tmp.c_str(), "wb");
+  if (!fp) return fail(PMSZ_ERR_INVALID_ARG, "tune cache %s: cannot write", path);
+  const int w = fprintf(fp, "{\"2d_f32\": %d, \"2d_f64\": %d, \"3d_f32\": %d, \"3d_f64\": %d}\n",
+                        t[0][0], t[0][1], t[1][0], t[1][1]);
+  const bool ok = w > 0 && fclose(fp) == 0;
+  if (!ok || rename(tmp.c_str(), path) != 0)
+    return fail(PMSZ_ERR_INVALID_ARG, "tune cache %s: cannot write", path);
+  return PMSZ_OK;
+}
+
 int32_t tiles_target(int ndim, int dtype) {
+  ensure_tune_cache();
   std::lock_guard<std::mutex> lk(g_tiles_mu);
   const int32_t t = g_tiles_target[ndim == 3][dtype == PMSZ_F64];
   return t > 0 ? t : kDefaultTilesTarget;
@@ -268,7 +328,9 @@ void release_staging(Staging& s) {
 
 // Events around the engine launch and the figures of the last run.
 struct Timing {
-  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};  // directions, engine, end
+  // directions, first sweep, first engine launch, second sweep, second
+  // engine launch, end (the sweeps and the first launch only when split)
+  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   uint64_t gen = 0;
   pmsz_timing last;
   pmsz_round rounds[kTraceRounds];
@@ -344,6 +406,9 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
   if (P.edit_mode) HIP_TRY(engine_fill(base + P.prop, P.total - P.prop, 0xFFFFFFFFu, s));
   HIP_TRY(hipMemcpyAsync(base + P.desc, stage, up, hipMemcpyHostToDevice, s));
   EngineArgs a;
+  a.tiles_swept = 0;
+  a.stop_on_done = 0;
+  a.stop_host = nullptr;
   a.fd = (const FieldDesc*)(base + P.desc);
   a.out = out;
   a.nf = n;
@@ -357,13 +422,37 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
   if (timed && (r = timing_events(tm))) return r;
   int grid = 0;
   bool need_dirs = false;
-  for (int32_t i = 0; i < n; ++i) need_dirs |= !P.fd[i].dirs_given;
-  // directions of f, then the whole correction loop in one launch
+  int64_t voxels = 0;
+  int dims = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    need_dirs |= !P.fd[i].dirs_given;
+    voxels += P.fd[i].geo.n;
+    dims |= P.fd[i].geo.ndim == 3 ? 4 : 2;
+  }
+  // Directions of f, then the correction loop.  Large batches run the tile
+  // detection of rounds 0 and 1 (full sweeps: every tile in round 0, nearly
+  // every one in round 1) as plain kernels at the march's own occupancy,
+  // each followed by an engine launch that starts with that round's apply;
+  // small ones keep the whole loop in one launch (the extra launches would
+  // cost more than they save).
+  const bool split = voxels >= kSplitVoxels;
   if (timed) HIP_TRY(hipEventRecord(tm.ev[0], s));
   if (need_dirs) HIP_TRY(engine_dirs(dtype, a.fd, n, P.total_tiles, s));
   if (timed) HIP_TRY(hipEventRecord(tm.ev[1], s));
+  if (split) {
+    a.tiles_swept = 1;
+    a.max_rounds = 1;
+    HIP_TRY(engine_sweep(dtype, KIND_FIRST_GIVEN, P.edit_mode != 0, dims, a, s));
+    if (timed) HIP_TRY(hipEventRecord(tm.ev[2], s));
+    HIP_TRY(engine_launch(dtype, a, s, &grid));
+    if (timed) HIP_TRY(hipEventRecord(tm.ev[3], s));
+    a.has_fresh = 0;
+    a.max_rounds = -1;
+    HIP_TRY(engine_sweep(dtype, KIND_NEXT, P.edit_mode != 0, dims, a, s));
+    if (timed) HIP_TRY(hipEventRecord(tm.ev[4], s));
+  }
   HIP_TRY(engine_launch(dtype, a, s, &grid));
-  if (timed) HIP_TRY(hipEventRecord(tm.ev[2], s));
+  if (timed) HIP_TRY(hipEventRecord(tm.ev[5], s));
   // the staging buffer is reused for the results: the upload above is
   // stream-ordered before this copy, so it has been consumed
   HIP_TRY(hipMemcpyAsync(stage, ctl, kCtlHostBytes, hipMemcpyDeviceToHost, s));
@@ -388,17 +477,24 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
     if (first != PMSZ_OK) return fail(first, "%s", pmsz_status_string(first));
     return PMSZ_OK;
   }
-  float el[2];
-  for (int k = 0; k < 2; ++k) HIP_TRY(hipEventElapsedTime(&el[k], tm.ev[k], tm.ev[k + 1]));
+  float el[5] = {0.f, 0.f, 0.f, 0.f, 0.f};
+  HIP_TRY(hipEventElapsedTime(&el[0], tm.ev[0], tm.ev[1]));
+  if (split) {
+    for (int k = 1; k < 5; ++k) HIP_TRY(hipEventElapsedTime(&el[k], tm.ev[k], tm.ev[k + 1]));
+  } else {
+    HIP_TRY(hipEventElapsedTime(&el[4], tm.ev[1], tm.ev[5]));
+  }
   memset(&tm.last, 0, sizeof(tm.last));
   tm.last.dirs_ms = el[0];
-  tm.last.engine_ms = el[1];
-  tm.last.rounds = (int64_t)hc->rounds;
+  tm.last.sweep_ms = el[1] + el[3];
+  tm.last.sweeps = split ? 2 : 0;
+  tm.last.engine_ms = el[2] + el[4];
+  tm.last.rounds = (int64_t)hc->epoch;  // the workspace starts every call at round 0
   tm.last.tiles = P.total_tiles;
   tm.last.grid = grid;
   {
-    const int64_t R = hc->rounds < (unsigned long long)kTraceRounds ? (int64_t)hc->rounds
-                                                                       : kTraceRounds;
+    const int64_t R = hc->epoch < (unsigned long long)kTraceRounds ? (int64_t)hc->epoch
+                                                                      : kTraceRounds;
     tm.nrounds = R;
     for (int64_t r = 0; r < R; ++r) {
       const unsigned long long* t = tr + kTraceSlots * r;
@@ -410,6 +506,7 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
       o.flagged = (int64_t)t[4];
       o.edits = (int64_t)t[5];
       o.sparse = (int64_t)t[6];
+      if (split && r < 2) o.detect_ms += (double)el[r == 0 ? 1 : 3];  // the sweep kernel
       if (r == 0) {
         tm.last.first_round_ms = o.detect_ms + o.apply_ms;
       } else {
@@ -581,6 +678,8 @@ struct pmsz_session {
   std::unordered_map<int32_t, Entry> fields;
   std::vector<int32_t> order;  // insertion order of live handles
   std::vector<int32_t> stepped;  // handles of the last step, in descriptor order
+  std::vector<int32_t> finished;  // handles that finished in the last synced step
+  unsigned* stop_word = nullptr;  // pinned host word the engine polls (stop requests)
   pmsz_timing last;
 };
 
@@ -866,6 +965,27 @@ int pmsz_correct_noalloc(const pmsz_grid* grid, const void* f, void* g, double x
   return run_batch(grid->dtype, P, given, ws, stats, s, stage, false);
 }
 
+int pmsz_probe_read(const void* p, int64_t bytes, int32_t pattern, uint64_t* sum, void* stream) {
+  if (!p || !sum) return fail(PMSZ_ERR_INVALID_ARG, "NULL argument");
+  if (bytes < 0 || (pattern == 0 && bytes % 4) || (pattern != 0 && pattern != 1))
+    return fail(PMSZ_ERR_INVALID_ARG, "bytes must be >= 0 (a multiple of 4 for pattern 0); "
+                "pattern 0 or 1");
+  if ((uintptr_t)p % 4) return fail(PMSZ_ERR_INVALID_ARG, "p must be 4-byte aligned");
+  const hipStream_t s = (hipStream_t)stream;
+  unsigned long long* d = nullptr;
+  HIP_TRY(hipMallocAsync((void**)&d, sizeof(*d), s));
+  int r = hip_check(engine_zero(d, 8, s));
+  if (!r) r = hip_check(launch_probe_read(p, bytes, pattern, d, s));
+  unsigned long long h = 0;
+  if (!r) r = hip_check(hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, s));
+  const int r2 = hip_check(hipFreeAsync(d, s));
+  if (!r) r = r2;
+  if (!r) r = hip_check(hipStreamSynchronize(s));
+  if (r) return r;
+  *sum = h;
+  return PMSZ_OK;
+}
+
 int pmsz_edits_workspace_size(const pmsz_grid* grid, int64_t max_edits, size_t* bytes) {
   int r = check_grid(grid);
   if (r) return r;
@@ -1034,6 +1154,7 @@ int pmsz_correct_batched(int32_t n, const pmsz_field* fields, void* ws, size_t w
 int pmsz_set_tiles_target(int32_t ndim, int32_t dtype, int32_t target) {
   if ((ndim != 2 && ndim != 3) || (dtype != PMSZ_F32 && dtype != PMSZ_F64) || target < 0)
     return fail(PMSZ_ERR_INVALID_ARG, "bad ndim, dtype or target");
+  ensure_tune_cache();  // an explicit setting overrides the cache
   std::lock_guard<std::mutex> lk(g_tiles_mu);
   g_tiles_target[ndim == 3][dtype == PMSZ_F64] = target;
   return PMSZ_OK;
@@ -1111,7 +1232,7 @@ int pmsz_tune_tiles(int32_t n, const pmsz_field* fields, const int32_t* candidat
       }
       r = run_batch(fields[0].grid.dtype, P, nullptr, base + (total - P.total), st.data(), s);
       if (r != PMSZ_OK && r != PMSZ_ERR_NOT_CONVERGED && r != PMSZ_ERR_STALLED) return r;
-      const double t = t_timing.last.dirs_ms + t_timing.last.engine_ms;
+      const double t = t_timing.last.dirs_ms + t_timing.last.sweep_ms + t_timing.last.engine_ms;
       if (k == 0 || t < t_min) t_min = t;
     }
     if (ms) ms[c] = t_min;
@@ -1121,7 +1242,8 @@ int pmsz_tune_tiles(int32_t n, const pmsz_field* fields, const int32_t* candidat
     }
   }
   *best = best_t;
-  return pmsz_set_tiles_target(fields[0].grid.ndim, fields[0].grid.dtype, best_t);
+  if ((r = pmsz_set_tiles_target(fields[0].grid.ndim, fields[0].grid.dtype, best_t))) return r;
+  return write_tune_cache();
 }
 
 int pmsz_blocks_workspace_size(const pmsz_grid* grid, const int32_t* blocks, size_t* bytes) {
@@ -1293,8 +1415,14 @@ int pmsz_session_create(int32_t dtype, int32_t max_fields, void* ws, size_t ws_b
   S->out_off = S->desc_off + align_up(sizeof(FieldDesc) * (size_t)max_fields);
   S->stream = (hipStream_t)stream;
   hipError_t e = hipEventCreateWithFlags(&S->ev, hipEventDisableTiming);
-  if (e == hipSuccess) e = engine_zero(S->ws, align_up(sizeof(EngineCtl)), S->stream);
+  if (e == hipSuccess) e = hipHostMalloc((void**)&S->stop_word, 64, hipHostMallocDefault);
+  if (e == hipSuccess) {
+    __atomic_store_n(S->stop_word, 0u, __ATOMIC_RELAXED);
+    e = engine_zero(S->ws, align_up(sizeof(EngineCtl)), S->stream);
+  }
   if (e != hipSuccess) {
+    if (S->ev) (void)hipEventDestroy(S->ev);
+    if (S->stop_word) (void)hipHostFree(S->stop_word);
     delete S;
     return fail(PMSZ_ERR_DEVICE, "session setup failed: %s", hipGetErrorString(e));
   }
@@ -1339,9 +1467,46 @@ int pmsz_session_add(pmsz_session* S, const pmsz_field* field, int64_t max_iters
 }
 
 int pmsz_session_step(pmsz_session* S, int64_t max_rounds) {
+  if (max_rounds < 1) return fail(PMSZ_ERR_INVALID_ARG, "max_rounds must be >= 1");
+  return pmsz_session_step_ex(S, max_rounds, 0);
+}
+
+int pmsz_session_request_stop(pmsz_session* S) {
+  if (!S) return fail(PMSZ_ERR_INVALID_ARG, "NULL session");
+  __atomic_store_n(S->stop_word, 1u, __ATOMIC_RELEASE);
+  return PMSZ_OK;
+}
+
+int pmsz_session_query(pmsz_session* S, int32_t* running) {
+  if (!S || !running) return fail(PMSZ_ERR_INVALID_ARG, "NULL argument");
+  *running = 0;
+  if (!S->pending) return PMSZ_OK;
+  const hipError_t e = hipEventQuery(S->ev);
+  if (e == hipErrorNotReady) {
+    *running = 1;
+    return PMSZ_OK;
+  }
+  HIP_TRY(e);
+  return PMSZ_OK;
+}
+
+int pmsz_session_finished(pmsz_session* S, int32_t cap, int32_t* handles, pmsz_stats* stats,
+                          int32_t* n) {
+  if (!S || !n || (cap > 0 && !handles)) return fail(PMSZ_ERR_INVALID_ARG, "NULL argument");
+  const int32_t k = (int32_t)S->finished.size();
+  *n = k;
+  for (int32_t i = 0; i < k && i < cap; ++i) {
+    handles[i] = S->finished[i];
+    if (stats) stats[i] = S->fields[S->finished[i]].st;
+  }
+  return PMSZ_OK;
+}
+
+int pmsz_session_step_ex(pmsz_session* S, int64_t max_rounds, int32_t flags) {
   if (!S) return fail(PMSZ_ERR_INVALID_ARG, "NULL session");
   if (S->pending) return fail(PMSZ_ERR_INVALID_ARG, "a step is in flight: sync first");
-  if (max_rounds < 1) return fail(PMSZ_ERR_INVALID_ARG, "max_rounds must be >= 1");
+  if (flags & ~PMSZ_STEP_STOP_ON_DONE) return fail(PMSZ_ERR_INVALID_ARG, "unknown step flags");
+  if (max_rounds < 1) max_rounds = -1;  // until every field is done or a stop
   S->stepped.clear();
   std::vector<FieldDesc> fd;
   int64_t tiles = 0, segs = 0;
@@ -1369,6 +1534,9 @@ int pmsz_session_step(pmsz_session* S, int64_t max_rounds) {
   HIP_TRY(hipMemcpyAsync(S->ws + S->desc_off, up, sizeof(FieldDesc) * (size_t)n,
                          hipMemcpyHostToDevice, S->stream));
   EngineArgs a;
+  a.tiles_swept = 0;
+  a.stop_on_done = 0;
+  a.stop_host = nullptr;
   a.fd = (const FieldDesc*)(S->ws + S->desc_off);
   a.out = (FieldIter*)(S->ws + S->out_off);
   a.nf = n;
@@ -1378,6 +1546,11 @@ int pmsz_session_step(pmsz_session* S, int64_t max_rounds) {
   a.total_segs = segs;
   a.max_rounds = max_rounds;
   a.trace = nullptr;
+  a.stop_on_done = (flags & PMSZ_STEP_STOP_ON_DONE) ? 1 : 0;
+  a.stop_host = S->stop_word;
+  // a stop requested before this launch is spent (the host's store is
+  // ordered before the launch that reads the word)
+  __atomic_store_n(S->stop_word, 0u, __ATOMIC_RELEASE);
   int grid = 0;
   HIP_TRY(engine_launch(S->dtype, a, S->stream, &grid));
   HIP_TRY(hipMemcpyAsync(down, S->ws, kCtlHostBytes, hipMemcpyDeviceToHost, S->stream));
@@ -1401,6 +1574,7 @@ int pmsz_session_sync(pmsz_session* S, int32_t* n_done) {
     if (hc->error) return fail(PMSZ_ERR_DEVICE, "grid barrier timed out in the correction engine");
     S->epoch = hc->epoch;
     S->last.rounds = (int64_t)hc->rounds;
+    S->finished.clear();
     for (size_t i = 0; i < S->stepped.size(); ++i) {
       pmsz_session::Entry& e = S->fields[S->stepped[i]];
       fill_stats(hs[i], e.st);
@@ -1409,6 +1583,7 @@ int pmsz_session_sync(pmsz_session* S, int32_t* n_done) {
       if (hs[i].done && !e.done) {
         e.done = 1;
         ++finished;
+        S->finished.push_back(S->stepped[i]);
       }
     }
   }
@@ -1443,6 +1618,7 @@ int pmsz_session_destroy(pmsz_session* S) {
   if (!S) return PMSZ_OK;
   if (S->pending) (void)hipEventSynchronize(S->ev);
   if (S->ev) (void)hipEventDestroy(S->ev);
+  if (S->stop_word) (void)hipHostFree(S->stop_word);
   release_staging(S->up);
   release_staging(S->down);
   delete S;

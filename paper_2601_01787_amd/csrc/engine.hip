@@ -762,25 +762,39 @@ __device__ __forceinline__ void flush_counts(gptr<CtrSlot> c, unsigned long long
   }
 }
 
-template <class T, int SETS>
+// Tile detection of round E over the grid's share of the tiles.  ONLY < 0:
+// each field by its state (the engine); ONLY = KIND_FIRST_GIVEN: every tile
+// of the fields in their first round, unmarked (engine_sweep); ONLY =
+// KIND_NEXT: the marked tiles of fields in a tile round (engine_sweep).
+template <class T, int SETS, int ONLY = -1, bool PROP = true, int DIM = 0>
 __device__ void detect_tiles(const EngineArgs& a, TileLds<T>& sm, unsigned long long* red,
-                             uint16_t* s_tiles, int* s_scan, unsigned long long E,
-                             unsigned long long E0, int64_t first, unsigned G) {
+                             uint16_t* s_tiles, int* s_scan, unsigned long long* s_acc,
+                             unsigned long long E, unsigned long long E0, int64_t first,
+                             unsigned G) {
   const int tid = threadIdx.x;
   const int p = (int)(E & 1);
   const int q = (int)(E % 3);
   EngineCtl* ctl = a.ctl;
-  unsigned long long acc_m = 0, acc_nf = 0, acc_nb = 0, acc_sw = 0;
+  // the current field's counts, kept by thread 0 in LDS (registers are the
+  // tile march's)
+  unsigned long long &acc_m = s_acc[0], &acc_nf = s_acc[1], &acc_nb = s_acc[2],
+                     &acc_sw = s_acc[3];
+  if (tid == 0) acc_m = acc_nf = acc_nb = acc_sw = 0;
   int cur = -1, cached = -1, cached_kind = -1;
   for (int64_t base = first; base < a.total_tiles; base += (int64_t)G * 256) {
     const int64_t mine = base + (int64_t)tid * G;
     int take = 0;
     if (mine < a.total_tiles) {
       const FieldDesc& d = a.fd[field_of_tile(a.fd, a.nf, mine)];
-      const gptr<uint8_t> flag = as_global(d.act) + p * tile_count(d.geo) + (mine - d.tile_base);
-      if (*flag) {
-        *flag = 0;
-        take = 1;
+      if (ONLY == KIND_FIRST_GIVEN) {
+        const FieldIter s = state_at(d, E, E0);
+        take = !s.started && !s.done;
+      } else {
+        const gptr<uint8_t> flag = as_global(d.act) + p * tile_count(d.geo) + (mine - d.tile_base);
+        if (*flag) {
+          *flag = 0;
+          take = 1;
+        }
       }
     }
     int n_act = 0;
@@ -788,7 +802,8 @@ __device__ void detect_tiles(const EngineArgs& a, TileLds<T>& sm, unsigned long 
     if (take) s_tiles[pos] = (uint16_t)tid;
     __syncthreads();
     for (int j = 0; j < n_act; ++j) {
-      const int64_t tt = base + (int64_t)s_tiles[j] * G;
+      // uniform over the block: read once and kept in scalar registers
+      const int64_t tt = base + (int64_t)__builtin_amdgcn_readfirstlane(s_tiles[j]) * G;
       const int fi = field_of_tile(a.fd, a.nf, tt);
       if (fi != cached) {
         const FieldIter s = state_at(a.fd[fi], E, E0);
@@ -797,8 +812,9 @@ __device__ void detect_tiles(const EngineArgs& a, TileLds<T>& sm, unsigned long 
                     : s.started ? KIND_NEXT : KIND_FIRST_GIVEN;
       }
       const int kind = cached_kind;
-      if (kind < 0) continue;
+      if (kind < 0 || (ONLY >= 0 && kind != ONLY)) continue;
       const FieldDesc& d = a.fd[fi];
+      if (DIM != 0 && d.geo.ndim != DIM) continue;  // the other dimension's kernel
       if (tid == 0 && fi != cur) {
         if (cur >= 0) {
           flush_counts(&as_global(a.fd[cur].st)->c[q].s[ctr_slot()], acc_m, acc_nf, acc_nb,
@@ -811,17 +827,18 @@ __device__ void detect_tiles(const EngineArgs& a, TileLds<T>& sm, unsigned long 
       const T* g = (const T*)d.g;
       const T* f = (const T*)d.f;
       const T xi = (T)d.xi_t;
+      void* const prop = PROP ? d.prop : nullptr;  // proposals of the targeted edit
       TileCounts tc;
-      if (d.geo.ndim == 3) {
-        if (kind == KIND_NEXT)
-          tc = tile3<T, KIND_NEXT, SETS>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile, d.prop);
-        else
-          tc = tile3<T, KIND_FIRST_GIVEN, SETS>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile, d.prop);
-      } else {
-        if (kind == KIND_NEXT)
-          tc = tile2<T, KIND_NEXT, SETS>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile, d.prop);
-        else
-          tc = tile2<T, KIND_FIRST_GIVEN, SETS>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile, d.prop);
+      if (DIM == 3 || (DIM == 0 && d.geo.ndim == 3)) {
+        if (ONLY != KIND_FIRST_GIVEN && kind == KIND_NEXT)
+          tc = tile3<T, KIND_NEXT, SETS>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile, prop);
+        else if (ONLY != KIND_NEXT)
+          tc = tile3<T, KIND_FIRST_GIVEN, SETS>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile, prop);
+      } else if (DIM != 3) {
+        if (ONLY != KIND_FIRST_GIVEN && kind == KIND_NEXT)
+          tc = tile2<T, KIND_NEXT, SETS>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile, prop);
+        else if (ONLY != KIND_NEXT)
+          tc = tile2<T, KIND_FIRST_GIVEN, SETS>(sm, red, g, f, d.dirs, d.bm, xi, d.geo, tile, prop);
       }
       if (tid == 0) {
         acc_m += unpack3(tc, 0);
@@ -842,6 +859,7 @@ template <class T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 3))) void k_engine(EngineArgs a) {
   __shared__ TileLds<T> sm;
   __shared__ unsigned long long red[4];
+  __shared__ unsigned long long s_acc[4];
   __shared__ uint16_t s_tiles[256];
   __shared__ long long s_pre[256];
   __shared__ uint32_t s_slot[256 * kCtrSlots];
@@ -857,10 +875,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
   const unsigned long long E0 = ctl->epoch;
   unsigned long long E = E0;
   const bool tracer = a.trace && blockIdx.x == 0 && tid == 0;
-  if (tracer) a.trace[kTraceRounds * kTraceSlots] = wall_clock64();
+  if (tracer && E0 == 0) a.trace[kTraceRounds * kTraceSlots] = wall_clock64();
 
   // Fields that have not started: every tile is active in their first round.
-  if (a.has_fresh) {
+  if (a.has_fresh && !a.tiles_swept) {
     for (int64_t tt = (int64_t)blockIdx.x * 256 + tid; tt < a.total_tiles; tt += (int64_t)G * 256) {
       const FieldDesc& d = a.fd[field_of_tile(a.fd, a.nf, tt)];
       const FieldIter s = load_iter(&as_global(d.st)->s[E0 & 1]);
@@ -879,16 +897,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     if (engine_failed(ctl)) break;
     const int p = (int)(E & 1);
     const int q = (int)(E % 3), qn = (int)((E + 1) % 3);
-    if (tracer && r < kTraceRounds) a.trace[kTraceSlots * r] = wall_clock64();
+    if (tracer && E < kTraceRounds) a.trace[kTraceSlots * E] = wall_clock64();
 
-    // ---- block 0: persist the state of round E, clear next-but-one counters
+    // ---- block 0: persist the state of round E, clear next-but-one counters;
+    // a field finished at E (stop_on_done) or the host's request ends the
+    // launch after this round (every block reads the word after the detect
+    // barrier)
     if (blockIdx.x == 0) {
+      bool stop = false;
       for (int fi = tid; fi < a.nf; fi += 256) {
         const FieldDesc& d = a.fd[fi];
         const gptr<FieldState> st = as_global(d.st);
-        if (E > E0) store_iter(&st->s[p], state_at(d, E, E0));
+        if (E > E0) {
+          const FieldIter s = state_at(d, E, E0);
+          store_iter(&st->s[p], s);
+          stop |= a.stop_on_done && s.done && !st->s[p ^ 1].done;
+        }
         clear_ctr(&st->c[qn]);
       }
+      if (tid == 0 && a.stop_host &&
+          __hip_atomic_load(a.stop_host, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0u)
+        stop = true;
+      if (stop) __hip_atomic_store(&ctl->stop.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (tid < kCtrSlots) {
         ctl->tot[qn][tid].edits = 0;
         ctl->tot[qn][tid].swept = 0;
@@ -945,12 +975,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     }
     // Tiles: skipped when every running field is in a sparse round (marks
     // left from earlier rounds then only widen a later tile round).
-    if (any_tiles)
-      detect_tiles<T, sets_for<T, KIND_NEXT>()>(a, sm, red, s_tiles, s_scan, E, E0, blockIdx.x,
-                                                G);
+    if (any_tiles && !(r == 0 && a.tiles_swept))
+      detect_tiles<T, sets_for<T, KIND_NEXT>()>(a, sm, red, s_tiles, s_scan, s_acc, E, E0,
+                                                blockIdx.x, G);
     xcd_sync(ctl, xb, gen);
     if (engine_failed(ctl)) break;
-    if (tracer && r < kTraceRounds) a.trace[kTraceSlots * r + 1] = wall_clock64();
+    // written by block 0 before the barrier above
+    const bool stop_here =
+        __hip_atomic_load(&ctl->stop.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+    if (tracer && E < kTraceRounds) a.trace[kTraceSlots * E + 1] = wall_clock64();
 
     // ---- apply -------------------------------------------------------------
     // One pass per 4096-word segment of each field's flag bitmap, or per part
@@ -1000,8 +1033,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     }
     xcd_sync(ctl, xb, gen);
     if (engine_failed(ctl)) break;
-    if (tracer && r < kTraceRounds) {
-      unsigned long long* t = a.trace + kTraceSlots * r;
+    if (tracer && E < kTraceRounds) {
+      unsigned long long* t = a.trace + kTraceSlots * E;
       const RoundTot rt = load_tot(ctl, q);
       t[2] = wall_clock64();
       t[3] = rt.swept;
@@ -1011,7 +1044,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     }
     const unsigned long long edited = load_edits(ctl, q);
     ++E;
-    if (edited == 0) break;
+    if (edited == 0 || stop_here) break;
   }
   // persist the state at the start of the next round, and gather it
   if (blockIdx.x == 0 && !engine_failed(ctl)) {
@@ -1044,6 +1077,32 @@ __global__ __launch_bounds__(256) void k_dirs_fields(const FieldDesc* fd, int nf
     else
       tile2<T, KIND_DIRS>(sm, nullptr, f, f, d.dirs, nullptr, T(0), d.geo, tt - d.tile_base);
   }
+}
+
+// The sweep kernels' occupancy and prefetch depth (measured on the 512^3
+// binary32 workload: seven waves per SIMD with two plane sets in flight beat
+// five or six waves and four sets, spills included; binary64 keeps the
+// engine's three waves).
+constexpr int kSweepSets = 2;
+constexpr int kSweepWaves32 = 7, kSweepWaves64 = 3;
+
+// Tile detection of the round the workspace's epoch names, as a plain kernel
+// (see engine_sweep in engine.hpp); it adds to the same counters, flag
+// bitmaps and totals as the engine's own tile detection.
+template <class T, int KIND, bool PROP, int DIM, int SETS>
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? kSweepWaves32 : kSweepWaves64)))
+void k_sweep(EngineArgs a) {
+  __shared__ TileLds<T> sm;
+  __shared__ unsigned long long red[4];
+  __shared__ uint16_t s_tiles[256];
+  __shared__ int s_scan[4];
+  __shared__ unsigned long long s_acc[4];
+  for (int k = threadIdx.x; k < kFlagWords; k += 256) sm.flags[k] = 0u;
+  __syncthreads();
+  const unsigned long long E = a.ctl->epoch;  // written by the previous launch
+  detect_tiles<T, SETS, KIND, PROP, DIM>(a, sm, red, s_tiles, s_scan, s_acc, E, E, blockIdx.x,
+                                         gridDim.x);
 }
 
 hipError_t engine_dirs(int dtype, const FieldDesc* fd, int nf, int64_t total_tiles,
@@ -1083,22 +1142,68 @@ hipError_t engine_zero(void* p, size_t bytes, hipStream_t s) { return engine_fil
 struct Occupancy {
   int per_cu = -1, cus = -1;
 };
-template <class T>
-static hipError_t occupancy(int dev, Occupancy& out) {
+// Resident blocks per compute unit of a 256-thread kernel on a device, and
+// the device's compute units (cached per kernel and device).
+static hipError_t occupancy_of(const void* kernel, int dev, Occupancy& out) {
   static std::mutex mu;
-  static std::map<int, Occupancy> cache;
+  static std::map<std::pair<const void*, int>, Occupancy> cache;
   std::lock_guard<std::mutex> lk(mu);
-  auto it = cache.find(dev);
+  auto it = cache.find({kernel, dev});
   if (it == cache.end()) {
     Occupancy o;
     hipError_t e = hipDeviceGetAttribute(&o.cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&o.per_cu, k_engine<T>, 256, 0);
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&o.per_cu, kernel, 256, 0);
     if (e != hipSuccess) return e;
-    it = cache.emplace(dev, o).first;
+    it = cache.emplace(std::make_pair(kernel, dev), o).first;
   }
   out = it->second;
   return hipSuccess;
+}
+template <class T>
+static hipError_t occupancy(int dev, Occupancy& out) {
+  return occupancy_of((const void*)k_engine<T>, dev, out);
+}
+
+// One block per resident slot of the chip (every block resident at once),
+// at most one per tile.
+template <class T, int KIND, bool PROP, int DIM>
+static hipError_t sweep_t(const EngineArgs& a, hipStream_t s) {
+  constexpr int SETS = kSweepSets;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  Occupancy occ;
+  if ((e = occupancy_of((const void*)k_sweep<T, KIND, PROP, DIM, SETS>, dev, occ)) != hipSuccess)
+    return e;
+  int64_t grid = (int64_t)(occ.per_cu > 0 ? occ.per_cu : 1) * (occ.cus > 0 ? occ.cus : 1);
+  if (grid > a.total_tiles) grid = a.total_tiles;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL((k_sweep<T, KIND, PROP, DIM, SETS>), dim3((unsigned)grid), dim3(256), 0, s,
+                     a);
+  return hipGetLastError();
+}
+
+template <class T, int DIM>
+static hipError_t sweep_kind(int kind, bool prop, const EngineArgs& a, hipStream_t s) {
+  if (kind == KIND_FIRST_GIVEN)
+    return prop ? sweep_t<T, KIND_FIRST_GIVEN, true, DIM>(a, s)
+                : sweep_t<T, KIND_FIRST_GIVEN, false, DIM>(a, s);
+  return prop ? sweep_t<T, KIND_NEXT, true, DIM>(a, s) : sweep_t<T, KIND_NEXT, false, DIM>(a, s);
+}
+
+template <class T>
+static hipError_t sweep_dims(int kind, bool prop, int dims, const EngineArgs& a, hipStream_t s) {
+  hipError_t e = hipSuccess;
+  if ((dims & 2) && (e = sweep_kind<T, 2>(kind, prop, a, s)) != hipSuccess) return e;
+  if (dims & 4) e = sweep_kind<T, 3>(kind, prop, a, s);
+  return e;
+}
+
+hipError_t engine_sweep(int dtype, int kind, bool prop, int dims, const EngineArgs& a,
+                        hipStream_t s) {
+  if (dtype == PMSZ_F32) return sweep_dims<float>(kind, prop, dims, a, s);
+  return sweep_dims<double>(kind, prop, dims, a, s);
 }
 
 template <class T>
@@ -1110,7 +1215,9 @@ static hipError_t launch_t(const EngineArgs& a, hipStream_t s, int* grid_out) {
   if ((e = occupancy<T>(dev, occ)) != hipSuccess) return e;
   const int per_cu = occ.per_cu, cus = occ.cus;
   // the XCD and compute-unit barrier state starts cleared in every launch
-  e = engine_fill(&a.ctl->xbar[0], sizeof(EngineCtl) - offsetof(EngineCtl, xbar), 0u, s);
+  // (the round totals after it are kept: a sweep kernel may have added to
+  // the current round's already)
+  e = engine_fill(&a.ctl->xbar[0], offsetof(EngineCtl, tot) - offsetof(EngineCtl, xbar), 0u, s);
   if (e != hipSuccess) return e;
   int64_t want = a.total_tiles > a.total_segs ? a.total_tiles : a.total_segs;
   if (want < 1) want = 1;

@@ -103,14 +103,16 @@ struct EngineCtl {
   unsigned long long rounds;    // rounds run by the last launch
   int error;                    // a grid barrier timed out
   int pad;
-  // per-launch barrier state, cleared before every launch (from xbar to the end)
+  // per-launch barrier state, cleared before every launch (from xbar up to tot)
   BarWord xbar[kXcdSlots];      // arrivals per XCD
   BarWord xtop;                 // XCDs arrived
+  BarWord stop;                 // nonzero: the launch ends after the current round
   unsigned census[kXcdSlots];   // blocks of the launch on each XCD
   unsigned census_pad[64 - kXcdSlots];
   unsigned cu_claim[kCuSlots];  // last barrier generation claimed on each unit
   unsigned cu_done[kCuSlots];   // last generation whose invalidate completed
-  // totals over all fields per round (mod 3), spread over slots like FieldCtr
+  // totals over all fields per round (mod 3), spread over slots like FieldCtr;
+  // cleared a round ahead by block 0, like the field counters
   RoundTot tot[3][kCtrSlots];
 };
 constexpr size_t kCtlHostBytes = offsetof(EngineCtl, xbar);
@@ -125,9 +127,16 @@ struct EngineArgs {
   int64_t total_segs;
   int64_t max_rounds;    // < 0: until every field is done
   unsigned long long* trace;  // nullable: per-round record (kTraceRounds x kTraceSlots)
+  int32_t tiles_swept;   // the tile detection of the launch's first round has
+                         // already run as its own kernel (engine_sweep)
+  int32_t stop_on_done;  // end the launch after the round in which a field is
+                         // first seen finished
+  unsigned* stop_host;   // nullable, host memory: nonzero asks the launch to end
+                         // after the round in progress
 };
 
-// Round trace, for the first kTraceRounds rounds of a launch: block 0 stamps
+// Round trace, for the first kTraceRounds rounds since the workspace was
+// initialised (indexed by the round number E): block 0 stamps
 // the 100 MHz wall clock at the start of a round, after its detect barrier
 // and after its apply barrier, then copies the round's totals (vertices
 // examined, flagged vertices, edits, sparse examinations); slot
@@ -143,6 +152,19 @@ hipError_t engine_launch(int dtype, const EngineArgs& a, hipStream_t s, int* gri
 // from given directions.
 hipError_t engine_dirs(int dtype, const FieldDesc* fd, int nf, int64_t total_tiles,
                        hipStream_t s);
+// Tile detection of one round as a plain kernel (no grid barrier, so it runs
+// at the march's own occupancy instead of the persistent engine's), for the
+// round the workspace's epoch names: every tile of a field in its first
+// round (kind KIND_FIRST_GIVEN) or every marked tile of a field in a tile
+// round (KIND_NEXT); fields of the other kind, finished fields and fields in
+// a sparse round are left to the engine.  The engine launch that follows
+// sets tiles_swept and skips its first round's tile detection.
+// prop: the batch uses the targeted edit (flags also propose values).  dims:
+// bit 2 set when the batch holds 2D fields, bit 4 when it holds 3D fields
+// (one kernel per dimension, each at its own occupancy).
+hipError_t engine_sweep(int dtype, int kind, bool prop, int dims, const EngineArgs& a,
+                        hipStream_t s);
+
 // Zero `bytes` bytes (multiple of 4, 4-byte aligned) with a kernel, so that
 // the call can sit inside a captured graph.
 hipError_t engine_zero(void* p, size_t bytes, hipStream_t s);

@@ -84,4 +84,9 @@ hipError_t edits_decode(int dtype, const uint8_t* table, const uint8_t* payload,
                         int64_t payload_bytes, int64_t ne, int64_t n, void* g, int* err,
                         hipStream_t s);
 
+// Counter-calibration probe (probe.hip): reads `bytes` bytes of p once, as
+// dword rows (pattern 0) or byte rows (pattern 1), adding their sum to *out.
+hipError_t launch_probe_read(const void* p, int64_t bytes, int pattern, unsigned long long* out,
+                             hipStream_t s);
+
 }  // namespace pmsz

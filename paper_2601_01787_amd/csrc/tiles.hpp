@@ -275,7 +275,7 @@ __device__ __forceinline__ void flush_flags(uint32_t* flags, const FlagBox& fb, 
 // below the largest value <= a + xi iff b < s2, or b == s2 and e2 >= 0; an
 // overflowed sum (infinite s) admits every finite b.
 template <class T>
-__device__ __forceinline__ int bound_class(T a, T b, T xi) {
+__device__ __forceinline__ int bound_class_exact(T a, T b, T xi) {
   if (!__builtin_isfinite(a) || !__builtin_isfinite(b)) return 1;
   T s1, e1, s2, e2;
   two_sum<T>(a, -xi, s1, e1);
@@ -283,6 +283,25 @@ __device__ __forceinline__ int bound_class(T a, T b, T xi) {
   const bool lo_ok = b > s1 || (b == s1 && e1 <= T(0));
   const bool hi_ok = b < s2 || (b == s2 && e2 >= T(0));
   return (lo_ok && hi_ok) ? 0 : 2;
+}
+
+// bound_class with a two-instruction test for the common case.  With
+// d = fl(b - a), |d - (b - a)| <= 2^-p |b - a| (p = 24 / 53; a subnormal
+// difference is exact), so |d| < xi (1 - 2^-(p-4)) proves |b - a| < xi: b is
+// then finite and strictly inside (a - xi, a + xi), hence inside [lb, ub].
+// A non-finite a or b makes d NaN or infinite and fails the test; so does a
+// value near a bound, and both go to the exact classification.  xi_in: xi
+// times (1 - 2^-(p-4)), rounded down (fast_margin).
+template <class T>
+__device__ __forceinline__ int bound_class(T a, T b, T xi, T xi_in) {
+  const T d = b - a;
+  if (__builtin_fabs(d) < xi_in) return 0;
+  return bound_class_exact<T>(a, b, xi);
+}
+template <class T>
+__device__ __forceinline__ T fast_margin(T xi) {
+  const T m = xi * (T(1) - T(sizeof(T) == 4 ? 1.0 / (1 << 20) : 1.0 / (1ll << 49)));
+  return m < xi ? m : next_down<T>(xi);  // strictly below xi (xi > 0)
 }
 
 // One 3D tile.  h: field whose directions are evaluated (g, or f for
@@ -314,6 +333,7 @@ __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_
   const gptr<const T> f = as_global(f_in);
   const gptr<uint8_t> dirs = as_global(dirs_in);
   const gptr<uint32_t> bm = as_global(bm_in);
+  const T xi_in = fast_margin<T>(xi);  // validation's fast test (bound_class)
   constexpr int PER = (PLANE + 255) / 256;
   constexpr bool kReadDirs = (KIND == KIND_NEXT || KIND == KIND_FIRST_GIVEN);
   constexpr bool kGivenF = (KIND == KIND_FIRST_GIVEN);
@@ -406,7 +426,7 @@ __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_
     } else {
       const int fa = d & 15, fd = d >> 4;
       if (kGivenF) {
-        const int bc = bound_class<T>(fv, centre, xi);
+        const int bc = bound_class<T>(fv, centre, xi, xi_in);
         nf += bc == 1;
         nb += bc == 2;
       }
@@ -478,6 +498,7 @@ __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_
   const gptr<const T> f = as_global(f_in);
   const gptr<uint8_t> dirs = as_global(dirs_in);
   const gptr<uint32_t> bm = as_global(bm_in);
+  const T xi_in = fast_margin<T>(xi);  // validation's fast test (bound_class)
   constexpr int PER = (RW + 255) / 256;
   constexpr bool kReadDirs = (KIND == KIND_NEXT || KIND == KIND_FIRST_GIVEN);
   constexpr bool kGivenF = (KIND == KIND_FIRST_GIVEN);
@@ -568,7 +589,7 @@ __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_
       } else {
         const int fa = d_cur & 15, fd = d_cur >> 4;
         if (kGivenF) {
-          const int bc = bound_class<T>(f_cur, gc, xi);
+          const int bc = bound_class<T>(f_cur, gc, xi, xi_in);
           nf += bc == 1;
           nb += bc == 2;
         }

@@ -48,28 +48,40 @@ def footprint(f):
 
 
 class BatchingServer:
-    """Admits requests by HBM footprint into a serving session and steps the
-    session until every request is done.
+    """Admits requests by HBM footprint into a serving session and keeps the
+    persistent correction kernel running over every admitted request.
+
+    Steps are preemptible: a step runs until every field is done, but ends
+    after the round in which a field finishes (its result is collected at
+    once) and after the current round when a waiting request can be admitted
+    (the server asks the engine to stop; the request joins the next step).
+    With `rounds_per_step` > 0 steps are instead fixed at that many rounds.
 
     Every field of a step advances in the same rounds, so a round lasts as
     long as the largest field's round; `work_budget` (vertices) caps the
     vertices admitted at once so that large fields do not hold every small
     one back for their whole run (a request larger than the budget is
-    admitted when the session is empty).  None disables the cap."""
+    admitted when the session is empty).  None disables the cap.  Requests
+    are admitted in arrival order, a request that does not fit being passed
+    by later ones that do, until it has waited `max_wait` seconds."""
 
-    def __init__(self, device, hbm_budget, max_fields=64, rounds_per_step=4,
-                 dtype=torch.float32, max_iters=1 << 40, work_budget=DEFAULT_WORK_BUDGET):
+    def __init__(self, device, hbm_budget, max_fields=64, rounds_per_step=0,
+                 dtype=torch.float32, max_iters=1 << 40, work_budget=DEFAULT_WORK_BUDGET,
+                 max_wait=0.02):
         self.device = torch.device(device)
         self.budget = int(hbm_budget)
         self.work_budget = work_budget
         self.work = 0
         self.rounds = int(rounds_per_step)
         self.max_iters = max_iters
+        self.max_wait = max_wait
         self.session = Session(dtype, max_fields, self.device)
         self.max_fields = max_fields
         self.in_use = 0
         self.active = {}
         self.steps = 0
+        self.in_flight = False
+        self.stop_sent = False
 
     def can_admit(self, req):
         if len(self.active) >= self.max_fields or self.in_use + req.footprint > self.budget:
@@ -89,31 +101,70 @@ class BatchingServer:
         self.work += req.f.numel()
         self.active[req.handle] = req
 
-    def step(self):
-        """One step over every admitted request; returns the finished ones."""
-        if not self.active:
+    def admit_from(self, pending, now):
+        """Admit waiting requests (a deque in arrival order) that fit."""
+        kept = collections.deque()
+        blocked = False
+        while pending:
+            r = pending.popleft()
+            if not blocked and self.can_admit(r):
+                self.admit(r, now)
+            else:
+                kept.append(r)
+                # the oldest request that waited too long is not passed again
+                if now - r.arrival > self.max_wait:
+                    blocked = True
+        pending.extend(kept)
+
+    def launch(self):
+        if self.active and not self.in_flight:
+            if self.rounds > 0:
+                self.session.step(self.rounds)
+            else:
+                self.session.step(0, stop_on_done=True)
+            self.in_flight = True
+            self.stop_sent = False
+            self.steps += 1
+
+    def preempt(self):
+        """End the step in flight after its current round."""
+        if self.in_flight and not self.stop_sent and self.rounds <= 0:
+            self.session.request_stop()
+            self.stop_sent = True
+
+    def poll(self, wait=False):
+        """None while the step runs (unless wait); else the finished
+        requests of the step that ended."""
+        if not self.in_flight:
             return []
-        self.session.step(self.rounds)
+        if not wait and self.session.running():
+            return None
         self.session.sync()
-        self.steps += 1
+        self.in_flight = False
         finished = []
-        for h, req in list(self.active.items()):
-            st, done = self.session.result(h)
-            if done:
-                req.stats = st
-                self.session.remove(h)
-                self.in_use -= req.footprint
-                self.work -= req.f.numel()
-                del self.active[h]
-                req.ws = None
-                finished.append(req)
+        for h, st in self.session.finished():
+            req = self.active.pop(h)
+            req.stats = st
+            self.session.remove(h)
+            self.in_use -= req.footprint
+            self.work -= req.f.numel()
+            req.ws = None
+            finished.append(req)
         return finished
 
+    def step(self):
+        """One blocking step over every admitted request; returns the
+        finished ones."""
+        self.launch()
+        return self.poll(wait=True)
+
     def close(self):
+        if self.in_flight:
+            self.poll(wait=True)
         self.session.close()
 
 
-def run_open_loop(server_kind, requests, device, hbm_budget, max_fields=64, rounds_per_step=4,
+def run_open_loop(server_kind, requests, device, hbm_budget, max_fields=64, rounds_per_step=0,
                   check=None, work_budget=DEFAULT_WORK_BUDGET):
     """Replay `requests` (sorted by arrival time, seconds from start) against
     a server in real time.  Returns the served requests.  `check(req)` (if
@@ -143,11 +194,18 @@ def _replay(server_kind, srv, arrivals, pending, done, dev, check):
         while arrivals and arrivals[0].arrival <= now:
             pending.append(arrivals.popleft())
         if server_kind == "batched":
-            while pending and srv.can_admit(pending[0]):
-                srv.admit(pending.popleft(), now)
-            if pending and not srv.active:
-                raise RuntimeError("request %d does not fit the HBM budget" % pending[0].rid)
-            finished = srv.step()
+            if srv.in_flight:
+                if pending and any(srv.can_admit(r) for r in pending):
+                    srv.preempt()
+                finished = srv.poll()
+                if finished is None:
+                    continue  # the step runs on; keep watching arrivals
+            else:
+                finished = []
+                srv.admit_from(pending, now)
+                if pending and not srv.active:
+                    raise RuntimeError("request %d does not fit the HBM budget" % pending[0].rid)
+                srv.launch()
             t = time.perf_counter() - t0
             for r in finished:
                 r.done_at = t

@@ -93,9 +93,11 @@ def test_session_matches_oracle_on_small_field():
     assert np.array_equal(g.cpu().numpy().view(np.uint32), g_ref.view(np.uint32))
 
 
-def test_open_loop_server_results_match_alone():
-    """Poisson arrivals into the batching server: every served result equals
-    the alone result of the same input."""
+@pytest.mark.parametrize("rounds_per_step", [2, 0], ids=["fixed2", "preemptive"])
+def test_open_loop_server_results_match_alone(rounds_per_step):
+    """Poisson arrivals into the batching server (fixed two-round steps, and
+    preemptible steps that end when a field finishes or a request waits):
+    every served result equals the alone result of the same input."""
     cases = _cases()
     alone = _alone(cases)
     rng = np.random.default_rng(7)
@@ -116,7 +118,7 @@ def test_open_loop_server_results_match_alone():
             bad.append(r.rid)
 
     done = serve.run_open_loop("batched", reqs, DEV, hbm_budget=1 << 30, max_fields=4,
-                               rounds_per_step=2, check=check)
+                               rounds_per_step=rounds_per_step, check=check)
     assert len(done) == len(reqs) and not bad
     summary = serve.latency_summary(done)
     assert summary["requests"] == len(reqs) and summary["p50_ms"] > 0
@@ -165,6 +167,45 @@ def test_cancelled_field_leaves_the_others_unchanged():
                 del live[h]
     ses.close()
     assert victim not in finished and len(finished) == len(cases) - 1
+    for i, (g_b, st_b) in finished.items():
+        g_a, st_a = alone[i]
+        assert torch.equal(g_a, g_b), i
+        assert [st_a[k] for k in KEYS] == [st_b[k] for k in KEYS], (i, st_a, st_b)
+
+
+def test_preemptible_steps_match_alone():
+    """Steps that end when a field finishes (stop_on_done) and steps ended by
+    a stop request after their first round: each field ends bit-identical to
+    its alone result, and the fields a step reports finished are exactly the
+    ones that are done."""
+    cases = _cases()
+    alone = _alone(cases)
+    ses = pmsz.Session(torch.float32, 8, torch.device(DEV))
+    live, bufs = {}, []
+    for i, (f, fh, xi) in enumerate(cases):
+        g = fh.clone()
+        n = pmsz.field_workspace_size(pmsz.grid_of(f))
+        buf = torch.empty(n + 256, dtype=torch.uint8, device=DEV)
+        off = (-buf.data_ptr()) % 256
+        bufs.append(buf)
+        live[ses.add(f, g, xi, buf[off:off + n])] = (i, g)
+    finished, steps = {}, 0
+    while live and steps < 10000:
+        ses.step(0, stop_on_done=True)
+        if steps % 2:
+            ses.request_stop()  # ends the step after at most two rounds
+        ses.sync()
+        steps += 1
+        fin = dict(ses.finished())
+        for h, (i, g) in list(live.items()):
+            st, done = ses.result(h)
+            assert done == (h in fin)
+            if done:
+                finished[i] = (g, st)
+                ses.remove(h)
+                del live[h]
+    ses.close()
+    assert not live and steps > 1
     for i, (g_b, st_b) in finished.items():
         g_a, st_a = alone[i]
         assert torch.equal(g_a, g_b), i

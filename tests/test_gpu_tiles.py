@@ -51,7 +51,12 @@ def test_batch_results_do_not_depend_on_tile_height():
             assert same_bits(host(g), g_ref)
 
 
-def test_tuner_installs_a_candidate_and_keeps_inputs():
+def test_tuner_installs_a_candidate_and_keeps_inputs(tmp_path, monkeypatch):
+    """The tuner installs the fastest candidate, leaves fhat alone and records
+    every target in the tune cache named by PMSZ_TUNE_CACHE."""
+    import json
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("PMSZ_TUNE_CACHE", str(cache))
     cases = [synth.make_2d_case(n, n, 1e-3, 10 + n) for n in (256, 512, 1024)]
     fields = [(dev(f.numpy()), dev(fh.numpy()), xi) for f, fh, xi in cases]
     keep = [fh.clone() for _, fh, _ in fields]
@@ -59,5 +64,6 @@ def test_tuner_installs_a_candidate_and_keeps_inputs():
     best, ms = pmsz.tune_tiles(fields, candidates=cands, reps=1)
     assert best in cands and set(ms) == set(cands) and all(v > 0 for v in ms.values())
     assert pmsz.get_tiles_target(2, torch.float32) == best
+    assert json.loads(cache.read_text())["2d_f32"] == best
     for (_, fh, _), k in zip(fields, keep):
         assert torch.equal(fh, k)

@@ -107,3 +107,27 @@ def test_tiles_target_host_only():
     assert lib.pmsz_set_tiles_target(4, pmsz.F32, 64) == 1
     assert lib.pmsz_set_tiles_target(3, 9, 64) == 1
     assert lib.pmsz_set_tiles_target(3, pmsz.F32, -1) == 1
+
+
+def test_tune_cache_is_read_before_the_first_target(tmp_path):
+    """PMSZ_TUNE_CACHE names a JSON file of tuned tiles-per-field targets: its
+    entries are the process's targets until set otherwise, absent keys keep
+    the default, and a malformed file is ignored (host-only calls)."""
+    import json
+    import subprocess
+    import sys
+    code = ("import paper_2601_01787_amd as p, torch; "
+            "print(p.get_tiles_target(3, torch.float32), p.get_tiles_target(2, torch.float64), "
+            "p.get_tiles_target(2, torch.float32), p.get_tiles_target(3, torch.float64))")
+
+    def targets(text):
+        cache = tmp_path / "tune.json"
+        cache.write_text(text)
+        env = dict(os.environ, PMSZ_TUNE_CACHE=str(cache))
+        out = subprocess.run([sys.executable, "-c", code], env=env, cwd=ROOT, check=True,
+                             capture_output=True, text=True).stdout
+        return [int(v) for v in out.split()]
+
+    assert targets(json.dumps({"3d_f32": 96, "2d_f64": 7})) == [96, 7, 2048, 2048]
+    assert targets('{"2d_f32" :  40 ,\n "3d_f64": 0}') == [2048, 2048, 40, 2048]
+    assert targets("not json at all") == [2048, 2048, 2048, 2048]
