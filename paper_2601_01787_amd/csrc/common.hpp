@@ -128,6 +128,29 @@ __device__ __forceinline__ gptr<T> as_global(T* p) {
   return (gptr<T>)p;
 }
 
+// A pointer or integer that is the same in every active lane, moved into
+// scalar registers.  Values read from a descriptor table through a vector
+// load stay in vector registers, and every address formed from them then
+// costs 64-bit vector arithmetic per load; from scalar registers the loads
+// take a scalar base and a 32-bit lane offset.
+__device__ __forceinline__ int32_t uniform(int32_t v) {
+  return __builtin_amdgcn_readfirstlane(v);
+}
+// Makes a loop-invariant 32-bit lane offset opaque to loop-invariant code
+// motion, in place (an empty asm statement that claims to rewrite the
+// register; no instruction is emitted).  Otherwise the compiler widens the
+// offset to 64 bits outside the loop, and every load inside it then pays a
+// 64-bit vector add instead of taking the scalar-base + 32-bit-offset form.
+__device__ __forceinline__ void opaque_off(uint32_t& o) { asm volatile("" : "+v"(o)); }
+
+template <class T>
+__device__ __forceinline__ T* uniform_ptr(T* p) {
+  const unsigned long long v = (unsigned long long)p;
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)v);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(v >> 32));
+  return (T*)(((unsigned long long)hi << 32) | lo);
+}
+
 // ---------------------------------------------------------------------------
 // Block barrier that orders LDS only.  A plain __syncthreads() also waits for
 // every outstanding global load of the wave (gfx9 counts loads and stores in

@@ -88,6 +88,18 @@ struct TileGeo {
   int32_t cx0, cx1, cy0, cy1, cz0, cz1;
 };
 
+// The geometry of the tile being marched, in scalar registers (see uniform).
+__device__ __forceinline__ TileGeo uniform_geo(const TileGeo& g) {
+  TileGeo u;
+  u.nx = uniform(g.nx), u.ny = uniform(g.ny), u.nz = uniform(g.nz);
+  u.sxy = uniform(g.sxy), u.n = uniform(g.n), u.ndim = uniform(g.ndim);
+  u.chunk = uniform(g.chunk);
+  u.tiles_x = uniform(g.tiles_x), u.tiles_y = uniform(g.tiles_y), u.tiles_z = uniform(g.tiles_z);
+  u.cx0 = uniform(g.cx0), u.cx1 = uniform(g.cx1), u.cy0 = uniform(g.cy0);
+  u.cy1 = uniform(g.cy1), u.cz0 = uniform(g.cz0), u.cz1 = uniform(g.cz1);
+  return u;
+}
+
 __host__ __device__ inline int64_t tile_count(const TileGeo& G) {
   return (int64_t)G.tiles_x * G.tiles_y * G.tiles_z;
 }
@@ -137,17 +149,20 @@ __device__ __forceinline__ unsigned unpack3(unsigned long long v, int k) {
 }
 using TileCounts = unsigned long long;  // packed, valid in thread 0
 
-// Flag words of one tile in LDS: the targets of a tile's vertices lie in its
-// one-vertex halo, i.e. in (chunk + 2) x (TY + 2) rows of 66 vertices (3D) or
-// (chunk + 2) rows of 258 vertices (2D); a row of the flag bitmap then spans at
-// most 4 (3D) or 10 (2D) 32-bit words, counted from the word holding the
-// row's first halo vertex.
+// Flag words of one tile in LDS, in tile-local rows: the targets of a tile's
+// vertices lie in its one-vertex halo box, (chunk + 2) x (TY + 2) rows of
+// TX + 2 vertices (3D) or chunk + 2 rows of RX + 2 vertices (2D).  Halo
+// position lx of row r is bit r * kRowBits + lx, so a target's bit is the
+// flagging vertex's own bit plus a constant per direction code (a 16-entry
+// table); the flush shifts each row onto the global bitmap's word
+// boundaries.
 constexpr int kMaxChunk = 32;
 // Planes in flight per tile march: four binary32 sets fit the register
 // budget of four waves per SIMD; binary64 values take twice the registers.
 template <class T, int KIND>
 constexpr int sets_for() { return sizeof(T) == 4 ? 4 : 2; }
-constexpr int kFlagW3 = 4, kFlagW2 = 10;
+constexpr int kRowBits3 = 128, kRowBits2 = 320;  // >= TX + 2 and RX + 2
+constexpr int kFlagW3 = kRowBits3 / 32, kFlagW2 = kRowBits2 / 32;
 constexpr int kFlagWords = (kMaxChunk + 2) * (TY + 2) * kFlagW3 > (kMaxChunk + 2) * kFlagW2
                                ? (kMaxChunk + 2) * (TY + 2) * kFlagW3
                                : (kMaxChunk + 2) * kFlagW2;
@@ -159,7 +174,22 @@ struct TileLds {
     T r2[2][RW];
   } ring;
   uint32_t flags[kFlagWords];
+  int32_t fdelta[16];  // flag-bit offset of the neighbour with each direction code
 };
+
+// Fill the direction-code table of the flag layout (threads 0..15; read after
+// the march's first barrier).  Code bits +x, +y, +z and "negative".
+__device__ __forceinline__ void set_flag_deltas(int32_t* t, int32_t row_bits, int32_t plane_bits) {
+  const int k = threadIdx.x;
+  if (k < 16) {
+    const int32_t d = (k & 1) + ((k >> 1) & 1) * row_bits + ((k >> 2) & 1) * plane_bits;
+    t[k] = (k & 8) ? -d : d;
+  }
+}
+
+__device__ __forceinline__ void flag_bit(uint32_t* flags, int32_t bi) {
+  atomicOr(flags + (bi >> 5), 1u << (bi & 31));
+}
 
 // Targeted edit: a flag also proposes a value for its target, the highest
 // value at which the target no longer beats its rival in the (value, index)
@@ -198,35 +228,18 @@ __device__ __forceinline__ void propose(void* prop, int32_t t, int32_t rival, T 
 // Targets go to the tile's LDS flag words (row r of the halo box, word
 // offset from the row's first word); the tile flushes them to the global
 // bitmap once at its end, so the march never waits on global atomics.
-struct FlagBox {
-  int32_t x0, y0, z0;   // tile origin
-  int32_t nrow_y;       // rows per plane in the LDS flag layout (TY + 2 in 3D, 1 in 2D)
-  int32_t words;        // words per row (kFlagW3 / kFlagW2)
-  int32_t span;         // halo vertices per row minus one (TX + 1 or RX + 1)
-};
-
-__device__ __forceinline__ void flag_lds(uint32_t* flags, const FlagBox& fb, const TileGeo& G,
-                                         int32_t tx, int32_t ty, int32_t tz) {
-  const int32_t row = (tz - (fb.z0 - 1)) * fb.nrow_y + (fb.nrow_y > 1 ? ty - (fb.y0 - 1) : 0);
-  const int32_t rbase = (G.ndim == 3 ? G.nx * ty + G.sxy * tz : G.nx * ty);
-  const int32_t first = (rbase + fb.x0 - 1) >> 5;  // arithmetic shift: floor
-  const int32_t gb = rbase + tx;
-  atomicOr(flags + row * fb.words + ((gb >> 5) - first), 1u << (gb & 31));
-}
-
+// bi: the vertex's own flag bit; v: its index in the field (proposals only).
 // With prop set (targeted edit) each flag also proposes a value: the
 // ascending rival is n_max under f (value read from g), the descending rival
 // is the current n_min, whose value `lo` the stencil already holds.
 template <class T>
-__device__ __forceinline__ unsigned flag_targets3(int32_t X, int32_t Y, int32_t Z, int ca, int cd,
-                                                  int fa, int fd, const FlagBox& fb,
-                                                  const TileGeo& G, uint32_t* flags, void* prop,
-                                                  gptr<const T> g, T lo) {
+__device__ __forceinline__ unsigned flag_targets(int32_t bi, int32_t v, int ca, int cd, int fa,
+                                                 int fd, const TileGeo& G, uint32_t* flags,
+                                                 const int32_t* fdelta, void* prop,
+                                                 gptr<const T> g, T lo) {
   unsigned cnt = 0;
-  const int32_t v = X + G.nx * Y + G.sxy * Z;
   if (ca != fa) {
-    const int m = ca & 7, sg = (ca & 8) ? -1 : 1;
-    flag_lds(flags, fb, G, X + sg * (m & 1), Y + sg * ((m >> 1) & 1), Z + sg * ((m >> 2) & 1));
+    flag_bit(flags, bi + fdelta[ca]);
     if (prop) {
       const int32_t c = v + code_delta32(fa, G.nx, G.sxy);
       propose<T>(prop, v + code_delta32(ca, G.nx, G.sxy), c, g[c]);
@@ -234,8 +247,7 @@ __device__ __forceinline__ unsigned flag_targets3(int32_t X, int32_t Y, int32_t 
     ++cnt;
   }
   if (cd != fd) {
-    const int m = fd & 7, sg = (fd & 8) ? -1 : 1;
-    flag_lds(flags, fb, G, X + sg * (m & 1), Y + sg * ((m >> 1) & 1), Z + sg * ((m >> 2) & 1));
+    flag_bit(flags, bi + fdelta[fd]);
     if (prop)
       propose<T>(prop, v + code_delta32(fd, G.nx, G.sxy), v + code_delta32(cd, G.nx, G.sxy), lo);
     ++cnt;
@@ -243,27 +255,35 @@ __device__ __forceinline__ unsigned flag_targets3(int32_t X, int32_t Y, int32_t 
   return cnt;
 }
 
-// Flush the tile's LDS flag words into the field's bitmap and clear them.
-// Must follow a barrier after the last flag_lds of the tile.
-__device__ __forceinline__ void flush_flags(uint32_t* flags, const FlagBox& fb, const TileGeo& G,
-                                            int32_t rows, gptr<uint32_t> bm) {
-  const int32_t nw = rows * fb.words;
-  for (int k = threadIdx.x; k < nw; k += 256) {
-    const uint32_t v = flags[k];
-    if (!v) continue;
-    flags[k] = 0u;
-    const int32_t row = k / fb.words, wo = k - row * fb.words;
-    int32_t ty, tz;
-    if (fb.nrow_y > 1) {
-      tz = fb.z0 - 1 + row / fb.nrow_y;
-      ty = fb.y0 - 1 + row % fb.nrow_y;
-    } else {
-      tz = 0;
-      ty = fb.y0 - 1 + row;
+// Flush the tile's LDS flag rows into the field's bitmap and clear them; one
+// row per thread.  Row r covers global bits row_start(r) .. + W * 32 - 1
+// (row_start may be negative or run past the field for halo rows outside
+// it, which hold no flags: targets are vertices of the field).  Must follow
+// a barrier after the last flag of the tile.
+template <int W, class RowStart>
+__device__ __forceinline__ void flush_rows(uint32_t* flags, int32_t rows, RowStart row_start,
+                                           gptr<uint32_t> bm) {
+  for (int r = threadIdx.x; r < rows; r += 256) {
+    uint32_t L[W];
+    uint32_t any = 0;
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      L[j] = flags[r * W + j];
+      any |= L[j];
     }
-    const int32_t rbase = (G.ndim == 3 ? G.nx * ty + G.sxy * tz : G.nx * ty);
-    const int32_t first = (rbase + fb.x0 - 1) >> 5;
-    __hip_atomic_fetch_or(bm + first + wo, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!any) continue;
+#pragma unroll
+    for (int j = 0; j < W; ++j) flags[r * W + j] = 0u;
+    const int32_t gb0 = row_start(r);
+    const int32_t w0 = gb0 >> 5;  // arithmetic shift: floor
+    const uint32_t sh = (uint32_t)gb0 & 31u;
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      uint32_t w = L[j] << sh;
+      if (j > 0 && sh) w |= L[j - 1] >> (32u - sh);
+      if (w)
+        __hip_atomic_fetch_or(bm + (w0 + j), w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
   }
 }
 
@@ -328,11 +348,15 @@ __device__ __forceinline__ T fast_margin(T xi) {
 template <class T, int KIND, int SETS = sets_for<T, KIND>()>
 __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_in,
                             const T* f_in, uint8_t* dirs_in, uint32_t* bm_in, T xi,
-                            const TileGeo G, int64_t tile, void* prop = nullptr) {
-  const gptr<const T> h = as_global(h_in);
-  const gptr<const T> f = as_global(f_in);
-  const gptr<uint8_t> dirs = as_global(dirs_in);
-  const gptr<uint32_t> bm = as_global(bm_in);
+                            const TileGeo G_in, int64_t tile_in, void* prop_in = nullptr) {
+  // every argument is uniform over the block (one tile of one field)
+  const TileGeo G = uniform_geo(G_in);
+  const int64_t tile = (int64_t)uniform((int32_t)tile_in);
+  void* const prop = uniform_ptr(prop_in);
+  const gptr<const T> h = as_global(uniform_ptr(h_in));
+  const gptr<const T> f = as_global(uniform_ptr(f_in));
+  const gptr<uint8_t> dirs = as_global(uniform_ptr(dirs_in));
+  const gptr<uint32_t> bm = as_global(uniform_ptr(bm_in));
   const T xi_in = fast_margin<T>(xi);  // validation's fast test (bound_class)
   constexpr int PER = (PLANE + 255) / 256;
   constexpr bool kReadDirs = (KIND == KIND_NEXT || KIND == KIND_FIRST_GIVEN);
@@ -374,20 +398,29 @@ __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_
   const bool mine = X < G.nx && Y < G.ny;
   const bool core_col = mine && X >= G.cx0 && X < G.cx1 && Y >= G.cy0 && Y < G.cy1;
   // this column from the corner (the tile's first vertex for idle lanes)
-  const uint32_t rel = mine ? (uint32_t)(ty + 1) * (uint32_t)G.nx + (uint32_t)(tx + 1) : safe;
+  uint32_t rel = mine ? (uint32_t)(ty + 1) * (uint32_t)G.nx + (uint32_t)(tx + 1) : safe;
+  uint32_t relb = rel * (uint32_t)sizeof(T);
   auto fetch = [&](int32_t z, Set& S) {
     const bool zin = z >= 0 && z < G.nz;
     const int64_t zb = zin ? (int64_t)G.sxy * z : 0;
     S.zmask = zin ? 0u : nan_mask<T>();
     const gptr<const char> pb = (gptr<const char>)(h + (zb + corner));
 #pragma unroll
-    for (int k = 0; k < PER; ++k) S.h[k] = *(gptr<const T>)(pb + offb[k]);
+    for (int k = 0; k < PER; ++k) {
+      opaque_off(offb[k]);
+      S.h[k] = *(gptr<const T>)(pb + offb[k]);
+    }
   };
   auto fetch_own = [&](int32_t v, Set& S) {
     const int64_t pl = (int64_t)G.sxy * (v >= 0 && v < G.nz ? v : 0) + corner;
-    if (kReadDirs) S.d = (dirs + pl)[rel];
-    if (kGivenF)
-      S.fv = *(gptr<const T>)((gptr<const char>)(f + pl) + rel * (uint32_t)sizeof(T));
+    if (kReadDirs) {
+      opaque_off(rel);
+      S.d = (dirs + pl)[rel];
+    }
+    if (kGivenF) {
+      opaque_off(relb);
+      S.fv = *(gptr<const T>)((gptr<const char>)(f + pl) + relb);
+    }
   };
   auto commit = [&](int buf, const Set& S) {
 #pragma unroll
@@ -409,7 +442,10 @@ __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_
     const Ext<T> q1 = merge_dn(ext_of(P[c - 1], 9), ext_of(P[c], 0));
     dn = merge_dn(q0, q1);
   };
-  FlagBox fbx{x0, y0, z0, TY + 2, kFlagW3, TX + 1};
+  // flag bit of this column's vertex in the halo box's first plane
+  constexpr int32_t kPlaneBits3 = kRowBits3 * (TY + 2);
+  const int32_t bit0 = (ty + 1) * kRowBits3 + (tx + 1) - (z0 - 1) * kPlaneBits3;
+  if (KIND != KIND_DIRS) set_flag_deltas(sm.fdelta, kRowBits3, kPlaneBits3);
   unsigned mism = 0, nf = 0, nb = 0;
   // carried from plane p-1: its squares, the lower box of vertex p-1 and the
   // centre value (for validation)
@@ -431,7 +467,8 @@ __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_
         nb += bc == 2;
       }
       if (core_col && v >= G.cz0 && v < G.cz1)
-        mism += flag_targets3<T>(X, Y, v, ca, cd, fa, fd, fbx, G, sm.flags, prop, h, e.lo);
+        mism += flag_targets<T>(bit0 + v * kPlaneBits3, X + G.nx * Y + G.sxy * v, ca, cd, fa, fd,
+                                G, sm.flags, sm.fdelta, prop, h, e.lo);
     }
   };
   // Two planes per barrier: step p stages planes p and p+1 in one pair of LDS
@@ -483,7 +520,10 @@ __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_
   }
   lds_barrier();  // the next tile of this block reuses the LDS buffers
   if (KIND == KIND_DIRS) return 0;
-  flush_flags(sm.flags, fbx, G, (z1 - z0 + 2) * (TY + 2), bm);
+  flush_rows<kFlagW3>(sm.flags, (z1 - z0 + 2) * (TY + 2), [&](int32_t r) {
+    const int32_t lz = r / (TY + 2), ly = r - lz * (TY + 2);
+    return G.nx * (y0 - 1 + ly) + G.sxy * (z0 - 1 + lz) + (x0 - 1);
+  }, bm);
   return block_sum(pack3(mism, nf, nb), red);
 }
 
@@ -493,11 +533,15 @@ __device__ TileCounts tile3(TileLds<T>& sm, unsigned long long* red, const T* h_
 template <class T, int KIND, int SETS = sets_for<T, KIND>()>
 __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_in,
                             const T* f_in, uint8_t* dirs_in, uint32_t* bm_in, T xi,
-                            const TileGeo G, int64_t tile, void* prop = nullptr) {
-  const gptr<const T> h = as_global(h_in);
-  const gptr<const T> f = as_global(f_in);
-  const gptr<uint8_t> dirs = as_global(dirs_in);
-  const gptr<uint32_t> bm = as_global(bm_in);
+                            const TileGeo G_in, int64_t tile_in, void* prop_in = nullptr) {
+  // every argument is uniform over the block (one tile of one field)
+  const TileGeo G = uniform_geo(G_in);
+  const int64_t tile = (int64_t)uniform((int32_t)tile_in);
+  void* const prop = uniform_ptr(prop_in);
+  const gptr<const T> h = as_global(uniform_ptr(h_in));
+  const gptr<const T> f = as_global(uniform_ptr(f_in));
+  const gptr<uint8_t> dirs = as_global(uniform_ptr(dirs_in));
+  const gptr<uint32_t> bm = as_global(uniform_ptr(bm_in));
   const T xi_in = fast_margin<T>(xi);  // validation's fast test (bound_class)
   constexpr int PER = (RW + 255) / 256;
   constexpr bool kReadDirs = (KIND == KIND_NEXT || KIND == KIND_FIRST_GIVEN);
@@ -529,7 +573,8 @@ __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_
   const int32_t X = x0 + tid;
   const bool mine = X < G.nx;
   const bool core_col = mine && X >= G.cx0 && X < G.cx1;
-  const uint32_t rel = mine ? (uint32_t)tid + 1u : 1u;  // from the corner x0-1
+  uint32_t rel = mine ? (uint32_t)tid + 1u : 1u;  // from the corner x0-1
+  uint32_t relb = rel * (uint32_t)sizeof(T);
   const int64_t corner = (int64_t)x0 - 1;
   auto fetch = [&](int32_t y, Set& S) {
     const bool yin = y >= 0 && y < G.ny;
@@ -537,13 +582,21 @@ __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_
     S.zmask = yin ? 0u : nan_mask<T>();
     const gptr<const char> pb = (gptr<const char>)(h + (yb + corner));
 #pragma unroll
-    for (int k = 0; k < PER; ++k) S.h[k] = *(gptr<const T>)(pb + offb[k]);
+    for (int k = 0; k < PER; ++k) {
+      opaque_off(offb[k]);
+      S.h[k] = *(gptr<const T>)(pb + offb[k]);
+    }
   };
   auto fetch_own = [&](int32_t v, Set& S) {
     const int64_t pl = (int64_t)G.nx * (v >= 0 && v < G.ny ? v : 0) + corner;
-    if (kReadDirs) S.d = (dirs + pl)[rel];
-    if (kGivenF)
-      S.fv = *(gptr<const T>)((gptr<const char>)(f + pl) + rel * (uint32_t)sizeof(T));
+    if (kReadDirs) {
+      opaque_off(rel);
+      S.d = (dirs + pl)[rel];
+    }
+    if (kGivenF) {
+      opaque_off(relb);
+      S.fv = *(gptr<const T>)((gptr<const char>)(f + pl) + relb);
+    }
   };
   auto commit = [&](int buf, const Set& S) {
 #pragma unroll
@@ -560,16 +613,12 @@ __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_
     up = merge_up(ext_of(R[c], 0), ext_of(R[c + 1], 1));
     dn = merge_dn(ext_of(R[c - 1], 9), ext_of(R[c], 0));
   };
-  // 2D flag rows are indexed by y: the box's "z" origin is the first row
-  FlagBox fbx{x0, y0, y0, 1, kFlagW2, RX + 1};
+  // flag rows are the strip's rows y0-1 .. y1; this column's bit in the first
+  const int32_t bit0 = tid + 1 - (y0 - 1) * kRowBits2;
+  if (KIND != KIND_DIRS) set_flag_deltas(sm.fdelta, kRowBits2, 0);
   unsigned mism = 0, nf = 0, nb = 0;
   Ext<T> gu{}, gl{}, gbox{};
   T gc = T(0);
-  auto flag2 = [&](int32_t y, int code) {
-    const int m = code & 7, sg = (code & 8) ? -1 : 1;
-    const int32_t yy = y + sg * ((m >> 1) & 1);
-    flag_lds(sm.flags, fbx, G, X + sg * (m & 1), yy, yy);
-  };
   auto step = [&](int32_t r, Set& S, bool out) {
     const int buf = (r - y0 + 1) & 1;
     commit(buf, S);
@@ -596,8 +645,9 @@ __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_
         // 2D codes only use the x and y bits; rows are indexed by y
         const int32_t vi = X + G.nx * v;
         const bool core = core_col && v >= G.cy0 && v < G.cy1;
+        const int32_t bi = bit0 + v * kRowBits2;
         if (core && ca != fa) {
-          flag2(v, ca);
+          flag_bit(sm.flags, bi + sm.fdelta[ca]);
           if (prop) {
             const int32_t c = vi + code_delta32(fa, G.nx, G.sxy);
             propose<T>(prop, vi + code_delta32(ca, G.nx, G.sxy), c, h[c]);
@@ -605,7 +655,7 @@ __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_
           ++mism;
         }
         if (core && cd != fd) {
-          flag2(v, fd);
+          flag_bit(sm.flags, bi + sm.fdelta[fd]);
           if (prop)
             propose<T>(prop, vi + code_delta32(fd, G.nx, G.sxy),
                        vi + code_delta32(cd, G.nx, G.sxy), e.lo);
@@ -636,7 +686,8 @@ __device__ TileCounts tile2(TileLds<T>& sm, unsigned long long* red, const T* h_
   }
   lds_barrier();  // the next tile of this block reuses the LDS buffers
   if (KIND == KIND_DIRS) return 0;
-  flush_flags(sm.flags, fbx, G, y1 - y0 + 2, bm);
+  flush_rows<kFlagW2>(sm.flags, y1 - y0 + 2,
+                      [&](int32_t r) { return G.nx * (y0 - 1 + r) + (x0 - 1); }, bm);
   return block_sum(pack3(mism, nf, nb), red);
 }
 
