@@ -368,6 +368,12 @@ int pmsz_session_step_ex(pmsz_session* s, int64_t max_rounds, int32_t flags);
 /* Asks the step in flight to end after its current round (a new request is
  * waiting); thread-safe; spent by the next step's launch. */
 int pmsz_session_request_stop(pmsz_session* s);
+/* Asks the step in flight to end after the first round that begins with one
+ * of its fields done (at most two rounds after that field finished), so that
+ * finished fields can be collected without ending every step at the first
+ * one; overrides nothing (a pending pmsz_session_request_stop stands).
+ * Thread-safe; spent by the next step's launch. */
+int pmsz_session_request_stop_when_done(pmsz_session* s);
 /* *running = 1 while the step in flight has not ended (non-blocking). */
 int pmsz_session_query(pmsz_session* s, int32_t* running);
 /* After a sync: the handles (up to cap) and stats of the fields that

@@ -37,7 +37,8 @@ EXPORTS = ("pmsz_workspace_size", "pmsz_directions", "pmsz_correct",
            "pmsz_session_workspace_size", "pmsz_field_workspace_size", "pmsz_session_create",
            "pmsz_session_add", "pmsz_session_step", "pmsz_session_sync", "pmsz_session_result",
            "pmsz_session_remove", "pmsz_session_destroy", "pmsz_session_step_ex",
-           "pmsz_session_request_stop", "pmsz_session_query", "pmsz_session_finished",
+           "pmsz_session_request_stop", "pmsz_session_request_stop_when_done",
+           "pmsz_session_query", "pmsz_session_finished",
            "pmsz_edits_workspace_size",
            "pmsz_edits_max_bytes", "pmsz_encode_edits", "pmsz_decode_edits",
            "pmsz_blocks_workspace_size", "pmsz_correct_blocks", "pmsz_set_tiles_target",
@@ -177,6 +178,7 @@ def load():
     L.pmsz_session_step.argtypes = [vp, i64]
     L.pmsz_session_step_ex.argtypes = [vp, i64, i32]
     L.pmsz_session_request_stop.argtypes = [vp]
+    L.pmsz_session_request_stop_when_done.argtypes = [vp]
     L.pmsz_session_query.argtypes = [vp, ctypes.POINTER(i32)]
     L.pmsz_session_finished.argtypes = [vp, i32, vp, vp, ctypes.POINTER(i32)]
     L.pmsz_session_sync.argtypes = [vp, ctypes.POINTER(ctypes.c_int32)]
@@ -481,9 +483,14 @@ class Session:
         _raise_if(load().pmsz_session_step_ex(self._h, int(max_rounds),
                                               STEP_STOP_ON_DONE if stop_on_done else 0))
 
-    def request_stop(self):
-        """Ask the step in flight to end after its current round."""
-        _raise_if(load().pmsz_session_request_stop(self._h))
+    def request_stop(self, when_done=False):
+        """Ask the step in flight to end after its current round, or (with
+        when_done) after the first round that begins with one of its fields
+        done."""
+        if when_done:
+            _raise_if(load().pmsz_session_request_stop_when_done(self._h))
+        else:
+            _raise_if(load().pmsz_session_request_stop(self._h))
 
     def running(self):
         """True while the step in flight has not ended (non-blocking)."""

@@ -1473,7 +1473,15 @@ int pmsz_session_step(pmsz_session* S, int64_t max_rounds) {
 
 int pmsz_session_request_stop(pmsz_session* S) {
   if (!S) return fail(PMSZ_ERR_INVALID_ARG, "NULL session");
-  __atomic_store_n(S->stop_word, 1u, __ATOMIC_RELEASE);
+  __atomic_store_n(S->stop_word, kStopNow, __ATOMIC_RELEASE);
+  return PMSZ_OK;
+}
+
+int pmsz_session_request_stop_when_done(pmsz_session* S) {
+  if (!S) return fail(PMSZ_ERR_INVALID_ARG, "NULL session");
+  unsigned expect = 0u;  // a stop already requested stands
+  __atomic_compare_exchange_n(S->stop_word, &expect, kStopWhenDone, false, __ATOMIC_RELEASE,
+                              __ATOMIC_RELAXED);
   return PMSZ_OK;
 }
 
@@ -1551,8 +1559,34 @@ int pmsz_session_step_ex(pmsz_session* S, int64_t max_rounds, int32_t flags) {
   // a stop requested before this launch is spent (the host's store is
   // ordered before the launch that reads the word)
   __atomic_store_n(S->stop_word, 0u, __ATOMIC_RELEASE);
+  // Fields starting in this step with kSplitVoxels vertices or more in all:
+  // the tile detection of the step's first two rounds runs as plain kernels
+  // between engine launches, as in run_batch.  The first round's sweeps
+  // cover both the starting fields and the running fields in tile rounds
+  // (each sweep takes only the fields of its kind); a field that finishes
+  // in the first launch ends the step after the next round.
+  int64_t fresh_voxels = 0;
+  int dims = 0;
+  for (int32_t i = 0; i < n; ++i) {
+    if (!S->fields[S->stepped[i]].started) fresh_voxels += fd[i].geo.n;
+    dims |= fd[i].geo.ndim == 3 ? 4 : 2;
+  }
   int grid = 0;
-  HIP_TRY(engine_launch(S->dtype, a, S->stream, &grid));
+  if (fresh_voxels >= kSplitVoxels) {
+    a.tiles_swept = 1;
+    a.max_rounds = 1;
+    HIP_TRY(engine_sweep(S->dtype, KIND_FIRST_GIVEN, false, dims, a, S->stream));
+    HIP_TRY(engine_sweep(S->dtype, KIND_NEXT, false, dims, a, S->stream));
+    HIP_TRY(engine_launch(S->dtype, a, S->stream, &grid));
+    a.has_fresh = 0;
+    a.max_rounds = max_rounds < 0 ? -1 : max_rounds - 1;
+    if (a.max_rounds != 0) {
+      HIP_TRY(engine_sweep(S->dtype, KIND_NEXT, false, dims, a, S->stream));
+      HIP_TRY(engine_launch(S->dtype, a, S->stream, &grid));
+    }
+  } else {
+    HIP_TRY(engine_launch(S->dtype, a, S->stream, &grid));
+  }
   HIP_TRY(hipMemcpyAsync(down, S->ws, kCtlHostBytes, hipMemcpyDeviceToHost, S->stream));
   HIP_TRY(hipMemcpyAsync((char*)down + kCtlHostBytes, a.out, sizeof(FieldIter) * (size_t)n,
                          hipMemcpyDeviceToHost, S->stream));

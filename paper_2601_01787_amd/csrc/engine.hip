@@ -908,15 +908,28 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
       for (int fi = tid; fi < a.nf; fi += 256) {
         const FieldDesc& d = a.fd[fi];
         const gptr<FieldState> st = as_global(d.st);
+        bool done;
         if (E > E0) {
           const FieldIter s = state_at(d, E, E0);
           store_iter(&st->s[p], s);
           stop |= a.stop_on_done && s.done && !st->s[p ^ 1].done;
+          done = s.done;
+        } else {
+          done = load_iter(&st->s[p]).done;
+          // a later launch of a step whose tile detection ran as sweeps: a
+          // field done at its start finished in the step's earlier launch
+          stop |= a.stop_on_done && a.tiles_swept && done;
         }
+        // the host asked for the step to end once a field is done (every
+        // field of a step was running when it began)
+        if (done && a.stop_host &&
+            __hip_atomic_load(a.stop_host, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) ==
+                kStopWhenDone)
+          stop = true;
         clear_ctr(&st->c[qn]);
       }
       if (tid == 0 && a.stop_host &&
-          __hip_atomic_load(a.stop_host, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) != 0u)
+          __hip_atomic_load(a.stop_host, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) == kStopNow)
         stop = true;
       if (stop) __hip_atomic_store(&ctl->stop.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       if (tid < kCtrSlots) {

@@ -117,6 +117,10 @@ struct EngineCtl {
 };
 constexpr size_t kCtlHostBytes = offsetof(EngineCtl, xbar);
 
+// Values of the host's stop word: end the launch after the current round;
+// end it after a round that begins with a field of the launch done.
+constexpr unsigned kStopNow = 1u, kStopWhenDone = 2u;
+
 struct EngineArgs {
   const FieldDesc* fd;
   FieldIter* out;        // state of every field at the end of the launch
@@ -131,7 +135,7 @@ struct EngineArgs {
                          // already run as its own kernel (engine_sweep)
   int32_t stop_on_done;  // end the launch after the round in which a field is
                          // first seen finished
-  unsigned* stop_host;   // nullable, host memory: nonzero asks the launch to end
+  unsigned* stop_host;   // nullable, host memory: kStopNow / kStopWhenDone (below)
                          // after the round in progress
 };
 

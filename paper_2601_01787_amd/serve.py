@@ -13,6 +13,7 @@ iteration does not depend on what else is in the step).
 arrival order.
 """
 import collections
+import itertools
 import time
 
 import torch
@@ -51,11 +52,16 @@ class BatchingServer:
     """Admits requests by HBM footprint into a serving session and keeps the
     persistent correction kernel running over every admitted request.
 
-    Steps are preemptible: a step runs until every field is done, but ends
-    after the round in which a field finishes (its result is collected at
-    once) and after the current round when a waiting request can be admitted
-    (the server asks the engine to stop; the request joins the next step).
-    With `rounds_per_step` > 0 steps are instead fixed at that many rounds.
+    Steps are preemptible.  With no backlog (nothing waiting when the step
+    is launched) a step ends after the round in which a field finishes (its
+    result is collected at once) and after the current round when a new
+    request arrives that can be admitted (it joins the next step).  Under a
+    backlog, ending a step at every arrival and every finished field would
+    relaunch the kernel about twice per request; such steps instead run for
+    `bulk_step` seconds and then end after the current round when a waiting
+    request can be admitted, else after the first round that begins with a
+    field done, collecting every field finished by then.  With
+    `rounds_per_step` > 0 steps are instead fixed at that many rounds.
 
     Every field of a step advances in the same rounds, so a round lasts as
     long as the largest field's round; `work_budget` (vertices) caps the
@@ -67,7 +73,7 @@ class BatchingServer:
 
     def __init__(self, device, hbm_budget, max_fields=64, rounds_per_step=0,
                  dtype=torch.float32, max_iters=1 << 40, work_budget=DEFAULT_WORK_BUDGET,
-                 max_wait=0.02):
+                 max_wait=0.02, bulk_step=0.002):
         self.device = torch.device(device)
         self.budget = int(hbm_budget)
         self.work_budget = work_budget
@@ -82,6 +88,10 @@ class BatchingServer:
         self.steps = 0
         self.in_flight = False
         self.stop_sent = False
+        self.bulk_step = bulk_step
+        self.bulk = False
+        self.launched_at = 0.0
+        self.deliver_sent = False
 
     def can_admit(self, req):
         if len(self.active) >= self.max_fields or self.in_use + req.footprint > self.budget:
@@ -101,29 +111,37 @@ class BatchingServer:
         self.work += req.f.numel()
         self.active[req.handle] = req
 
-    def admit_from(self, pending, now):
-        """Admit waiting requests (a deque in arrival order) that fit."""
-        kept = collections.deque()
-        blocked = False
-        while pending:
+    def admit_from(self, pending, now, max_scan=64):
+        """Admit waiting requests (a deque in arrival order) that fit,
+        looking at no more than the `max_scan` oldest (a long queue is not
+        rescanned at every step)."""
+        kept = []
+        scanned = 0
+        while pending and scanned < max_scan and len(self.active) < self.max_fields:
             r = pending.popleft()
-            if not blocked and self.can_admit(r):
+            scanned += 1
+            if self.can_admit(r):
                 self.admit(r, now)
-            else:
-                kept.append(r)
-                # the oldest request that waited too long is not passed again
-                if now - r.arrival > self.max_wait:
-                    blocked = True
-        pending.extend(kept)
+                continue
+            kept.append(r)
+            # the oldest request that waited too long is not passed again
+            if now - r.arrival > self.max_wait:
+                break
+        pending.extendleft(reversed(kept))
 
-    def launch(self):
+    def launch(self, now=0.0, backlog=False):
+        """Launch a step over every admitted request (none in flight).  now:
+        the caller's clock; backlog: requests are waiting."""
         if self.active and not self.in_flight:
             if self.rounds > 0:
                 self.session.step(self.rounds)
             else:
-                self.session.step(0, stop_on_done=True)
+                self.session.step(0, stop_on_done=not backlog)
             self.in_flight = True
             self.stop_sent = False
+            self.deliver_sent = False
+            self.bulk = backlog and self.rounds <= 0
+            self.launched_at = now
             self.steps += 1
 
     def preempt(self):
@@ -131,6 +149,21 @@ class BatchingServer:
         if self.in_flight and not self.stop_sent and self.rounds <= 0:
             self.session.request_stop()
             self.stop_sent = True
+
+    def tick(self, now, admissible):
+        """Stop requests for the step in flight.  admissible: a waiting
+        request can be admitted."""
+        if not self.in_flight or self.stop_sent or self.rounds > 0:
+            return
+        if not self.bulk:
+            if admissible:
+                self.preempt()
+        elif now - self.launched_at >= self.bulk_step:
+            if admissible:
+                self.preempt()
+            elif not self.deliver_sent:
+                self.session.request_stop(when_done=True)
+                self.deliver_sent = True
 
     def poll(self, wait=False):
         """None while the step runs (unless wait); else the finished
@@ -195,8 +228,8 @@ def _replay(server_kind, srv, arrivals, pending, done, dev, check):
             pending.append(arrivals.popleft())
         if server_kind == "batched":
             if srv.in_flight:
-                if pending and any(srv.can_admit(r) for r in pending):
-                    srv.preempt()
+                srv.tick(now, bool(pending) and
+                         any(srv.can_admit(r) for r in itertools.islice(pending, 64)))
                 finished = srv.poll()
                 if finished is None:
                     continue  # the step runs on; keep watching arrivals
@@ -205,7 +238,7 @@ def _replay(server_kind, srv, arrivals, pending, done, dev, check):
                 srv.admit_from(pending, now)
                 if pending and not srv.active:
                     raise RuntimeError("request %d does not fit the HBM budget" % pending[0].rid)
-                srv.launch()
+                srv.launch(now, backlog=bool(pending))
             t = time.perf_counter() - t0
             for r in finished:
                 r.done_at = t

@@ -210,3 +210,105 @@ def test_preemptible_steps_match_alone():
         g_a, st_a = alone[i]
         assert torch.equal(g_a, g_b), i
         assert [st_a[k] for k in KEYS] == [st_b[k] for k in KEYS], (i, st_a, st_b)
+
+
+def _add(ses, case, bufs):
+    f, fh, xi = case
+    g = fh.clone()
+    n = pmsz.field_workspace_size(pmsz.grid_of(f))
+    buf = torch.empty(n + 256, dtype=torch.uint8, device=DEV)
+    off = (-buf.data_ptr()) % 256
+    bufs.append(buf)
+    return ses.add(f, g, xi, buf[off:off + n]), g
+
+
+def test_split_steps_match_alone():
+    """Steps whose starting fields hold 2^23 vertices or more run the tile
+    detection of their first two rounds as kernels of their own between
+    engine launches.  Fields that start in such steps, and fields already
+    running in them (tile and sparse rounds), end bit-identical to their
+    alone results, with fixed-round, stop-on-done and stopped steps."""
+    big = [synth.perlin_case(208, 4, 4, 1e-3, 11), synth.make_2d_case(3000, 3000, 1e-3, 12)]
+    cases = [(f.to(DEV), fh.to(DEV), xi) for f, fh, xi in big] + _cases()[:3]
+    alone = _alone(cases)
+    ses = pmsz.Session(torch.float32, 8, torch.device(DEV))
+    live, bufs, finished = {}, [], {}
+
+    def collect():
+        fin = dict(ses.finished())
+        for h, (i, g) in list(live.items()):
+            st, done = ses.result(h)
+            assert done == (h in fin), (i, done)
+            if done:
+                finished[i] = (g, st)
+                ses.remove(h)
+                del live[h]
+
+    def add(i):
+        h, g = _add(ses, cases[i], bufs)
+        live[h] = (i, g)
+
+    add(0)
+    ses.step(1)  # split, first launch only
+    ses.sync()
+    collect()
+    add(2)
+    add(3)
+    ses.step(3)  # nothing fresh at 2^23: one launch
+    ses.sync()
+    collect()
+    add(1)  # a fresh 9M-vertex field next to running ones: split
+    ses.step(0, stop_on_done=True)
+    ses.sync()
+    collect()
+    add(4)
+    steps = 0
+    while live and steps < 10000:
+        ses.step(0, stop_on_done=True)
+        if steps % 3 == 1:
+            ses.request_stop()
+        ses.sync()
+        collect()
+        steps += 1
+    ses.close()
+    assert len(finished) == len(cases)
+    for i, (g_a, st_a) in enumerate(alone):
+        g_b, st_b = finished[i]
+        assert torch.equal(g_a, g_b), i
+        assert [st_a[k] for k in KEYS] == [st_b[k] for k in KEYS], (i, st_a, st_b)
+
+
+def test_stop_when_done_steps_match_alone():
+    """Steps asked to end once a field is done (pmsz_session_request_stop_when_done)
+    end with at least one field finished, report exactly the fields that are
+    done, and every field ends bit-identical to its alone result."""
+    cases = _cases()
+    alone = _alone(cases)
+    ses = pmsz.Session(torch.float32, 8, torch.device(DEV))
+    live, bufs, finished = {}, [], {}
+    for i in range(len(cases)):
+        h, g = _add(ses, cases[i], bufs)
+        live[h] = (i, g)
+    steps = 0
+    while live and steps < 10000:
+        ses.step(0)
+        ses.request_stop(when_done=True)
+        if steps == 1:
+            ses.request_stop()  # a plain stop request overrides it
+        ses.sync()
+        fin = dict(ses.finished())
+        assert fin or steps == 1
+        for h, (i, g) in list(live.items()):
+            st, done = ses.result(h)
+            assert done == (h in fin), (i, done)
+            if done:
+                finished[i] = (g, st)
+                ses.remove(h)
+                del live[h]
+        steps += 1
+    ses.close()
+    assert len(finished) == len(cases) and steps < len(cases) + 2
+    for i, (g_a, st_a) in enumerate(alone):
+        g_b, st_b = finished[i]
+        assert torch.equal(g_a, g_b), i
+        assert [st_a[k] for k in KEYS] == [st_b[k] for k in KEYS], (i, st_a, st_b)
