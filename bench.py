@@ -236,11 +236,16 @@ def bench_small(dev, calls):
     torch.cuda.synchronize()
     us = (time.perf_counter() - t0) * 1e6 / calls
     tm = pmsz.last_timing()
+    rr = pmsz.last_rounds()
     dev_us = (tm["dirs_ms"] + tm["sweep_ms"] + tm["engine_ms"]) * 1e3
     return {"workload": "perlin 64^3 f32, 4 octaves, 4 cells, eps 1e-3, seed 1234",
             "us_per_call": round(us, 1), "device_us": round(dev_us, 1),
             "rounds": tm["rounds"], "device_us_per_round": round(tm["engine_ms"] * 1e3 / max(tm["rounds"], 1), 1),
-            "iterations": st["iterations"], "status": st["status"]}
+            "iterations": st["iterations"], "status": st["status"],
+            "per_round": {"detect_us": [round(r["detect_ms"] * 1e3, 1) for r in rr],
+                          "apply_us": [round(r["apply_ms"] * 1e3, 1) for r in rr],
+                          "swept": [r["swept"] for r in rr], "sparse": [r["sparse"] for r in rr],
+                          "edits": [r["edits"] for r in rr]}}
 
 
 def bench_large(dev, steps):

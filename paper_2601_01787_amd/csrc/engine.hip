@@ -786,7 +786,9 @@ __device__ void detect_tiles(const EngineArgs& a, TileLds<T>& sm, unsigned long 
     int take = 0;
     if (mine < a.total_tiles) {
       const FieldDesc& d = a.fd[field_of_tile(a.fd, a.nf, mine)];
-      if (ONLY == KIND_FIRST_GIVEN) {
+      if (DIM != 0 && d.geo.ndim != DIM) {
+        // the other dimension's sweep kernel takes this tile (and its mark)
+      } else if (ONLY == KIND_FIRST_GIVEN) {
         const FieldIter s = state_at(d, E, E0);
         take = !s.started && !s.done;
       } else {

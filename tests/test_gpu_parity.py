@@ -269,6 +269,27 @@ def test_batched_matches_alone():
         assert same_bits(g_a, host(g_b))
 
 
+def test_mixed_dimension_batch_with_sweep_kernels_matches_alone():
+    """A batch of 2^23 vertices or more runs its first two rounds' tile
+    detection as sweep kernels, one per dimension; with 2D and 3D fields both
+    in tile rounds (round 1 here), each kernel must take only its own
+    dimension's tiles and their activity marks.  Every field ends as it does
+    alone (where the two big fields take the one-launch path)."""
+    cases = [synth.perlin_case(160, 4, 4, 1e-3, 21), synth.make_2d_case(2100, 2100, 1e-3, 22),
+             synth.perlin_case(24, 3, 3, 1e-3, 1), synth.make_2d_case(300, 190, 1e-2, 3)]
+    assert sum(f.numel() for f, _, _ in cases) >= 1 << 23
+    alone = []
+    for f, fhat, xi in cases:
+        g, st = pmsz.correct(f.to(DEV), fhat.to(DEV), xi)
+        alone.append((g, st))
+    fields = [(f.to(DEV), fhat.to(DEV), xi) for f, fhat, xi in cases]
+    stats = pmsz.correct_batched(fields)
+    assert pmsz.last_timing()["sweeps"] > 0
+    for i, ((g_a, st_a), (_, g_b, _), st_b) in enumerate(zip(alone, fields, stats)):
+        assert st_a == st_b, i
+        assert torch.equal(g_a, g_b), i
+
+
 def test_full_size_perlin_512():
     """512^3 binary32 Perlin (one GPU's weak-scaling share): the corrected field
     and the directions are compared through hashes the oracle wrote, and the
