@@ -1330,7 +1330,7 @@ int pmsz_correct_blocks(const pmsz_grid* grid, const void* f, void* g, double xi
         r = fail(st[id].status, "block %lld: %s", (long long)id,
                  pmsz_status_string(st[id].status));
     if (r != PMSZ_OK) break;
-    stats->compute_ms += t_timing.last.dirs_ms + t_timing.last.engine_ms;
+    stats->compute_ms += t_timing.last.dirs_ms + t_timing.last.sweep_ms + t_timing.last.engine_ms;
     // ghost-layer exchange
     unsigned long long lowered = 0;
     if ((r = hip_check(engine_fill(ctr, sizeof(unsigned long long), 0u, s)))) break;
