@@ -67,16 +67,22 @@ class BatchingServer:
     long as the largest field's round; `work_budget` (vertices) caps the
     vertices admitted at once so that large fields do not hold every small
     one back for their whole run (a request larger than the budget is
-    admitted when the session is empty).  None disables the cap.  Requests
+    admitted when the session is empty).  None disables the cap.  With
+    `backlog_len` or more requests waiting the cap is `backlog_work_budget`
+    instead (None: none): under a backlog, fields that share steps overlap
+    their latency-bound rounds, and waiting costs more than sharing.  Requests
     are admitted in arrival order, a request that does not fit being passed
     by later ones that do, until it has waited `max_wait` seconds."""
 
     def __init__(self, device, hbm_budget, max_fields=64, rounds_per_step=0,
                  dtype=torch.float32, max_iters=1 << 40, work_budget=DEFAULT_WORK_BUDGET,
-                 max_wait=0.02, bulk_step=0.002):
+                 max_wait=0.02, bulk_step=0.002, backlog_len=16, backlog_work_budget=None):
         self.device = torch.device(device)
         self.budget = int(hbm_budget)
         self.work_budget = work_budget
+        self.backlog_len = backlog_len
+        self.backlog_work_budget = backlog_work_budget
+        self.cap = work_budget
         self.work = 0
         self.rounds = int(rounds_per_step)
         self.max_iters = max_iters
@@ -93,11 +99,15 @@ class BatchingServer:
         self.launched_at = 0.0
         self.deliver_sent = False
 
+    def set_queue(self, waiting):
+        """The vertex cap for `waiting` requests in the queue."""
+        self.cap = self.backlog_work_budget if waiting >= self.backlog_len else self.work_budget
+
     def can_admit(self, req):
         if len(self.active) >= self.max_fields or self.in_use + req.footprint > self.budget:
             return False
-        return (self.work_budget is None or not self.active
-                or self.work + req.f.numel() <= self.work_budget)
+        return (self.cap is None or not self.active
+                or self.work + req.f.numel() <= self.cap)
 
     def admit(self, req, now):
         req.g = req.fhat.clone()
@@ -115,6 +125,7 @@ class BatchingServer:
         """Admit waiting requests (a deque in arrival order) that fit,
         looking at no more than the `max_scan` oldest (a long queue is not
         rescanned at every step)."""
+        self.set_queue(len(pending))
         kept = []
         scanned = 0
         while pending and scanned < max_scan and len(self.active) < self.max_fields:
@@ -228,6 +239,7 @@ def _replay(server_kind, srv, arrivals, pending, done, dev, check):
             pending.append(arrivals.popleft())
         if server_kind == "batched":
             if srv.in_flight:
+                srv.set_queue(len(pending))
                 srv.tick(now, bool(pending) and
                          any(srv.can_admit(r) for r in itertools.islice(pending, 64)))
                 finished = srv.poll()
