@@ -312,3 +312,30 @@ def test_stop_when_done_steps_match_alone():
         g_b, st_b = finished[i]
         assert torch.equal(g_a, g_b), i
         assert [st_a[k] for k in KEYS] == [st_b[k] for k in KEYS], (i, st_a, st_b)
+
+
+def test_burst_of_requests_matches_alone():
+    """A burst of requests arriving together (a backlog from the start): the
+    server runs bulk steps, admits without the vertex cap while 16 or more
+    wait, collects fields on stop-when-done requests; every result equals
+    the alone result and every request is served."""
+    cases = _cases()
+    alone = _alone(cases)
+    rng = np.random.default_rng(11)
+    reqs = []
+    for i in range(40):
+        k = int(rng.integers(len(cases)))
+        f, fh, xi = cases[k]
+        r = serve.Request(i, f, fh, xi, 0.0001 * i)
+        r.stats = k
+        reqs.append(r)
+    which = {r.rid: r.stats for r in reqs}
+    bad = []
+
+    def check(r):
+        if not torch.equal(r.g, alone[which[r.rid]][0]):
+            bad.append(r.rid)
+
+    done = serve.run_open_loop("batched", reqs, DEV, hbm_budget=1 << 30, max_fields=6,
+                               rounds_per_step=0, check=check, work_budget=1 << 14)
+    assert len(done) == len(reqs) and not bad
