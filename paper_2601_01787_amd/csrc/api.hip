@@ -47,9 +47,6 @@ inline int hip_check(hipError_t e) {
 }
 
 constexpr size_t kAlign = 256;
-// Batches of at least this many vertices run the sweeps of rounds 0 and 1 as
-// their own kernels (run_batch).
-constexpr int64_t kSplitVoxels = int64_t(1) << 23;
 constexpr int64_t DEFAULT_TUNE_ITERS = int64_t(1) << 40;  // tuning runs go to convergence
 inline size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
@@ -329,8 +326,9 @@ void release_staging(Staging& s) {
 // Events around the engine launch and the figures of the last run.
 struct Timing {
   // directions, first sweep, first engine launch, second sweep, second
-  // engine launch, end (the sweeps and the first launch only when split)
-  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  // engine launch, end (the sweeps and the first launch only when split);
+  // then around each later sweep and engine launch (large tile rounds)
+  hipEvent_t ev[9] = {};
   uint64_t gen = 0;
   pmsz_timing last;
   pmsz_round rounds[kTraceRounds];
@@ -409,6 +407,7 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
   a.tiles_swept = 0;
   a.stop_on_done = 0;
   a.stop_host = nullptr;
+  a.split_tiles = 0;
   a.fd = (const FieldDesc*)(base + P.desc);
   a.out = out;
   a.nf = n;
@@ -451,22 +450,54 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
     HIP_TRY(engine_sweep(dtype, KIND_NEXT, P.edit_mode != 0, dims, a, s));
     if (timed) HIP_TRY(hipEventRecord(tm.ev[4], s));
   }
+  // A large batch's later launches end before any round in which a field of
+  // kSplitVoxels vertices or more sweeps tiles; the host then runs that
+  // round's tile detection as a sweep kernel and launches the engine again.
+  a.split_tiles = split ? 1 : 0;
   HIP_TRY(engine_launch(dtype, a, s, &grid));
   if (timed) HIP_TRY(hipEventRecord(tm.ev[5], s));
-  // the staging buffer is reused for the results: the upload above is
-  // stream-ordered before this copy, so it has been consumed
-  HIP_TRY(hipMemcpyAsync(stage, ctl, kCtlHostBytes, hipMemcpyDeviceToHost, s));
-  if (timed)
-    HIP_TRY(hipMemcpyAsync((char*)stage + kCtlHostBytes, a.trace, kTraceBytes,
-                           hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync((char*)stage + kCtlHostBytes + kTraceBytes, out,
-                         sizeof(FieldIter) * (size_t)n, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
   const EngineCtl* hc = (const EngineCtl*)stage;
   const unsigned long long* tr = (const unsigned long long*)((char*)stage + kCtlHostBytes);
   const FieldIter* hs =
       (const FieldIter*)((char*)stage + kCtlHostBytes + kTraceBytes);
-  if (hc->error) return fail(PMSZ_ERR_DEVICE, "grid barrier timed out in the correction engine");
+  // the sweeps of those later tile rounds: ms by round (timed runs), count
+  float late_ms[kTraceRounds] = {};
+  int64_t late = 0;
+  unsigned long long late_round = 0;
+  float late_sweep_ms = 0.f, late_engine_ms = 0.f;
+  for (;;) {
+    // the staging buffer is reused for the results: the upload above is
+    // stream-ordered before this copy, so it has been consumed
+    HIP_TRY(hipMemcpyAsync(stage, ctl, kCtlHostBytes, hipMemcpyDeviceToHost, s));
+    if (timed)
+      HIP_TRY(hipMemcpyAsync((char*)stage + kCtlHostBytes, a.trace, kTraceBytes,
+                             hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync((char*)stage + kCtlHostBytes + kTraceBytes, out,
+                           sizeof(FieldIter) * (size_t)n, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (hc->error) return fail(PMSZ_ERR_DEVICE, "grid barrier timed out in the correction engine");
+    if (late > 0 && timed) {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, tm.ev[6], tm.ev[7]));
+      if (late_round < (unsigned long long)kTraceRounds) late_ms[late_round] += ms;
+      late_sweep_ms += ms;
+      HIP_TRY(hipEventElapsedTime(&ms, tm.ev[7], tm.ev[8]));
+      late_engine_ms += ms;
+    }
+    bool running = false;
+    for (int32_t i = 0; i < n && !running; ++i) running = !hs[i].done;
+    if (!running || !split) break;
+    ++late;
+    late_round = hc->epoch;
+    a.tiles_swept = 1;
+    a.has_fresh = 0;
+    a.max_rounds = -1;
+    if (timed) HIP_TRY(hipEventRecord(tm.ev[6], s));
+    HIP_TRY(engine_sweep(dtype, KIND_NEXT, P.edit_mode != 0, dims, a, s));
+    if (timed) HIP_TRY(hipEventRecord(tm.ev[7], s));
+    HIP_TRY(engine_launch(dtype, a, s, &grid));
+    if (timed) HIP_TRY(hipEventRecord(tm.ev[8], s));
+  }
   if (!timed) {
     int first = PMSZ_OK;
     for (int32_t i = 0; i < n; ++i) {
@@ -486,9 +517,9 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
   }
   memset(&tm.last, 0, sizeof(tm.last));
   tm.last.dirs_ms = el[0];
-  tm.last.sweep_ms = el[1] + el[3];
-  tm.last.sweeps = split ? 2 : 0;
-  tm.last.engine_ms = el[2] + el[4];
+  tm.last.sweep_ms = el[1] + el[3] + late_sweep_ms;
+  tm.last.sweeps = split ? 2 + late : 0;
+  tm.last.engine_ms = el[2] + el[4] + late_engine_ms;
   tm.last.rounds = (int64_t)hc->epoch;  // the workspace starts every call at round 0
   tm.last.tiles = P.total_tiles;
   tm.last.grid = grid;
@@ -507,6 +538,7 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
       o.edits = (int64_t)t[5];
       o.sparse = (int64_t)t[6];
       if (split && r < 2) o.detect_ms += (double)el[r == 0 ? 1 : 3];  // the sweep kernel
+      o.detect_ms += (double)late_ms[r];  // a later round's sweep kernel
       if (r == 0) {
         tm.last.first_round_ms = o.detect_ms + o.apply_ms;
       } else {
@@ -1545,6 +1577,7 @@ int pmsz_session_step_ex(pmsz_session* S, int64_t max_rounds, int32_t flags) {
   a.tiles_swept = 0;
   a.stop_on_done = 0;
   a.stop_host = nullptr;
+  a.split_tiles = 0;
   a.fd = (const FieldDesc*)(S->ws + S->desc_off);
   a.out = (FieldIter*)(S->ws + S->out_off);
   a.nf = n;

@@ -654,6 +654,7 @@ __device__ __forceinline__ int prefix_find(const long long* s_pre, int n, long l
 }
 
 constexpr int kApplyCap = 2048;   // targets per compaction pass
+constexpr int kEditUnroll = 2;    // targets per thread with loads in flight together
 
 // Apply pass over bitmap words [w0, w1) of one field: the block reads the
 // segment in one sweep (16 words per thread), compacts the set bits into an
@@ -716,29 +717,50 @@ __device__ __forceinline__ void apply_segment(const FieldDesc& d, int32_t w0, in
                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     lds_barrier();
     const long long lbase = edit ? *lbase_sh : 0;
-    for (int j = tid; j < n; j += 256) {
-      const int32_t t = (int32_t)list[j];
-      const T gt = g[t];
-      const T lb = lower_bound<T>(f[t], xi);
-      const bool above = gt > lb;
-      if (d.prop) {
-        // targeted edit: the smallest proposal, never below the bound; the
-        // proposal slot is reset for the next round
-        using K = decltype(prop_key(gt));
-        const gptr<K> slot = (gptr<K>)d.prop + t;
-        if (above && edit) {
-          const T pv = prop_value(*slot);
-          g[t] = pv > lb ? pv : lb;
-        }
-        *slot = ~K(0);
-      } else if (above && edit) {
-        g[t] = halving_edit<T>(gt, lb);
+    // kEditUnroll targets per thread at a time: their loads are all issued
+    // before any of their stores (the targets are distinct vertices), so a
+    // thread keeps several gathers in flight instead of one dependent chain
+    // per target
+    for (int j0 = tid; j0 < n; j0 += 256 * kEditUnroll) {
+      int32_t t[kEditUnroll];
+      T gt[kEditUnroll], ft[kEditUnroll];
+#pragma unroll
+      for (int u = 0; u < kEditUnroll; ++u) {
+        const int j = j0 + 256 * u;
+        t[u] = (int32_t)list[j < n ? j : j0];
       }
-      edits += (above && edit) ? 1u : 0u;
-      at_lb += above ? 0u : 1u;
+#pragma unroll
+      for (int u = 0; u < kEditUnroll; ++u) {
+        gt[u] = g[t[u]];
+        ft[u] = f[t[u]];
+      }
+#pragma unroll
+      for (int u = 0; u < kEditUnroll; ++u) {
+        const int j = j0 + 256 * u;
+        if (j >= n) break;
+        const T lb = lower_bound<T>(ft[u], xi);
+        const bool above = gt[u] > lb;
+        if (d.prop) {
+          // targeted edit: the smallest proposal, never below the bound; the
+          // proposal slot is reset for the next round
+          using K = decltype(prop_key(gt[u]));
+          const gptr<K> slot = (gptr<K>)d.prop + t[u];
+          if (above && edit) {
+            const T pv = prop_value(*slot);
+            g[t[u]] = pv > lb ? pv : lb;
+          }
+          *slot = ~K(0);
+        } else if (above && edit) {
+          g[t[u]] = halving_edit<T>(gt[u], lb);
+        }
+        edits += (above && edit) ? 1u : 0u;
+        at_lb += above ? 0u : 1u;
+        if (edit && lbase + j < slice) tlist[(int64_t)slot * slice + lbase + j] = (uint32_t)t[u];
+      }
       if (edit) {
-        mark_box(d, box_of(d.geo, t), nxt);
-        if (lbase + j < slice) tlist[(int64_t)slot * slice + lbase + j] = (uint32_t)t;
+#pragma unroll
+        for (int u = 0; u < kEditUnroll; ++u)
+          if (j0 + 256 * u < n) mark_box(d, box_of(d.geo, t[u]), nxt);
       }
     }
     lds_barrier();
@@ -947,25 +969,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     // one index space (prefix sums in LDS) that the grid strides over.  The
     // mismatch counts are only tested against zero in these rounds.
     int any_tiles = 0;
+    bool split_here = false;
     for (int f0 = 0; f0 < a.nf; f0 += 256) {
       const int fi = f0 + tid;
       long long items = 0;
-      int sweeps = 0;
+      int sweeps = 0, big = 0;
       if (fi < a.nf) {
         const FieldDesc& d = a.fd[fi];
         const FieldIter s = state_at(d, E, E0);
         items = sparse_items(d, s, E, s_slot + tid * kCtrSlots);
         if (items < 0) {
           sweeps = !s.done;
+          big = sweeps && s.started && d.geo.n >= kSplitVoxels;
           items = 0;
-        }
-        if (items > 0 && blockIdx.x == 0) {
-          relaxed_add(&as_global(d.st)->c[q].s[0].swept, (unsigned long long)items);
-          atomicAdd(&ctl->tot[q][0].swept, (unsigned long long)items);
-          atomicAdd(&ctl->tot[q][0].sparse, (unsigned long long)items);
         }
       }
       any_tiles |= __syncthreads_or(sweeps);
+      // A large tile round is left to a sweep kernel at the march's own
+      // occupancy: every block sees the same states and leaves here, before
+      // this round's detection has done anything (the marks of its active
+      // tiles stay set for the sweep).
+      if (a.split_tiles && r > 0 && f0 == 0 && __syncthreads_or(big)) {
+        split_here = true;
+        break;
+      }
+      if (fi < a.nf && items > 0 && blockIdx.x == 0) {
+        const FieldDesc& d = a.fd[fi];
+        relaxed_add(&as_global(d.st)->c[q].s[0].swept, (unsigned long long)items);
+        atomicAdd(&ctl->tot[q][0].swept, (unsigned long long)items);
+        atomicAdd(&ctl->tot[q][0].sparse, (unsigned long long)items);
+      }
       const long long total = block_prefix(items, s_pre);
       const int nfc = a.nf - f0 < 256 ? a.nf - f0 : 256;
       FieldAcc mism;
@@ -988,6 +1021,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
       acc_flush(mism, mism_ptr, s_scan, red);
       __syncthreads();  // s_pre is rewritten by the next group
     }
+    if (split_here) break;
     // Tiles: skipped when every running field is in a sparse round (marks
     // left from earlier rounds then only widen a later tile round).
     if (any_tiles && !(r == 0 && a.tiles_swept))

@@ -117,6 +117,10 @@ struct EngineCtl {
 };
 constexpr size_t kCtlHostBytes = offsetof(EngineCtl, xbar);
 
+// Batches (and fields) of at least this many vertices run their tile sweeps
+// as kernels of their own (engine_sweep) where the host can place them.
+constexpr int64_t kSplitVoxels = int64_t(1) << 23;
+
 // Values of the host's stop word: end the launch after the current round;
 // end it after a round that begins with a field of the launch done.
 constexpr unsigned kStopNow = 1u, kStopWhenDone = 2u;
@@ -136,6 +140,10 @@ struct EngineArgs {
   int32_t stop_on_done;  // end the launch after the round in which a field is
                          // first seen finished
   unsigned* stop_host;   // nullable, host memory: kStopNow / kStopWhenDone (below)
+  int32_t split_tiles;   // end the launch before a round, other than its first, in
+                         // which a field of kSplitVoxels vertices or more (among
+                         // the first 256) sweeps tiles: a sweep kernel takes that
+                         // round's tile detection and the next launch the rest
                          // after the round in progress
 };
 

@@ -290,6 +290,31 @@ def test_mixed_dimension_batch_with_sweep_kernels_matches_alone():
         assert torch.equal(g_a, g_b), i
 
 
+def test_later_tile_rounds_as_sweep_kernels_match_alone():
+    """In a batch of 2^23 vertices or more, an engine launch ends before any
+    later round in which a field of 2^23 vertices or more sweeps tiles, and
+    that round's tile detection runs as a sweep kernel between launches.
+    Here the 4096^2 field at 1e-2 keeps tile rounds past round 1 (more than
+    two sweep launches); every field ends as it does alone."""
+    cases = [synth.make_2d_case(4096, 4096, 1e-2, 31), synth.make_2d_case(1500, 900, 1e-3, 32),
+             synth.perlin_case(40, 3, 3, 1e-3, 2), synth.make_2d_case(70, 90, 1e-3, 4)]
+    alone = []
+    for f, fhat, xi in cases:
+        g, st = pmsz.correct(f.to(DEV), fhat.to(DEV), xi)
+        alone.append((g, st))
+    fields = [(f.to(DEV), fhat.to(DEV), xi) for f, fhat, xi in cases]
+    stats = pmsz.correct_batched(fields)
+    tm = pmsz.last_timing()
+    assert tm["sweeps"] > 2, tm
+    for i, ((g_a, st_a), (_, g_b, _), st_b) in enumerate(zip(alone, fields, stats)):
+        assert st_a == st_b, i
+        assert torch.equal(g_a, g_b), i
+    # the per-round record spans every launch: its edits add up to the fields'
+    rounds = pmsz.last_rounds()
+    assert len(rounds) == tm["rounds"]
+    assert sum(r["edits"] for r in rounds) == sum(st["steps_applied"] for st in stats)
+
+
 def test_full_size_perlin_512():
     """512^3 binary32 Perlin (one GPU's weak-scaling share): the corrected field
     and the directions are compared through hashes the oracle wrote, and the
