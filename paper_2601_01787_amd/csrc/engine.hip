@@ -351,17 +351,18 @@ struct TileBox {
 
 __device__ __forceinline__ TileBox box_of(const TileGeo& G, int32_t t) {
   TileBox b;
-  const int32_t x = t % G.nx;
+  const int32_t row = fdiv(t, G.div_nx);  // y + ny z
+  const int32_t x = t - row * G.nx;
   const int32_t xl = x > 0 ? x - 1 : 0, xh = x + 1 < G.nx ? x + 1 : x;
   if (G.ndim == 3) {
-    const int32_t y = (t / G.nx) % G.ny, z = t / G.sxy;
+    const int32_t z = fdiv(row, G.div_ny), y = row - z * G.ny;
     const int32_t yl = y > 0 ? y - 1 : 0, yh = y + 1 < G.ny ? y + 1 : y;
     const int32_t zl = z > 0 ? z - 1 : 0, zh = z + 1 < G.nz ? z + 1 : z;
-    b = {xl / TX, xh / TX, yl / TY, yh / TY, zl / G.chunk, zh / G.chunk};
+    b = {xl / TX, xh / TX, yl / TY, yh / TY, fdiv(zl, G.div_chunk), fdiv(zh, G.div_chunk)};
   } else {
-    const int32_t y = t / G.nx;
+    const int32_t y = row;
     const int32_t yl = y > 0 ? y - 1 : 0, yh = y + 1 < G.ny ? y + 1 : y;
-    b = {xl / RX, xh / RX, yl / G.chunk, yh / G.chunk, 0, 0};
+    b = {xl / RX, xh / RX, fdiv(yl, G.div_chunk), fdiv(yh, G.div_chunk), 0, 0};
   }
   return b;
 }
@@ -530,9 +531,10 @@ __device__ __forceinline__ Exam sparse_examine(const FieldDesc& d, uint32_t m,
   // the neighbour's offset
   const int mm = code & 7;
   const int sg = (code & 8) ? -1 : 1;
-  const int32_t x = t % G.nx;
-  const int32_t y = three ? (t / G.nx) % G.ny : t / G.nx;
-  const int32_t z = three ? t / G.sxy : 0;
+  const int32_t row = fdiv(t, G.div_nx);  // y + ny z
+  const int32_t x = t - row * G.nx;
+  const int32_t z = three ? fdiv(row, G.div_ny) : 0;
+  const int32_t y = row - z * G.ny;
   const int32_t X = x + sg * (mm & 1), Y = y + sg * ((mm >> 1) & 1), Z = z + sg * ((mm >> 2) & 1);
   Exam ex{-1, -1, 0u};
   // only vertices of the detection box are examined (it lies inside the grid)
@@ -693,6 +695,7 @@ __device__ __forceinline__ void apply_segment(const FieldDesc& d, int32_t w0, in
   const gptr<const T> f = as_global((const T*)d.f);
   const gptr<T> g = as_global((T*)d.g);
   const T xi = (T)d.xi_t;
+  TileBox last{-1, -1, -1, -1, -1, -1};  // the tile box this thread marked last
   for (int base = 0; base < total; base += kApplyCap) {
     int o = off;
     if (o < base + kApplyCap && o + cnt > base) {
@@ -759,8 +762,18 @@ __device__ __forceinline__ void apply_segment(const FieldDesc& d, int32_t w0, in
       }
       if (edit) {
 #pragma unroll
-        for (int u = 0; u < kEditUnroll; ++u)
-          if (j0 + 256 * u < n) mark_box(d, box_of(d.geo, t[u]), nxt);
+        for (int u = 0; u < kEditUnroll; ++u) {
+          if (j0 + 256 * u >= n) break;
+          // a thread's successive targets lie a few rows apart in a dense
+          // round and mostly share their tile box, whose marks are then set
+          // already (marks of this round's parity are only ever set here)
+          const TileBox b = box_of(d.geo, t[u]);
+          if (b.x0 != last.x0 || b.x1 != last.x1 || b.y0 != last.y0 || b.y1 != last.y1 ||
+              b.z0 != last.z0 || b.z1 != last.z1) {
+            mark_box(d, b, nxt);
+            last = b;
+          }
+        }
       }
     }
     lds_barrier();

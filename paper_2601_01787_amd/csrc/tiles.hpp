@@ -75,6 +75,31 @@ __device__ __forceinline__ Ext<T> merge_dn(const Ext<T>& A, const Ext<T>& B) {
   return Ext<T>{bh ? B.hi : A.hi, bl ? B.lo : A.lo, bh ? B.ca : A.ca, bl ? B.cd : A.cd};
 }
 
+// Division of a vertex index n in [0, 2^31) by a divisor d >= 1 fixed per
+// field, as a multiply and a shift: with l = ceil(log2 d) and
+// m = ceil(2^(31+l) / d) < 2^32, floor(n m / 2^(31+l)) = floor(n / d),
+// because n m / 2^(31+l) = n / d + n e / (d 2^(31+l)) with e = m d - 2^(31+l)
+// in [0, d), and that excess is below 2^-l <= 1/d (zero when d = 2^l), less
+// than the gap from n / d to the next integer.  The host computes m and the
+// shift (make_div); the loops of the apply pass and the sparse examination
+// then need no integer division per target.
+struct FastDiv {
+  uint32_t m;
+  int32_t sh;  // 31 + l
+};
+__host__ __device__ inline int32_t fdiv(int32_t n, FastDiv d) {
+  return (int32_t)(((uint64_t)(uint32_t)n * d.m) >> d.sh);
+}
+inline FastDiv make_div(int64_t d) {
+  int l = 0;
+  while ((int64_t(1) << l) < d) ++l;
+  const unsigned __int128 p = (unsigned __int128)1 << (31 + l);
+  FastDiv f;
+  f.m = (uint32_t)((p + (unsigned __int128)d - 1) / (unsigned __int128)d);
+  f.sh = 31 + l;
+  return f;
+}
+
 // Shape of one field as the tile code sees it.
 struct TileGeo {
   int32_t nx, ny, nz, sxy, n;  // vertex ids fit in int32 (n < 2^31)
@@ -86,6 +111,7 @@ struct TileGeo {
   // whole grid, except for a block of a decomposed domain (Sec. IV-B), whose
   // outer layer is a ghost copy of its neighbours' vertices.
   int32_t cx0, cx1, cy0, cy1, cz0, cz1;
+  FastDiv div_nx, div_ny, div_sxy, div_chunk;  // by nx, ny, nx * ny, chunk
 };
 
 // The geometry of the tile being marched, in scalar registers (see uniform).
@@ -97,6 +123,7 @@ __device__ __forceinline__ TileGeo uniform_geo(const TileGeo& g) {
   u.tiles_x = uniform(g.tiles_x), u.tiles_y = uniform(g.tiles_y), u.tiles_z = uniform(g.tiles_z);
   u.cx0 = uniform(g.cx0), u.cx1 = uniform(g.cx1), u.cy0 = uniform(g.cy0);
   u.cy1 = uniform(g.cy1), u.cz0 = uniform(g.cz0), u.cz1 = uniform(g.cz1);
+  u.div_nx = g.div_nx, u.div_ny = g.div_ny, u.div_sxy = g.div_sxy, u.div_chunk = g.div_chunk;
   return u;
 }
 
@@ -119,6 +146,10 @@ inline TileGeo make_tile_geo(int ndim, int64_t nx, int64_t ny, int64_t nz, int c
   G.cy1 = (int32_t)ny;
   G.cz0 = 0;
   G.cz1 = (int32_t)nz;
+  G.div_nx = make_div(nx);
+  G.div_ny = make_div(ny);
+  G.div_sxy = make_div(nx * ny);
+  G.div_chunk = make_div(chunk);
   if (ndim == 3) {
     G.tiles_x = (int32_t)((nx + TX - 1) / TX);
     G.tiles_y = (int32_t)((ny + TY - 1) / TY);
