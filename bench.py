@@ -65,7 +65,8 @@ def kernel_split(tm, rounds, s):
     writes flag bits (s + 1.125) per vertex examined, in tiles or by sparse
     examination; an edit reads f and g and writes g (3s).  With split sweeps
     the tile detection of rounds 0 and 1 is the sweep kernel's (two launches)
-    and the rest the engine's (two launches)."""
+    and the rest the engine's: round 0's apply kernel and the engine launch
+    from round 1 (two launches)."""
     det = [r["swept"] * ((2 * s + 1) if i == 0 else (s + 1.125)) for i, r in enumerate(rounds)]
     tiles = [(r["swept"] - r["sparse"]) * ((2 * s + 1) if i == 0 else (s + 1.125))
              for i, r in enumerate(rounds)]

@@ -395,15 +395,17 @@ int pmsz_session_destroy(pmsz_session* s);
  * events recorded on the caller's stream around each launch, and the work it
  * did.  Used by the benchmark for roofline figures. */
 typedef struct {
-  double engine_ms;  /* the persistent correction kernel (all its launches)   */
+  double engine_ms;  /* the persistent correction kernel (all its launches),
+                        with round 0's apply kernel of large batches          */
   int64_t rounds;    /* detect/apply rounds run                               */
   int64_t swept;     /* vertices examined by detect passes, all rounds        */
   int64_t edits;     /* value changes, all fields                             */
   int64_t voxels;    /* vertices of the batch                                 */
   int64_t tiles;     /* tiles of the batch                                    */
   int32_t grid;      /* blocks of the cooperative launch                      */
-  int32_t sweeps;    /* tile sweeps run as kernels of their own (0 or 2: the
-                        detection of rounds 0 and 1 of large batches)          */
+  int32_t sweeps;    /* tile sweeps run as kernels of their own (large
+                        batches: 2 for rounds 0 and 1, one more per later
+                        round with a large tile sweep; else 0)                 */
   double first_round_ms; /* first round: validation, detect, apply            */
   double detect_ms;  /* detect phases of the later rounds (block 0's clock)    */
   double apply_ms;   /* apply phases of the later rounds                       */

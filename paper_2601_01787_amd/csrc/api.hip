@@ -443,7 +443,8 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
     a.max_rounds = 1;
     HIP_TRY(engine_sweep(dtype, KIND_FIRST_GIVEN, P.edit_mode != 0, dims, a, s));
     if (timed) HIP_TRY(hipEventRecord(tm.ev[2], s));
-    HIP_TRY(engine_launch(dtype, a, s, &grid));
+    // round 0's apply pass as a plain kernel; the engine starts at round 1
+    HIP_TRY(engine_apply_first(dtype, a, s));
     if (timed) HIP_TRY(hipEventRecord(tm.ev[3], s));
     a.has_fresh = 0;
     a.max_rounds = -1;

@@ -892,6 +892,102 @@ __device__ void detect_tiles(const EngineArgs& a, TileLds<T>& sm, unsigned long 
   }
 }
 
+// Apply pass of a round (parity p, counter set q) on one unit: segment
+// u >> plog of the batch's flag bitmaps, part u & (2^plog - 1) of it.  Every
+// thread of the block takes part (block reductions inside).
+template <class T>
+__device__ __forceinline__ void apply_unit(const EngineArgs& a, int64_t u, int plog, int p, int q,
+                                           uint32_t* s_list, int* s_scan, long long* s_lbase,
+                                           unsigned long long* red) {
+  const int tid = threadIdx.x;
+  EngineCtl* ctl = a.ctl;
+  const int64_t sg = u >> plog;
+  const int32_t part = (int32_t)(u & ((int64_t(1) << plog) - 1));
+  const int fi = field_of_seg(a.fd, a.nf, sg);
+  const FieldDesc& d = a.fd[fi];
+  // the state at the start of the round (persisted before this pass)
+  const FieldIter s = load_iter(&as_global(d.st)->s[p]);
+  const gptr<FieldCtr> cq = &as_global(d.st)->c[q];
+  const gptr<uint8_t> nxt = as_global(d.act) + (p ^ 1) * tile_count(d.geo);
+  const unsigned long long mism = load_mism(cq);
+  bool bad = false;
+  if (!s.started) {
+    const CtrSum cs = load_ctr(cq);
+    bad = cs.bad_nf || cs.bad_b;
+  }
+  if (s.done || bad || mism == 0) return;
+  const bool edit = (long long)s.k < d.max_iters;
+  const int32_t span = (int32_t)(kSegWords >> plog);
+  const int32_t w0 = (int32_t)((sg - d.seg_base) * kSegWords) + part * span;
+  const int32_t w1 = (w0 + span < d.words) ? w0 + span : (int32_t)d.words;
+  if (w0 >= w1) return;  // a part past the end of the field's last segment
+  unsigned long long nflag = 0, at_lb = 0, edits = 0;
+  apply_segment<T>(d, w0, w1, edit, nxt, s_list, s_scan, s_lbase, cq, as_global(d.list), nflag,
+                   at_lb, edits);
+  // a segment holds at most 128K vertices: the three counts pack into
+  // 21-bit fields of one word for a single block reduction
+  const unsigned long long tot =
+      block_sum(pack3((unsigned)nflag, (unsigned)at_lb, (unsigned)edits), red);
+  if (tid == 0) {
+    const unsigned long long nf_ = unpack3(tot, 0), al_ = unpack3(tot, 1),
+                             ed_ = unpack3(tot, 2);
+    const int slot = ctr_slot();
+    if (nf_) {
+      relaxed_add(&cq->s[slot].nflag, nf_);
+      atomicAdd(&ctl->tot[q][slot].flagged, nf_);
+    }
+    if (al_) relaxed_add(&cq->s[slot].at_lb, al_);
+    if (ed_) atomicAdd(&ctl->tot[q][slot].edits, ed_);
+  }
+}
+
+// Round 0's apply pass of a batch whose round-0 tile detection ran as a sweep
+// kernel, as a plain kernel at the apply pass's own occupancy instead of a
+// one-round engine launch: the pass needs no grid barrier of its own, and
+// its scattered gathers want more waves in flight than the engine's register
+// budget allows.  k_first_round_end then does what the engine's block 0 and
+// tracer do at the end of a round, and the engine starts at round 1.
+template <class T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_apply_first(
+    EngineArgs a, int plog) {
+  __shared__ uint32_t s_list[kApplyCap];
+  __shared__ int s_scan[4];
+  __shared__ long long s_lbase;
+  __shared__ unsigned long long red[4];
+  if (a.trace && blockIdx.x == 0 && threadIdx.x == 0) {
+    // round 0 starts here (its detection was the sweep kernel's)
+    const unsigned long long now = wall_clock64();
+    a.trace[kTraceRounds * kTraceSlots] = now;
+    a.trace[0] = now;
+    a.trace[1] = now;
+  }
+  for (int64_t u = blockIdx.x; u < (a.total_segs << plog); u += gridDim.x)
+    apply_unit<T>(a, u, plog, 0, 0, s_list, s_scan, &s_lbase, red);
+}
+
+__global__ __launch_bounds__(256) void k_first_round_end(EngineArgs a) {
+  const int fi = blockIdx.x * 256 + threadIdx.x;
+  if (fi < a.nf) {
+    // the state at the start of round 1, as state_at(d, 1, 0) computes it
+    const FieldDesc& d = a.fd[fi];
+    const gptr<FieldState> st = as_global(d.st);
+    store_iter(&st->s[1], state_at(d, 1, 0));
+  }
+  if (fi == 0) {
+    a.ctl->epoch = 1;
+    a.ctl->rounds = 1;
+    if (a.trace) {
+      unsigned long long* t = a.trace;
+      const RoundTot rt = load_tot(a.ctl, 0);
+      t[2] = wall_clock64();
+      t[3] = rt.swept;
+      t[4] = rt.flagged;
+      t[5] = rt.edits;
+      t[6] = rt.sparse;
+    }
+  }
+}
+
 template <class T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 3))) void k_engine(EngineArgs a) {
   __shared__ TileLds<T> sm;
@@ -1054,45 +1150,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     // threads in a few long chains).
     // (Rounds after an all-sparse detect flag few vertices: whole segments.)
     const int plog = any_tiles ? parts_log2 : 0;
-    for (int64_t u = blockIdx.x; u < (a.total_segs << plog); u += G) {
-      const int64_t sg = u >> plog;
-      const int32_t part = (int32_t)(u & ((int64_t(1) << plog) - 1));
-      const int fi = field_of_seg(a.fd, a.nf, sg);
-      const FieldDesc& d = a.fd[fi];
-      const FieldIter s = load_iter(&as_global(d.st)->s[p]);  // persisted by block 0 before the barrier
-      const gptr<FieldCtr> cq = &as_global(d.st)->c[q];
-      const gptr<uint8_t> nxt = as_global(d.act) + (p ^ 1) * tile_count(d.geo);
-      const unsigned long long mism = load_mism(cq);
-      bool bad = false;
-      if (!s.started) {
-        const CtrSum cs = load_ctr(cq);
-        bad = cs.bad_nf || cs.bad_b;
-      }
-      if (s.done || bad || mism == 0) continue;
-      const bool edit = (long long)s.k < d.max_iters;
-      const int32_t span = (int32_t)(kSegWords >> plog);
-      const int32_t w0 = (int32_t)((sg - d.seg_base) * kSegWords) + part * span;
-      const int32_t w1 = (w0 + span < d.words) ? w0 + span : (int32_t)d.words;
-      if (w0 >= w1) continue;  // a part past the end of the field's last segment
-      unsigned long long nflag = 0, at_lb = 0, edits = 0;
-      apply_segment<T>(d, w0, w1, edit, nxt, s_list, s_scan, &s_lbase, cq, as_global(d.list), nflag,
-                       at_lb, edits);
-      // a segment holds at most 128K vertices: the three counts pack into
-      // 21-bit fields of one word for a single block reduction
-      const unsigned long long tot =
-          block_sum(pack3((unsigned)nflag, (unsigned)at_lb, (unsigned)edits), red);
-      if (tid == 0) {
-        const unsigned long long nf_ = unpack3(tot, 0), al_ = unpack3(tot, 1),
-                                 ed_ = unpack3(tot, 2);
-        const int slot = ctr_slot();
-        if (nf_) {
-          relaxed_add(&cq->s[slot].nflag, nf_);
-          atomicAdd(&ctl->tot[q][slot].flagged, nf_);
-        }
-        if (al_) relaxed_add(&cq->s[slot].at_lb, al_);
-        if (ed_) atomicAdd(&ctl->tot[q][slot].edits, ed_);
-      }
-    }
+    for (int64_t u = blockIdx.x; u < (a.total_segs << plog); u += G)
+      apply_unit<T>(a, u, plog, p, q, s_list, s_scan, &s_lbase, red);
     xcd_sync(ctl, xb, gen);
     if (engine_failed(ctl)) break;
     if (tracer && E < kTraceRounds) {
@@ -1266,6 +1325,33 @@ hipError_t engine_sweep(int dtype, int kind, bool prop, int dims, const EngineAr
                         hipStream_t s) {
   if (dtype == PMSZ_F32) return sweep_dims<float>(kind, prop, dims, a, s);
   return sweep_dims<double>(kind, prop, dims, a, s);
+}
+
+template <class T>
+static hipError_t apply_first_t(const EngineArgs& a, hipStream_t s) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  Occupancy occ;
+  if ((e = occupancy_of((const void*)k_apply_first<T>, dev, occ)) != hipSuccess) return e;
+  int64_t grid = (int64_t)(occ.per_cu > 0 ? occ.per_cu : 1) * (occ.cus > 0 ? occ.cus : 1);
+  // parts per segment as in the engine: a power of two up to 256, so that
+  // small fields' segments are shared by the grid's blocks
+  int plog = 0;
+  while (plog < 8 && (a.total_segs << (plog + 1)) <= grid) ++plog;
+  const int64_t units = a.total_segs << plog;
+  if (grid > units) grid = units;
+  if (grid < 1) grid = 1;
+  hipLaunchKernelGGL(k_apply_first<T>, dim3((unsigned)grid), dim3(256), 0, s, a, plog);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const unsigned fb = (unsigned)((a.nf + 255) / 256);
+  hipLaunchKernelGGL(k_first_round_end, dim3(fb > 0 ? fb : 1), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t engine_apply_first(int dtype, const EngineArgs& a, hipStream_t s) {
+  if (dtype == PMSZ_F32) return apply_first_t<float>(a, s);
+  return apply_first_t<double>(a, s);
 }
 
 template <class T>

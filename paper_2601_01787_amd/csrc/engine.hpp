@@ -139,12 +139,12 @@ struct EngineArgs {
                          // already run as its own kernel (engine_sweep)
   int32_t stop_on_done;  // end the launch after the round in which a field is
                          // first seen finished
-  unsigned* stop_host;   // nullable, host memory: kStopNow / kStopWhenDone (below)
+  unsigned* stop_host;   // nullable, host memory: kStopNow / kStopWhenDone (below),
+                         // read by block 0 at the start of every round
   int32_t split_tiles;   // end the launch before a round, other than its first, in
                          // which a field of kSplitVoxels vertices or more (among
                          // the first 256) sweeps tiles: a sweep kernel takes that
                          // round's tile detection and the next launch the rest
-                         // after the round in progress
 };
 
 // Round trace, for the first kTraceRounds rounds since the workspace was
@@ -176,6 +176,11 @@ hipError_t engine_dirs(int dtype, const FieldDesc* fd, int nf, int64_t total_til
 // (one kernel per dimension, each at its own occupancy).
 hipError_t engine_sweep(int dtype, int kind, bool prop, int dims, const EngineArgs& a,
                         hipStream_t s);
+
+// Round 0's apply pass as a plain kernel after a round-0 sweep, then the end
+// of round 0 (every field's state at round 1, epoch 1, the round's record):
+// the engine launch that follows starts at round 1.
+hipError_t engine_apply_first(int dtype, const EngineArgs& a, hipStream_t s);
 
 // Zero `bytes` bytes (multiple of 4, 4-byte aligned) with a kernel, so that
 // the call can sit inside a captured graph.
