@@ -389,6 +389,7 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
     d.act = (uint8_t*)(fb + L.act);
     d.bm = (uint32_t*)(fb + L.bm);
     d.list = (uint32_t*)(fb + L.list);
+    d.marks = (uint8_t*)(fb + L.marks);
     d.list_cap = list_capacity(d.geo);
     d.dirs = d.dirs_given ? (uint8_t*)dirs_given[i] : (uint8_t*)(base + P.dirs + P.dirs_off[i]);
     d.prop = P.edit_mode ? (void*)(base + P.prop + P.prop_off[i]) : nullptr;
@@ -408,6 +409,7 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
   a.stop_on_done = 0;
   a.stop_host = nullptr;
   a.split_tiles = 0;
+  a.tail_ok = n <= 256 ? 1 : 0;
   a.fd = (const FieldDesc*)(base + P.desc);
   a.out = out;
   a.nf = n;
@@ -456,6 +458,7 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
   // round's tile detection as a sweep kernel and launches the engine again.
   a.split_tiles = split ? 1 : 0;
   HIP_TRY(engine_launch(dtype, a, s, &grid));
+  if (a.tail_ok) HIP_TRY(engine_tail(dtype, a, s));
   if (timed) HIP_TRY(hipEventRecord(tm.ev[5], s));
   const EngineCtl* hc = (const EngineCtl*)stage;
   const unsigned long long* tr = (const unsigned long long*)((char*)stage + kCtlHostBytes);
@@ -487,7 +490,10 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
     }
     bool running = false;
     for (int32_t i = 0; i < n && !running; ++i) running = !hs[i].done;
-    if (!running || !split) break;
+    if (!running) break;
+    // the launches ended before a round with tile sweeps: a large one (split
+    // batches), or one after the tail (k_tail handed the loop back)
+    if (!split && hc->handoff != kHandToEngine) break;
     ++late;
     late_round = hc->epoch;
     a.tiles_swept = 1;
@@ -497,6 +503,7 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
     HIP_TRY(engine_sweep(dtype, KIND_NEXT, P.edit_mode != 0, dims, a, s));
     if (timed) HIP_TRY(hipEventRecord(tm.ev[7], s));
     HIP_TRY(engine_launch(dtype, a, s, &grid));
+    if (a.tail_ok) HIP_TRY(engine_tail(dtype, a, s));
     if (timed) HIP_TRY(hipEventRecord(tm.ev[8], s));
   }
   if (!timed) {
@@ -1484,6 +1491,7 @@ int pmsz_session_add(pmsz_session* S, const pmsz_field* field, int64_t max_iters
   e.d.act = (uint8_t*)(fb + L.act);
   e.d.bm = (uint32_t*)(fb + L.bm);
   e.d.list = (uint32_t*)(fb + L.list);
+  e.d.marks = (uint8_t*)(fb + L.marks);
   e.d.list_cap = list_capacity(e.d.geo);
   e.d.dirs = (uint8_t*)(fb + L.dirs);
   HIP_TRY(engine_zero(fb, L.dirs, S->stream));
@@ -1590,6 +1598,7 @@ int pmsz_session_step_ex(pmsz_session* S, int64_t max_rounds, int32_t flags) {
   a.trace = nullptr;
   a.stop_on_done = (flags & PMSZ_STEP_STOP_ON_DONE) ? 1 : 0;
   a.stop_host = S->stop_word;
+  a.tail_ok = 0;  // a step's launches end on the host's stop words and round budget
   // a stop requested before this launch is spent (the host's store is
   // ordered before the launch that reads the word)
   __atomic_store_n(S->stop_word, 0u, __ATOMIC_RELEASE);

@@ -56,6 +56,16 @@ __device__ __forceinline__ unsigned long long relaxed_load(gptr<const unsigned l
 __device__ __forceinline__ void relaxed_add(gptr<unsigned long long> p, unsigned long long v) {
   __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+// A load of data that another compute unit may have written since this unit
+// last invalidated its cache.  CO (the tail rounds of k_tail, below): a
+// device-scope load, which skips the unit's cache and reads the XCD's L2 where
+// every unit's stores and atomics land; otherwise a plain load (a grid
+// barrier's acquire has invalidated the unit's cache).
+template <bool CO, class V>
+__device__ __forceinline__ V ld(gptr<const V> p) {
+  if constexpr (CO) return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  else return *p;
+}
 
 __device__ __forceinline__ void grid_sync(EngineCtl* ctl, unsigned nblocks, unsigned& gen) {
   __syncthreads();
@@ -113,6 +123,7 @@ struct XcdBar {
   unsigned members;  // blocks of the launch on it
   unsigned nx;       // XCDs with blocks of the launch
   unsigned cu;       // compute-unit slot: XCD x 256 + HW_ID bits 15:8
+  unsigned rank;     // this block's index among the members (k_tail)
 };
 
 __device__ __forceinline__ unsigned xcd_of_block() {
@@ -175,12 +186,40 @@ __device__ __forceinline__ void xcd_sync(EngineCtl* ctl, const XcdBar& xb, unsig
   __syncthreads();
 }
 
+// Barrier of a sparse tail round (tail_round): only the blocks of one XCD
+// are left, and every load of data that another unit may have written is a
+// device-scope one (ld<true>), which skips the unit's cache and reads the
+// XCD's L2.  The barrier then needs neither an L2 write-back nor an
+// invalidate, only each wave's stores in L2 before its block arrives.  (An
+// agent-scope acquire also drops the XCD's L2: every line read after it came
+// from HBM at about 2 us, against about 0.12 us for a device-scope load that
+// hits the L2, measured between two units of one XCD.)
+__device__ __noinline__ void tail_sync(EngineCtl* ctl, const XcdBar& xb, unsigned& gen) {
+  __builtin_amdgcn_s_waitcnt(0);  // this wave's stores are complete in L2
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned target = gen + 1;
+    const unsigned arrived = __hip_atomic_fetch_add(&ctl->xbar[xb.xcc].v, 1u, __ATOMIC_RELAXED,
+                                                    __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == xb.members - 1) {
+      __hip_atomic_store(&ctl->xbar[xb.xcc].v, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_s_waitcnt(0);  // the reset lands before any block passes
+      __hip_atomic_store(&ctl->bar_gen.v, target, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      spin_until(ctl, &ctl->bar_gen.v, target);
+    }
+    gen = target;
+  }
+  __syncthreads();
+}
+
 // Census of the launch's blocks per XCD (the XCD counters start cleared),
 // ending with a full barrier.
 __device__ __forceinline__ XcdBar xcd_census(EngineCtl* ctl, unsigned& gen) {
   XcdBar xb;
   xb.xcc = xcd_of_block();
   xb.cu = cu_of_block(xb.xcc);
+  xb.rank = 0;
   if (threadIdx.x == 0)
     __hip_atomic_fetch_add(&ctl->census[xb.xcc], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   grid_sync(ctl, gridDim.x, gen);
@@ -195,6 +234,52 @@ __device__ __forceinline__ XcdBar xcd_census(EngineCtl* ctl, unsigned& gen) {
 __device__ __forceinline__ bool engine_failed(EngineCtl* ctl) {
   return __hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
 }
+
+// Census of a tail launch (k_tail): block 0 publishes its XCD (the lead,
+// where the tail runs), every block reads it and counts itself; the blocks of
+// other XCDs then leave, and the lead's blocks wait until every block of the
+// launch has counted itself, which fixes their number and their ranks (the
+// counters start cleared).  Spins are bounded like the barriers'.  Returns
+// false for a block that leaves.
+__device__ __forceinline__ bool tail_census(EngineCtl* ctl, XcdBar& xb) {
+  __shared__ unsigned s_info[3];  // lead, rank, members
+  if (threadIdx.x == 0) {
+    const unsigned xcc = xcd_of_block();
+    if (blockIdx.x == 0)
+      __hip_atomic_store(&ctl->lead.v, xcc + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long t0 = wall_clock64();
+    unsigned lead1;
+    while ((lead1 = relaxed_load(&ctl->lead.v)) == 0u) {
+      __builtin_amdgcn_s_sleep(1);
+      if (wall_clock64() - t0 > 400000000ull) {  // 100 MHz counter: 4 s
+        __hip_atomic_store(&ctl->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        break;
+      }
+    }
+    const unsigned lead = lead1 - 1u;
+    unsigned rank = ~0u, members = 0u;
+    if (lead1 != 0u && xcc == lead)
+      rank = __hip_atomic_fetch_add(&ctl->census[lead], 1u, __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT);
+    // counted after the census word (whose add has returned)
+    __hip_atomic_fetch_add(&ctl->arrived.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (rank != ~0u) {
+      spin_until(ctl, &ctl->arrived.v, gridDim.x);
+      members = relaxed_load(&ctl->census[lead]);
+    }
+    s_info[0] = xcc;
+    s_info[1] = rank;
+    s_info[2] = members;
+  }
+  __syncthreads();
+  xb.xcc = s_info[0];
+  xb.rank = s_info[1];
+  xb.members = s_info[2];
+  xb.nx = 1;
+  xb.cu = 0;
+  return xb.rank != ~0u && !engine_failed(ctl);
+}
+
 
 // Field owning global tile / segment v (fields sorted by base).
 __device__ __forceinline__ int field_of_tile(const FieldDesc* fd, int nf, int64_t v) {
@@ -248,18 +333,19 @@ __device__ __forceinline__ FieldIter next_state(FieldIter s, const CtrSum& c,
 
 // Whole-struct copies through global-space pointers, member by member (the
 // implicit copy operations take generic references).
+template <bool CO = false>
 __device__ __forceinline__ FieldIter load_iter(gptr<const FieldIter> p) {
   FieldIter r;
-  r.k = p->k;
-  r.steps = p->steps;
-  r.mism0 = p->mism0;
-  r.flagged_final = p->flagged_final;
-  r.stalled_final = p->stalled_final;
-  r.swept = p->swept;
-  r.status = p->status;
-  r.done = p->done;
-  r.started = p->started;
-  r.pad = p->pad;
+  r.k = ld<CO>(&p->k);
+  r.steps = ld<CO>(&p->steps);
+  r.mism0 = ld<CO>(&p->mism0);
+  r.flagged_final = ld<CO>(&p->flagged_final);
+  r.stalled_final = ld<CO>(&p->stalled_final);
+  r.swept = ld<CO>(&p->swept);
+  r.status = ld<CO>(&p->status);
+  r.done = ld<CO>(&p->done);
+  r.started = ld<CO>(&p->started);
+  r.pad = ld<CO>(&p->pad);
   return r;
 }
 __device__ __forceinline__ void store_iter(gptr<FieldIter> p, const FieldIter& s) {
@@ -290,57 +376,63 @@ __device__ __forceinline__ int ctr_slot() { return (int)(blockIdx.x % (unsigned)
 // the unit's cache serve the blocks that share it (every block of the grid
 // reads the same few lines after each barrier, and one L2 channel serves
 // each line).
+template <bool CO = false>
 __device__ __forceinline__ CtrSum load_ctr(gptr<const FieldCtr> c) {
   CtrSum r{0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
   for (int k = 0; k < kCtrSlots; ++k) {
     const gptr<const CtrSlot> x = &c->s[k];
-    r.mism += x->mism;
-    r.nflag += x->nflag;
-    r.at_lb += x->at_lb;
-    r.bad_nf += x->bad_nf;
-    r.bad_b += x->bad_b;
-    r.swept += x->swept;
-    r.nlist += x->nlist;
+    r.mism += ld<CO>(&x->mism);
+    r.nflag += ld<CO>(&x->nflag);
+    r.at_lb += ld<CO>(&x->at_lb);
+    r.bad_nf += ld<CO>(&x->bad_nf);
+    r.bad_b += ld<CO>(&x->bad_b);
+    r.swept += ld<CO>(&x->swept);
+    r.nlist += ld<CO>(&x->nlist);
   }
   return r;
 }
 // Mismatches of a finished round (the apply pass's only test in later rounds).
+template <bool CO = false>
 __device__ __forceinline__ unsigned long long load_mism(gptr<const FieldCtr> c) {
   unsigned long long m = 0;
 #pragma unroll
-  for (int k = 0; k < kCtrSlots; ++k) m += c->s[k].mism;
+  for (int k = 0; k < kCtrSlots; ++k) m += ld<CO>(&c->s[k].mism);
   return m;
 }
 
 // Round totals over all fields, summed over the slots (read after the barrier
 // that completed them, like the counters).
+template <bool CO = false>
 __device__ __forceinline__ RoundTot load_tot(const EngineCtl* ctl, int q) {
   RoundTot r{0, 0, 0, 0, {0, 0, 0, 0}};
   const gptr<const RoundTot> t = as_global(&ctl->tot[q][0]);
 #pragma unroll
   for (int k = 0; k < kCtrSlots; ++k) {
-    r.edits += t[k].edits;
-    r.swept += t[k].swept;
-    r.sparse += t[k].sparse;
-    r.flagged += t[k].flagged;
+    r.edits += ld<CO>(&t[k].edits);
+    r.swept += ld<CO>(&t[k].swept);
+    r.sparse += ld<CO>(&t[k].sparse);
+    r.flagged += ld<CO>(&t[k].flagged);
   }
   return r;
 }
+template <bool CO = false>
 __device__ __forceinline__ unsigned long long load_edits(const EngineCtl* ctl, int q) {
   const gptr<const RoundTot> t = as_global(&ctl->tot[q][0]);
   unsigned long long e = 0;
 #pragma unroll
-  for (int k = 0; k < kCtrSlots; ++k) e += t[k].edits;
+  for (int k = 0; k < kCtrSlots; ++k) e += ld<CO>(&t[k].edits);
   return e;
 }
 
 // State of a field at the start of round E.
+template <bool CO = false>
 __device__ __forceinline__ FieldIter state_at(const FieldDesc& d, unsigned long long E,
                                               unsigned long long E0) {
   const gptr<const FieldState> st = as_global((const FieldState*)d.st);
-  if (E == E0) return load_iter(&st->s[E & 1]);
-  return next_state(load_iter(&st->s[(E - 1) & 1]), load_ctr(&st->c[(E - 1) % 3]), d.max_iters);
+  if (E == E0) return load_iter<CO>(&st->s[E & 1]);
+  return next_state(load_iter<CO>(&st->s[(E - 1) & 1]), load_ctr<CO>(&st->c[(E - 1) % 3]),
+                    d.max_iters);
 }
 
 // Tiles containing a vertex within one step of target t (Freudenthal
@@ -373,6 +465,7 @@ __device__ __forceinline__ TileBox box_of(const TileGeo& G, int32_t t) {
 // eight corner combinations, duplicates included; all eight bytes are loaded
 // before any store, so the loads overlap instead of forming a chain of
 // dependent round trips (a store may alias a later load of the same array).
+template <bool CO = false>
 __device__ __forceinline__ void mark_box(const FieldDesc& d, const TileBox& b, gptr<uint8_t> nxt) {
   int32_t idx[8];
   uint8_t cur[8];
@@ -381,7 +474,7 @@ __device__ __forceinline__ void mark_box(const FieldDesc& d, const TileBox& b, g
     const int32_t bx = (k & 1) ? b.x1 : b.x0, by = (k & 2) ? b.y1 : b.y0,
                   bz = (k & 4) ? b.z1 : b.z0;
     idx[k] = bx + d.geo.tiles_x * (by + d.geo.tiles_y * bz);
-    cur[k] = nxt[idx[k]];
+    cur[k] = ld<CO>(nxt + idx[k]);
   }
 #pragma unroll
   for (int k = 0; k < 8; ++k)
@@ -424,6 +517,7 @@ __device__ __forceinline__ int block_scan(int v, int* sh, int* total) {
 // Examinations needed by round E of a field in a sparse round, or -1 when the
 // round sweeps its active tiles (first round, or a slot's slice of the target
 // list overflowed).  cnt (nullable) receives the targets listed per slot.
+template <bool CO = false>
 __device__ __forceinline__ long long sparse_items(const FieldDesc& d, const FieldIter& s,
                                                   unsigned long long E, uint32_t* cnt = nullptr) {
   if (!s.started || s.done) return -1;
@@ -433,7 +527,7 @@ __device__ __forceinline__ long long sparse_items(const FieldDesc& d, const Fiel
   bool over = false;
 #pragma unroll
   for (int k = 0; k < kCtrSlots; ++k) {
-    const unsigned long long nk = c->s[k].nlist;
+    const unsigned long long nk = ld<CO>(&c->s[k].nlist);
     over |= nk > cap;
     n += nk;
     if (cnt) cnt[k] = (uint32_t)nk;
@@ -451,7 +545,7 @@ __device__ __forceinline__ int32_t code_offset(const TileGeo& G, int code) {
 
 // Directions of g at vertex v from gathered values: the same upper / lower
 // box pair merges, in the same order, as the tile marches.
-template <class T>
+template <class T, bool CO = false>
 __device__ __forceinline__ void gather_dirs(const TileGeo& G, gptr<const T> g, int32_t v,
                                             int32_t x, int32_t y, int32_t z, int& ca, int& cd) {
   const T nan = T(__builtin_nan(""));
@@ -460,13 +554,13 @@ __device__ __forceinline__ void gather_dirs(const TileGeo& G, gptr<const T> g, i
     const bool ym = y > 0, yp = y + 1 < G.ny, zm = z > 0, zp = z + 1 < G.nz;
     auto up = [&](int bx, int by, int bz) {
       const bool ok = (!bx || xp) && (!by || yp) && (!bz || zp);
-      const T val = ok ? g[v + bx + by * G.nx + bz * G.sxy] : nan;
+      const T val = ok ? ld<CO>(g + (v + bx + by * G.nx + bz * G.sxy)) : nan;
       return ext_of(val, bx | (by << 1) | (bz << 2));
     };
     auto dn = [&](int bx, int by, int bz) {  // vertex v - (1-bx, 1-by, 1-bz)
       const int mx = 1 - bx, my = 1 - by, mz = 1 - bz, m = mx | (my << 1) | (mz << 2);
       const bool ok = (!mx || xm) && (!my || ym) && (!mz || zm);
-      const T val = ok ? g[v - mx - my * G.nx - mz * G.sxy] : nan;
+      const T val = ok ? ld<CO>(g + (v - mx - my * G.nx - mz * G.sxy)) : nan;
       return ext_of(val, m ? (8 | m) : 0);
     };
     const Ext<T> U = merge_up(merge_up(merge_up(up(0, 0, 0), up(1, 0, 0)),
@@ -484,12 +578,12 @@ __device__ __forceinline__ void gather_dirs(const TileGeo& G, gptr<const T> g, i
     const bool ym = y > 0, yp = y + 1 < G.ny;
     auto up = [&](int bx, int by) {
       const bool ok = (!bx || xp) && (!by || yp);
-      return ext_of(ok ? g[v + bx + by * G.nx] : nan, bx | (by << 1));
+      return ext_of(ok ? ld<CO>(g + (v + bx + by * G.nx)) : nan, bx | (by << 1));
     };
     auto dn = [&](int bx, int by) {
       const int mx = 1 - bx, my = 1 - by, m = mx | (my << 1);
       const bool ok = (!mx || xm) && (!my || ym);
-      return ext_of(ok ? g[v - mx - my * G.nx] : nan, m ? (8 | m) : 0);
+      return ext_of(ok ? ld<CO>(g + (v - mx - my * G.nx)) : nan, m ? (8 | m) : 0);
     };
     const Ext<T> U = merge_up(merge_up(up(0, 0), up(1, 0)), merge_up(up(0, 1), up(1, 1)));
     const Ext<T> L = merge_dn(merge_dn(dn(0, 0), dn(1, 0)), merge_dn(dn(0, 1), dn(1, 1)));
@@ -508,7 +602,7 @@ struct Exam {
   unsigned n;      // mismatches found (0, 1 or 2)
 };
 
-template <class T>
+template <class T, bool CO = false>
 __device__ __forceinline__ Exam sparse_examine(const FieldDesc& d, uint32_t m,
                                                const uint32_t* cnt) {
   const TileGeo& G = d.geo;
@@ -525,7 +619,7 @@ __device__ __forceinline__ Exam sparse_examine(const FieldDesc& d, uint32_t m,
     kk -= past ? ci : 0u;
     at += past ? slice : 0u;
   }
-  const int32_t t = (int32_t)as_global(d.list)[at + kk];
+  const int32_t t = (int32_t)ld<CO>(as_global((const uint32_t*)d.list) + (at + kk));
   // the vertex itself, then its neighbours: 3D codes 1..7, 9..15; 2D 1..3, 9..11
   const int code = three ? (j < 8 ? (int)j : (int)j + 1) : (j < 4 ? (int)j : (int)j + 5);
   // the neighbour's offset
@@ -541,7 +635,7 @@ __device__ __forceinline__ Exam sparse_examine(const FieldDesc& d, uint32_t m,
   if (X < G.cx0 || X >= G.cx1 || Y < G.cy0 || Y >= G.cy1 || Z < G.cz0 || Z >= G.cz1) return ex;
   const int32_t v = t + code_offset(G, code);
   int ca, cd;
-  gather_dirs<T>(G, as_global((const T*)d.g), v, X, Y, Z, ca, cd);
+  gather_dirs<T, CO>(G, as_global((const T*)d.g), v, X, Y, Z, ca, cd);
   const int d8 = as_global(d.dirs)[v];
   const int fa = d8 & 15, fd = d8 >> 4;
   // targets are neighbours of v, inside the box for directions made by the
@@ -553,7 +647,7 @@ __device__ __forceinline__ Exam sparse_examine(const FieldDesc& d, uint32_t m,
       ex.ta = tt;
       if (d.prop) {
         const int32_t c = v + code_offset(G, fa);
-        propose<T>(d.prop, tt, c, g[c]);
+        propose<T>(d.prop, tt, c, ld<CO>(g + c));
       }
     }
     ++ex.n;
@@ -564,7 +658,7 @@ __device__ __forceinline__ Exam sparse_examine(const FieldDesc& d, uint32_t m,
       ex.td = tt;
       if (d.prop) {
         const int32_t r = v + code_offset(G, cd);
-        propose<T>(d.prop, tt, r, g[r]);
+        propose<T>(d.prop, tt, r, ld<CO>(g + r));
       }
     }
     ++ex.n;
@@ -661,7 +755,7 @@ constexpr int kEditUnroll = 2;    // targets per thread with loads in flight tog
 // Apply pass over bitmap words [w0, w1) of one field: the block reads the
 // segment in one sweep (16 words per thread), compacts the set bits into an
 // LDS list, and edits the listed targets with all threads at once.
-template <class T>
+template <class T, bool CO = false>
 __device__ __forceinline__ void apply_segment(const FieldDesc& d, int32_t w0, int32_t w1,
                                               bool edit, gptr<uint8_t> nxt, uint32_t* list,
                                               int* scan, long long* lbase_sh, gptr<FieldCtr> cq,
@@ -682,7 +776,7 @@ __device__ __forceinline__ void apply_segment(const FieldDesc& d, int32_t w0, in
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
     const int32_t w = w0 + tid + 256 * k;
-    wv[k] = bm[w < w1 ? w : w0];
+    wv[k] = ld<CO>(bm + (w < w1 ? w : w0));
     if (w >= w1) wv[k] = 0u;
     cnt += __popc(wv[k]);
   }
@@ -734,7 +828,7 @@ __device__ __forceinline__ void apply_segment(const FieldDesc& d, int32_t w0, in
       }
 #pragma unroll
       for (int u = 0; u < kEditUnroll; ++u) {
-        gt[u] = g[t[u]];
+        gt[u] = ld<CO>(g + t[u]);
         ft[u] = f[t[u]];
       }
 #pragma unroll
@@ -749,7 +843,7 @@ __device__ __forceinline__ void apply_segment(const FieldDesc& d, int32_t w0, in
           using K = decltype(prop_key(gt[u]));
           const gptr<K> slot = (gptr<K>)d.prop + t[u];
           if (above && edit) {
-            const T pv = prop_value(*slot);
+            const T pv = prop_value(ld<CO>(slot));
             g[t[u]] = pv > lb ? pv : lb;
           }
           *slot = ~K(0);
@@ -770,7 +864,7 @@ __device__ __forceinline__ void apply_segment(const FieldDesc& d, int32_t w0, in
           const TileBox b = box_of(d.geo, t[u]);
           if (b.x0 != last.x0 || b.x1 != last.x1 || b.y0 != last.y0 || b.y1 != last.y1 ||
               b.z0 != last.z0 || b.z1 != last.z1) {
-            mark_box(d, b, nxt);
+            mark_box<CO>(d, b, nxt);
             last = b;
           }
         }
@@ -895,7 +989,7 @@ __device__ void detect_tiles(const EngineArgs& a, TileLds<T>& sm, unsigned long 
 // Apply pass of a round (parity p, counter set q) on one unit: segment
 // u >> plog of the batch's flag bitmaps, part u & (2^plog - 1) of it.  Every
 // thread of the block takes part (block reductions inside).
-template <class T>
+template <class T, bool CO = false>
 __device__ __forceinline__ void apply_unit(const EngineArgs& a, int64_t u, int plog, int p, int q,
                                            uint32_t* s_list, int* s_scan, long long* s_lbase,
                                            unsigned long long* red) {
@@ -906,13 +1000,13 @@ __device__ __forceinline__ void apply_unit(const EngineArgs& a, int64_t u, int p
   const int fi = field_of_seg(a.fd, a.nf, sg);
   const FieldDesc& d = a.fd[fi];
   // the state at the start of the round (persisted before this pass)
-  const FieldIter s = load_iter(&as_global(d.st)->s[p]);
+  const FieldIter s = load_iter<CO>(&as_global(d.st)->s[p]);
   const gptr<FieldCtr> cq = &as_global(d.st)->c[q];
   const gptr<uint8_t> nxt = as_global(d.act) + (p ^ 1) * tile_count(d.geo);
-  const unsigned long long mism = load_mism(cq);
+  const unsigned long long mism = load_mism<CO>(cq);
   bool bad = false;
   if (!s.started) {
-    const CtrSum cs = load_ctr(cq);
+    const CtrSum cs = load_ctr<CO>(cq);
     bad = cs.bad_nf || cs.bad_b;
   }
   if (s.done || bad || mism == 0) return;
@@ -922,8 +1016,8 @@ __device__ __forceinline__ void apply_unit(const EngineArgs& a, int64_t u, int p
   const int32_t w1 = (w0 + span < d.words) ? w0 + span : (int32_t)d.words;
   if (w0 >= w1) return;  // a part past the end of the field's last segment
   unsigned long long nflag = 0, at_lb = 0, edits = 0;
-  apply_segment<T>(d, w0, w1, edit, nxt, s_list, s_scan, s_lbase, cq, as_global(d.list), nflag,
-                   at_lb, edits);
+  apply_segment<T, CO>(d, w0, w1, edit, nxt, s_list, s_scan, s_lbase, cq, as_global(d.list),
+                       nflag, at_lb, edits);
   // a segment holds at most 128K vertices: the three counts pack into
   // 21-bit fields of one word for a single block reduction
   const unsigned long long tot =
@@ -938,6 +1032,51 @@ __device__ __forceinline__ void apply_unit(const EngineArgs& a, int64_t u, int p
     }
     if (al_) relaxed_add(&cq->s[slot].at_lb, al_);
     if (ed_) atomicAdd(&ctl->tot[q][slot].edits, ed_);
+  }
+}
+
+// Block 0 at the start of round E: persist the field states of round E, clear
+// the next-but-one counters; a field finished at E (stop_on_done) or the
+// host's request ends the launch after this round (every block reads the word
+// after the detect barrier).  CO as for ld.
+template <bool CO>
+__device__ __forceinline__ void persist_round(const EngineArgs& a, unsigned long long E,
+                                              unsigned long long E0, int p, int qn) {
+  const int tid = threadIdx.x;
+  EngineCtl* ctl = a.ctl;
+  bool stop = false;
+  for (int fi = tid; fi < a.nf; fi += 256) {
+    const FieldDesc& d = a.fd[fi];
+    const gptr<FieldState> st = as_global(d.st);
+    bool done;
+    if (E > E0) {
+      const FieldIter s = state_at<CO>(d, E, E0);
+      store_iter(&st->s[p], s);
+      stop |= a.stop_on_done && s.done && !ld<CO>(&st->s[p ^ 1].done);
+      done = s.done;
+    } else {
+      done = ld<CO>(&st->s[p].done);
+      // a later launch of a step whose tile detection ran as sweeps: a
+      // field done at its start finished in the step's earlier launch
+      stop |= a.stop_on_done && a.tiles_swept && done;
+    }
+    // the host asked for the step to end once a field is done (every
+    // field of a step was running when it began)
+    if (done && a.stop_host &&
+        __hip_atomic_load(a.stop_host, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) ==
+            kStopWhenDone)
+      stop = true;
+    clear_ctr(&st->c[qn]);
+  }
+  if (tid == 0 && a.stop_host &&
+      __hip_atomic_load(a.stop_host, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) == kStopNow)
+    stop = true;
+  if (stop) __hip_atomic_store(&ctl->stop.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (tid < kCtrSlots) {
+    ctl->tot[qn][tid].edits = 0;
+    ctl->tot[qn][tid].swept = 0;
+    ctl->tot[qn][tid].sparse = 0;
+    ctl->tot[qn][tid].flagged = 0;
   }
 }
 
@@ -988,6 +1127,127 @@ __global__ __launch_bounds__(256) void k_first_round_end(EngineArgs a) {
   }
 }
 
+// LDS of k_tail that a tail round uses.
+struct RoundLds {
+  long long* pre;           // [256] prefix sums of the fields' examinations
+  uint32_t* slot;           // [256 * kCtrSlots] targets listed per slot, per field
+  uint32_t* list;           // [kApplyCap] targets of an apply pass
+  int* scan;                // [4]
+  long long* lbase;         // [1]
+  unsigned long long* red;  // [4]
+  uint16_t* units;          // [256] marked segments of a batch
+};
+
+// One sparse round of the tail (k_tail), on the blocks of the lead XCD
+// (rank, members): detection of the listed targets' neighbours, the apply
+// pass over the segments that detection marked, and their barriers
+// (tail_sync), with every load of data that another unit may have written a
+// device-scope one.  Returns 0 when the round ran and the loop goes on, 1
+// when the loop ends after it, and 2, before anything has run, when some
+// field sweeps tiles in this round (the engine takes that round).  The tail
+// holds at most 256 fields.
+template <class T>
+__device__ __forceinline__ int tail_round(const EngineArgs& a, const XcdBar& xb, unsigned& gen,
+                                       unsigned long long& E, unsigned long long E0,
+                                       const RoundLds L) {
+  const int tid = threadIdx.x;
+  EngineCtl* ctl = a.ctl;
+  const int p = (int)(E & 1);
+  const int q = (int)(E % 3), qn = (int)((E + 1) % 3);
+  const bool tracer = a.trace && blockIdx.x == 0 && tid == 0;
+  long long items = 0;
+  int sweeps = 0;
+  if (tid < a.nf) {
+    const FieldDesc& d = a.fd[tid];
+    const FieldIter s = state_at<true>(d, E, E0);
+    items = sparse_items<true>(d, s, E, L.slot + tid * kCtrSlots);
+    if (items < 0) {
+      sweeps = !s.done;
+      items = 0;
+    }
+  }
+  if (__syncthreads_or(sweeps)) return 2;
+  if (tracer && E < kTraceRounds) a.trace[kTraceSlots * E] = wall_clock64();
+  if (blockIdx.x == 0) {
+    persist_round<true>(a, E, E0, p, qn);
+    if (tid < a.nf && items > 0) {
+      relaxed_add(&as_global(a.fd[tid].st)->c[q].s[0].swept, (unsigned long long)items);
+      atomicAdd(&ctl->tot[q][0].swept, (unsigned long long)items);
+      atomicAdd(&ctl->tot[q][0].sparse, (unsigned long long)items);
+    }
+  }
+  // ---- detect: the examinations of all fields form one index space
+  const long long total = block_prefix(items, L.pre);
+  {
+    FieldAcc mism;
+    auto mism_ptr = [&](int f) { return &as_global(a.fd[f].st)->c[q].s[ctr_slot()].mism; };
+    for (long long m = (long long)xb.rank * 256 + tid; m < total;
+         m += (long long)xb.members * 256) {
+      const int fx = prefix_find(L.pre, a.nf, m);
+      const Exam ex = sparse_examine<T, true>(
+          a.fd[fx], (uint32_t)(m - (fx ? L.pre[fx - 1] : 0)), L.slot + fx * kCtrSlots);
+      acc_add(mism, fx, ex.n, mism_ptr);
+      // the flags, and the marks of their segments for the apply pass below
+      const gptr<uint32_t> bm = as_global(a.fd[fx].bm);
+      const gptr<uint8_t> mk = as_global(a.fd[fx].marks);
+      if (ex.ta >= 0) {
+        __hip_atomic_fetch_or(bm + (ex.ta >> 5), 1u << (ex.ta & 31), __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_AGENT);
+        mk[ex.ta >> 17] = 1;
+      }
+      if (ex.td >= 0) {
+        __hip_atomic_fetch_or(bm + (ex.td >> 5), 1u << (ex.td & 31), __ATOMIC_RELAXED,
+                              __HIP_MEMORY_SCOPE_AGENT);
+        mk[ex.td >> 17] = 1;
+      }
+    }
+    acc_flush(mism, mism_ptr, L.scan, L.red);
+  }
+  tail_sync(ctl, xb, gen);
+  if (engine_failed(ctl)) return 1;
+  // written by block 0 before the barrier above
+  const bool stop_here =
+      __hip_atomic_load(&ctl->stop.v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
+  if (tracer && E < kTraceRounds) a.trace[kTraceSlots * E + 1] = wall_clock64();
+  // ---- apply: the block reads the marks of its segments 256 at a time,
+  // clears them, and takes the marked ones whole
+  for (int64_t base = xb.rank; base < a.total_segs; base += (int64_t)xb.members * 256) {
+    const int64_t mine = base + (int64_t)tid * xb.members;
+    int take = 0;
+    if (mine < a.total_segs) {
+      const FieldDesc& d = a.fd[field_of_seg(a.fd, a.nf, mine)];
+      const gptr<uint8_t> mk = as_global(d.marks) + (mine - d.seg_base);
+      if (ld<true>(mk)) {
+        *mk = 0;
+        take = 1;
+      }
+    }
+    int n_take = 0;
+    const int pos = block_scan(take, L.scan, &n_take);
+    if (take) L.units[pos] = (uint16_t)tid;
+    __syncthreads();
+    for (int j = 0; j < n_take; ++j) {
+      const int64_t u = base + (int64_t)__builtin_amdgcn_readfirstlane(L.units[j]) * xb.members;
+      apply_unit<T, true>(a, u, 0, p, q, L.list, L.scan, L.lbase, L.red);
+    }
+    __syncthreads();  // units is rewritten by the next batch
+  }
+  tail_sync(ctl, xb, gen);
+  if (engine_failed(ctl)) return 1;
+  if (tracer && E < kTraceRounds) {
+    unsigned long long* t = a.trace + kTraceSlots * E;
+    const RoundTot rt = load_tot<true>(ctl, q);
+    t[2] = wall_clock64();
+    t[3] = rt.swept;
+    t[4] = rt.flagged;
+    t[5] = rt.edits;
+    t[6] = rt.sparse;
+  }
+  const unsigned long long edited = load_edits<true>(ctl, q);
+  ++E;
+  return (edited == 0 || stop_here) ? 1 : 0;
+}
+
 template <class T>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 3))) void k_engine(EngineArgs a) {
   __shared__ TileLds<T> sm;
@@ -1025,6 +1285,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
   // that the grid's blocks share the segments of small fields
   int parts_log2 = 0;
   while (parts_log2 < 8 && a.total_segs << (parts_log2 + 1) <= (int64_t)G) ++parts_log2;
+  // the launch ends to hand its remaining rounds to k_tail
+  bool handoff = false;
 
   for (long long r = 0; a.max_rounds < 0 || r < a.max_rounds; ++r) {
     if (engine_failed(ctl)) break;
@@ -1032,46 +1294,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     const int q = (int)(E % 3), qn = (int)((E + 1) % 3);
     if (tracer && E < kTraceRounds) a.trace[kTraceSlots * E] = wall_clock64();
 
-    // ---- block 0: persist the state of round E, clear next-but-one counters;
-    // a field finished at E (stop_on_done) or the host's request ends the
-    // launch after this round (every block reads the word after the detect
-    // barrier)
-    if (blockIdx.x == 0) {
-      bool stop = false;
-      for (int fi = tid; fi < a.nf; fi += 256) {
-        const FieldDesc& d = a.fd[fi];
-        const gptr<FieldState> st = as_global(d.st);
-        bool done;
-        if (E > E0) {
-          const FieldIter s = state_at(d, E, E0);
-          store_iter(&st->s[p], s);
-          stop |= a.stop_on_done && s.done && !st->s[p ^ 1].done;
-          done = s.done;
-        } else {
-          done = load_iter(&st->s[p]).done;
-          // a later launch of a step whose tile detection ran as sweeps: a
-          // field done at its start finished in the step's earlier launch
-          stop |= a.stop_on_done && a.tiles_swept && done;
-        }
-        // the host asked for the step to end once a field is done (every
-        // field of a step was running when it began)
-        if (done && a.stop_host &&
-            __hip_atomic_load(a.stop_host, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) ==
-                kStopWhenDone)
-          stop = true;
-        clear_ctr(&st->c[qn]);
-      }
-      if (tid == 0 && a.stop_host &&
-          __hip_atomic_load(a.stop_host, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) == kStopNow)
-        stop = true;
-      if (stop) __hip_atomic_store(&ctl->stop.v, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (tid < kCtrSlots) {
-        ctl->tot[qn][tid].edits = 0;
-        ctl->tot[qn][tid].swept = 0;
-        ctl->tot[qn][tid].sparse = 0;
-        ctl->tot[qn][tid].flagged = 0;
-      }
-    }
+    if (blockIdx.x == 0) persist_round<false>(a, E, E0, p, qn);
 
     // ---- detect ------------------------------------------------------------
     // Sparse rounds first: the examinations of up to 256 fields at a time form
@@ -1166,6 +1389,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     const unsigned long long edited = load_edits(ctl, q);
     ++E;
     if (edited == 0 || stop_here) break;
+    // the next round examines at most 15 neighbours per edit: few enough for
+    // the blocks of one XCD, and few enough segments to mark for its apply
+    // pass, and k_tail takes the rest of the loop there
+    if (a.tail_ok && a.nf <= 256 &&
+        edited * 15ull <= (unsigned long long)(kTailGrid / 8) * 256ull * kTailExams &&
+        (edited <= (unsigned long long)kTailSegs || a.total_segs <= kTailSegs)) {
+      handoff = true;
+      break;
+    }
   }
   // persist the state at the start of the next round, and gather it
   if (blockIdx.x == 0 && !engine_failed(ctl)) {
@@ -1178,6 +1410,65 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(T) =
     if (tid == 0) {
       ctl->epoch = E;
       ctl->rounds = E - E0;
+      ctl->handoff = handoff ? kHandToTail : 0;
+    }
+    // k_tail's census starts cleared (the XCD arrival counters are cleared
+    // already: each barrier's last arrival resets its XCD's)
+    if (handoff) {
+      if (tid < kXcdSlots) ctl->census[tid] = 0u;
+      if (tid == 0) {
+        ctl->lead.v = 0u;
+        ctl->arrived.v = 0u;
+      }
+    }
+  }
+}
+
+// The tail of the correction loop (kHandToTail): the sparse rounds after the
+// engine launch that handed them over, on the blocks of one XCD (tail_round),
+// until every field is done, a round needs tile sweeps (kHandToEngine: the
+// host launches the engine again), or a barrier times out.  Launched after
+// every engine launch that may hand over; without a handover it ends at once.
+template <class T>
+__global__ __launch_bounds__(256) void k_tail(EngineArgs a) {
+  __shared__ long long s_pre[256];
+  __shared__ uint32_t s_slot[256 * kCtrSlots];
+  __shared__ uint32_t s_list[kApplyCap];
+  __shared__ int s_scan[4];
+  __shared__ long long s_lbase;
+  __shared__ unsigned long long red[4];
+  __shared__ uint16_t s_units[256];
+  EngineCtl* ctl = a.ctl;
+  if (ctl->handoff != kHandToTail) return;
+  XcdBar xb;
+  if (!tail_census(ctl, xb)) return;
+  unsigned gen = relaxed_load(&ctl->bar_gen.v);
+  const unsigned long long E0 = ctl->epoch;
+  unsigned long long E = E0;
+  RoundLds L;
+  L.pre = s_pre;
+  L.slot = s_slot;
+  L.list = s_list;
+  L.scan = s_scan;
+  L.lbase = &s_lbase;
+  L.red = red;
+  L.units = s_units;
+  int rc = 0;
+  while (!engine_failed(ctl) && (rc = tail_round<T>(a, xb, gen, E, E0, L)) == 0) {
+  }
+  // persist the state at the start of the next round, and gather it
+  if (blockIdx.x == 0 && !engine_failed(ctl)) {
+    const int tid = threadIdx.x;
+    for (int fi = tid; fi < a.nf; fi += 256) {
+      const FieldDesc& d = a.fd[fi];
+      const FieldIter s = state_at<true>(d, E, E0);
+      if (E > E0) store_iter(&as_global(d.st)->s[E & 1], s);
+      if (a.out) a.out[fi] = s;
+    }
+    if (tid == 0) {
+      ctl->epoch = E;
+      ctl->rounds = E - E0;
+      ctl->handoff = rc == 2 ? kHandToEngine : 0;
     }
   }
 }
@@ -1381,6 +1672,21 @@ static hipError_t launch_t(const EngineArgs& a, hipStream_t s, int* grid_out) {
 hipError_t engine_launch(int dtype, const EngineArgs& a, hipStream_t s, int* grid_out) {
   if (dtype == PMSZ_F32) return launch_t<float>(a, s, grid_out);
   return launch_t<double>(a, s, grid_out);
+}
+
+// kTailGrid blocks, all resident (cooperative); an engine launch that hands
+// over leaves the census and barrier words of the tail cleared.
+template <class T>
+static hipError_t tail_t(const EngineArgs& a, hipStream_t s) {
+  EngineArgs copy = a;
+  void* args[] = {&copy};
+  return hipLaunchCooperativeKernel((const void*)k_tail<T>, dim3(kTailGrid), dim3(256), args, 0,
+                                    s);
+}
+
+hipError_t engine_tail(int dtype, const EngineArgs& a, hipStream_t s) {
+  if (dtype == PMSZ_F32) return tail_t<float>(a, s);
+  return tail_t<double>(a, s);
 }
 
 }  // namespace pmsz

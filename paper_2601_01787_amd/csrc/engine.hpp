@@ -59,6 +59,8 @@ struct FieldDesc {
                       // (act[p * tiles + tile])
   uint32_t* list;     // targets of the last apply pass (list_cap entries, in
                       // kCtrSlots slices of list_cap / kCtrSlots, one per slot)
+  uint8_t* marks;     // per apply segment: a tail round's examination flagged a
+                      // vertex in it (set by detect, cleared by apply)
   void* prop;         // targeted edit: per-vertex proposal keys; nullptr for
                       // the halving edit
   TileGeo geo;
@@ -102,11 +104,13 @@ struct EngineCtl {
   unsigned long long epoch;     // rounds run since the workspace was initialised
   unsigned long long rounds;    // rounds run by the last launch
   int error;                    // a grid barrier timed out
-  int pad;
+  int handoff;                  // how the last launch ended: kHandToTail, kHandToEngine, 0
   // per-launch barrier state, cleared before every launch (from xbar up to tot)
   BarWord xbar[kXcdSlots];      // arrivals per XCD
   BarWord xtop;                 // XCDs arrived
   BarWord stop;                 // nonzero: the launch ends after the current round
+  BarWord lead;                 // k_tail: 1 + the XCD of block 0, where the tail runs
+  BarWord arrived;              // k_tail: blocks that have read their XCD
   unsigned census[kXcdSlots];   // blocks of the launch on each XCD
   unsigned census_pad[64 - kXcdSlots];
   unsigned cu_claim[kCuSlots];  // last barrier generation claimed on each unit
@@ -120,6 +124,22 @@ constexpr size_t kCtlHostBytes = offsetof(EngineCtl, xbar);
 // Batches (and fields) of at least this many vertices run their tile sweeps
 // as kernels of their own (engine_sweep) where the host can place them.
 constexpr int64_t kSplitVoxels = int64_t(1) << 23;
+
+// Tail rounds: once a round edits few enough vertices that the next round's
+// examinations (at most 15 per edit) come to at most kTailExams per thread of
+// one XCD's share of the grid, the engine launch ends (handoff kHandToTail)
+// and k_tail runs the following sparse rounds on the blocks of one XCD alone.
+// They share one L2, so their barriers need no L2 write-back and their loads
+// find each other's data in that L2 instead of in HBM.  A round in which a
+// field sweeps tiles ends k_tail before it starts (handoff kHandToEngine) and
+// the host launches the engine again.
+constexpr int kTailExams = 2;
+constexpr int kTailGrid = 512;  // blocks of a tail launch (64 per XCD)
+// The tail's apply pass takes each segment marked by its detection whole: the
+// engine hands over only once a round edits at most kTailSegs vertices (or
+// the batch has at most kTailSegs segments), so that the marks stay few.
+constexpr int64_t kTailSegs = 128;
+constexpr int kHandToTail = 1, kHandToEngine = 2;
 
 // Values of the host's stop word: end the launch after the current round;
 // end it after a round that begins with a field of the launch done.
@@ -145,6 +165,8 @@ struct EngineArgs {
                          // which a field of kSplitVoxels vertices or more (among
                          // the first 256) sweeps tiles: a sweep kernel takes that
                          // round's tile detection and the next launch the rest
+  int32_t tail_ok;       // the launch may hand its last rounds to k_tail (at most
+                         // 256 fields; the host launches k_tail after it)
 };
 
 // Round trace, for the first kTraceRounds rounds since the workspace was
@@ -159,6 +181,9 @@ constexpr size_t kTraceBytes = (kTraceRounds * kTraceSlots + 1) * 8;
 
 // Host side (engine.hip).
 hipError_t engine_launch(int dtype, const EngineArgs& a, hipStream_t s, int* grid_out);
+// The tail (k_tail) after an engine launch with tail_ok set: ends at once
+// unless that launch handed its remaining rounds over.
+hipError_t engine_tail(int dtype, const EngineArgs& a, hipStream_t s);
 // Directions of f, before the engine, for every field of the device table fd
 // whose dirs_given is 0 (into its dirs); the engine then starts every field
 // from given directions.
@@ -207,9 +232,9 @@ __host__ __device__ inline int32_t list_slices(int64_t words) {
 }
 
 // Per-field workspace: [FieldState][activity bytes x 2][bitmap][target list]
-// [directions].
+// [segment marks][directions].
 struct FieldLayout {
-  size_t state, act, bm, list, dirs, total;
+  size_t state, act, bm, list, marks, dirs, total;
 };
 inline size_t ws_align(size_t v) { return (v + 255) / 256 * 256; }
 inline FieldLayout field_layout(const TileGeo& G, bool dirs_given) {
@@ -222,7 +247,8 @@ inline FieldLayout field_layout(const TileGeo& G, bool dirs_given) {
   L.act = ws_align(sizeof(FieldState));
   L.bm = L.act + ws_align(2 * max_tiles);
   L.list = L.bm + ws_align(((size_t)G.n + 31) / 32 * 4);
-  L.dirs = L.list + ws_align((size_t)list_capacity(G) * 4);
+  L.marks = L.list + ws_align((size_t)list_capacity(G) * 4);
+  L.dirs = L.marks + ws_align((size_t)((G.n + 32 * kSegWords - 1) / (32 * kSegWords)));
   L.total = L.dirs + (dirs_given ? 0 : ws_align((size_t)G.n));
   return L;
 }
