@@ -396,7 +396,8 @@ int pmsz_session_destroy(pmsz_session* s);
  * did.  Used by the benchmark for roofline figures. */
 typedef struct {
   double engine_ms;  /* the persistent correction kernel (all its launches),
-                        with round 0's apply kernel of large batches          */
+                        with round 0's apply kernel of large batches and the
+                        tail kernel                                           */
   int64_t rounds;    /* detect/apply rounds run                               */
   int64_t swept;     /* vertices examined by detect passes, all rounds        */
   int64_t edits;     /* value changes, all fields                             */
@@ -412,7 +413,12 @@ typedef struct {
   double dirs_ms;    /* directions of f, computed before the correction kernel
                         (0 when the caller gave them)                           */
   double sweep_ms;   /* the sweep kernels; engine_ms covers the engine
-                        launches only                                           */
+                        launches only (with the tail kernel's)                  */
+  int32_t tail_rounds; /* rounds run by the tail kernel: the sparse rounds
+                        after a round with few edits, on the blocks of one
+                        XCD (Sec. IV-A's loop, unchanged)                       */
+  int32_t handbacks; /* times the tail kernel stopped before a round with
+                        tile sweeps and the engine was launched again          */
 } pmsz_timing;
 int pmsz_last_timing(pmsz_timing* out);
 

@@ -88,7 +88,8 @@ class Timing(ctypes.Structure):
                 ("tiles", ctypes.c_int64), ("grid", ctypes.c_int32), ("sweeps", ctypes.c_int32),
                 ("first_round_ms", ctypes.c_double), ("detect_ms", ctypes.c_double),
                 ("apply_ms", ctypes.c_double), ("dirs_ms", ctypes.c_double),
-                ("sweep_ms", ctypes.c_double)]
+                ("sweep_ms", ctypes.c_double), ("tail_rounds", ctypes.c_int32),
+                ("handbacks", ctypes.c_int32)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

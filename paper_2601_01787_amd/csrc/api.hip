@@ -469,6 +469,7 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
   int64_t late = 0;
   unsigned long long late_round = 0;
   float late_sweep_ms = 0.f, late_engine_ms = 0.f;
+  int32_t tail_rounds = 0, handbacks = 0;
   for (;;) {
     // the staging buffer is reused for the results: the upload above is
     // stream-ordered before this copy, so it has been consumed
@@ -480,6 +481,10 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
                            sizeof(FieldIter) * (size_t)n, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (hc->error) return fail(PMSZ_ERR_DEVICE, "grid barrier timed out in the correction engine");
+    if (hc->handoff == kHandToEngine || hc->handoff == kTailDone) {
+      tail_rounds += (int32_t)hc->rounds;
+      handbacks += hc->handoff == kHandToEngine ? 1 : 0;
+    }
     if (late > 0 && timed) {
       float ms = 0.f;
       HIP_TRY(hipEventElapsedTime(&ms, tm.ev[6], tm.ev[7]));
@@ -527,6 +532,8 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
   tm.last.dirs_ms = el[0];
   tm.last.sweep_ms = el[1] + el[3] + late_sweep_ms;
   tm.last.sweeps = split ? 2 + late : 0;
+  tm.last.tail_rounds = tail_rounds;
+  tm.last.handbacks = handbacks;
   tm.last.engine_ms = el[2] + el[4] + late_engine_ms;
   tm.last.rounds = (int64_t)hc->epoch;  // the workspace starts every call at round 0
   tm.last.tiles = P.total_tiles;

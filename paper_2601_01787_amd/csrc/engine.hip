@@ -1468,7 +1468,7 @@ __global__ __launch_bounds__(256) void k_tail(EngineArgs a) {
     if (tid == 0) {
       ctl->epoch = E;
       ctl->rounds = E - E0;
-      ctl->handoff = rc == 2 ? kHandToEngine : 0;
+      ctl->handoff = rc == 2 ? kHandToEngine : kTailDone;
     }
   }
 }

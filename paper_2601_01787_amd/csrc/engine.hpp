@@ -104,7 +104,8 @@ struct EngineCtl {
   unsigned long long epoch;     // rounds run since the workspace was initialised
   unsigned long long rounds;    // rounds run by the last launch
   int error;                    // a grid barrier timed out
-  int handoff;                  // how the last launch ended: kHandToTail, kHandToEngine, 0
+  int handoff;                  // how the last launch ended: kHandToTail, kHandToEngine,
+                                // kTailDone, or 0 (an engine launch that kept its rounds)
   // per-launch barrier state, cleared before every launch (from xbar up to tot)
   BarWord xbar[kXcdSlots];      // arrivals per XCD
   BarWord xtop;                 // XCDs arrived
@@ -139,7 +140,7 @@ constexpr int kTailGrid = 512;  // blocks of a tail launch (64 per XCD)
 // engine hands over only once a round edits at most kTailSegs vertices (or
 // the batch has at most kTailSegs segments), so that the marks stay few.
 constexpr int64_t kTailSegs = 128;
-constexpr int kHandToTail = 1, kHandToEngine = 2;
+constexpr int kHandToTail = 1, kHandToEngine = 2, kTailDone = 3;
 
 // Values of the host's stop word: end the launch after the current round;
 // end it after a round that begins with a field of the launch done.

@@ -315,6 +315,47 @@ def test_later_tile_rounds_as_sweep_kernels_match_alone():
     assert sum(r["edits"] for r in rounds) == sum(st["steps_applied"] for st in stats)
 
 
+def noise_case(n, xi, seed):
+    """White noise on [0, 1] in an n^3 binary32 grid, fhat within xi of f: a
+    loop whose edits shrink slowly, round after round."""
+    rng = np.random.default_rng(seed)
+    f = rng.uniform(0, 1, size=(n, n, n)).astype(np.float32)
+    lb, ub = oracle.bounds(f, xi)
+    fhat = (f.astype(np.float64) + rng.uniform(-xi, xi, size=f.shape)).astype(np.float32)
+    return f, np.minimum(np.maximum(fhat, lb), ub), xi
+
+
+@pytest.mark.parametrize("n", [24, 40])
+def test_tail_rounds_and_handback_match_oracle(n):
+    """Once a round edits few vertices the loop goes on in the tail kernel on
+    one XCD; a tail round whose target list overflowed (a field of n^3
+    vertices lists n^3 / 256 + 1024 targets) sweeps tiles, so the tail stops
+    before it and the engine takes that round.  Either way the result is the
+    oracle's, bit for bit."""
+    f, fhat, xi = noise_case(n, 0.2, 7 + n)
+    g_ref, st_ref = oracle.correct(f, fhat, xi)
+    g, st = pmsz.correct(dev(f), dev(fhat), xi)
+    tm = pmsz.last_timing()
+    assert tm["tail_rounds"] > 0, tm
+    assert tm["handbacks"] > 0, tm
+    for k in STAT_KEYS:
+        assert st[k] == st_ref[k], (k, st, st_ref)
+    assert same_bits(host(g), g_ref)
+    rounds = pmsz.last_rounds()
+    assert len(rounds) == tm["rounds"]
+    assert sum(r["edits"] for r in rounds) == st["steps_applied"]
+
+
+def test_small_perlin_tail():
+    """The 64^3 workload hands its rounds after the first few to the tail
+    kernel and ends there."""
+    f, fhat, xi = synth.small_perlin_case()
+    g, st = pmsz.correct(f.to(DEV), fhat.to(DEV), xi)
+    tm = pmsz.last_timing()
+    assert tm["tail_rounds"] > 0 and tm["handbacks"] == 0, tm
+    assert tm["tail_rounds"] < tm["rounds"]
+
+
 def test_full_size_perlin_512():
     """512^3 binary32 Perlin (one GPU's weak-scaling share): the corrected field
     and the directions are compared through hashes the oracle wrote, and the
