@@ -66,7 +66,8 @@ def kernel_split(tm, rounds, s):
     examination; an edit reads f and g and writes g (3s).  With split sweeps
     the tile detection of rounds 0 and 1 is the sweep kernel's (two launches)
     and the rest the engine's: round 0's apply kernel and the engine launch
-    from round 1 (two launches)."""
+    from round 1 (two launches; the tail kernel's rounds, timed with the
+    engine, are counted in it)."""
     det = [r["swept"] * ((2 * s + 1) if i == 0 else (s + 1.125)) for i, r in enumerate(rounds)]
     tiles = [(r["swept"] - r["sparse"]) * ((2 * s + 1) if i == 0 else (s + 1.125))
              for i, r in enumerate(rounds)]
