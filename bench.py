@@ -212,7 +212,7 @@ def bench_batched(dev, n_fields, seed):
             "plain_ms": round(t_plain * 1e3, 2), "batched_ms": round(t_tuned * 1e3, 2),
             "speedup": round(t_plain / t_tuned, 2), "identical": bool(same),
             "max_iterations": max(s["iterations"] for s in st_batch),
-            "tiles_target": {"default": target0, "tuned": best,
+            "tiles_target": {"default": target0 or "2048/fields in [32, 256]", "tuned": best,
                              "device_ms_by_target": {k: round(v, 3) for k, v in tune_ms.items()},
                              "batched_ms_default": round(t_batch * 1e3, 2)}}
 

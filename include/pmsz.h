@@ -197,12 +197,15 @@ int pmsz_correct_batched(int32_t n, const pmsz_field* fields, void* ws, size_t w
 
 /* Tile shapes.  The correction sweeps each field in tiles of 64 x 4 columns
  * (3D) or 256-wide strips (2D) of `h` planes / rows, h between 2 and 32,
- * chosen to give about `tiles_target` tiles per field (default 2048).  The
+ * chosen to give about `tiles_target` tiles per field (without a set or
+ * tuned target: 2048 / n for a batch of n fields, between 32 and 256; 256 for
+ * a serving session's fields).  The
  * tile height changes neither results nor statistics, only speed (the
  * iteration of Sec. IV-A is the same; the tiles only decide which vertices a
  * detect pass reads).  The target is kept per (ndim, dtype) for the whole
  * process and read when a correction, batch or session field is planned.
- * pmsz_set_tiles_target: 0 restores the default.  Host-only, thread-safe.
+ * pmsz_set_tiles_target: 0 restores the default rule, which
+ * pmsz_get_tiles_target reports as 0.  Host-only, thread-safe.
  * Tune cache: when the environment variable PMSZ_TUNE_CACHE names a file,
  * the targets it records (a JSON object with the keys "2d_f32", "2d_f64",
  * "3d_f32", "3d_f64"; absent keys and unreadable or malformed files keep the

@@ -368,12 +368,14 @@ TILE_TARGETS = (32, 64, 128, 256, 512, 1024, 2048, 4096, 8192, 16384)
 
 def set_tiles_target(ndim, dtype, target):
     """Tiles-per-field target of the tile-height policy for (ndim, dtype)
-    (torch.float32 / torch.float64); 0 restores the default."""
+    (torch.float32 / torch.float64); 0 restores the default rule (2048 /
+    fields of a batch, between 32 and 256)."""
     _raise_if(load().pmsz_set_tiles_target(int(ndim), F32 if dtype == torch.float32 else F64,
                                            int(target)))
 
 
 def get_tiles_target(ndim, dtype):
+    """The set or tuned target for (ndim, dtype); 0 under the default rule."""
     t = ctypes.c_int32()
     _raise_if(load().pmsz_get_tiles_target(int(ndim), F32 if dtype == torch.float32 else F64,
                                            ctypes.byref(t)))

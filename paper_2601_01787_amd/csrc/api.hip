@@ -190,16 +190,18 @@ int write_tune_cache() {
   return PMSZ_OK;
 }
 
+// The set or tuned target, 0 when there is none (the default rule).
 int32_t tiles_target(int ndim, int dtype) {
   ensure_tune_cache();
   std::lock_guard<std::mutex> lk(g_tiles_mu);
-  const int32_t t = g_tiles_target[ndim == 3][dtype == PMSZ_F64];
-  return t > 0 ? t : kDefaultTilesTarget;
+  return g_tiles_target[ndim == 3][dtype == PMSZ_F64];
 }
 
-// Descriptor of one field with everything but its device pointers.
+// Descriptor of one field with everything but its device pointers.  target:
+// tiles per field (0: the set or tuned target, else the default for a batch
+// of nf fields).
 int describe_field(const pmsz_field& fld, int64_t max_iters, int dirs_given, FieldDesc& d,
-                   int32_t target = 0) {
+                   int32_t target = 0, int64_t nf = 1) {
   const pmsz_grid& g = fld.grid;
   int r = check_grid(&g);
   if (r) return r;
@@ -207,9 +209,9 @@ int describe_field(const pmsz_field& fld, int64_t max_iters, int dirs_given, Fie
   memset(&d, 0, sizeof(d));
   d.f = fld.f;
   d.g = fld.g;
-  d.geo = make_tile_geo(g.ndim, g.nx, g.ny, g.nz,
-                        engine_chunk(g.ndim, g.nx, g.ny, g.nz,
-                                     target > 0 ? target : tiles_target(g.ndim, g.dtype)));
+  if (target <= 0) target = tiles_target(g.ndim, g.dtype);
+  if (target <= 0) target = default_tiles_target(nf);
+  d.geo = make_tile_geo(g.ndim, g.nx, g.ny, g.nz, engine_chunk(g.ndim, g.nx, g.ny, g.nz, target));
   d.xi_t = xi_in_type(g.dtype, fld.xi);
   d.max_iters = max_iters;
   d.words = bitmap_words(d.geo.n);
@@ -229,7 +231,8 @@ int plan_batch(int32_t n, const pmsz_field* fields, const uint8_t* const* dirs_g
     if (fields[i].grid.dtype != fields[0].grid.dtype)
       return fail(PMSZ_ERR_INVALID_ARG, "all fields of a batch must share one dtype");
     FieldDesc& d = P.fd[i];
-    int r = describe_field(fields[i], max_iters, (dirs_given && dirs_given[i]) ? 1 : 0, d, target);
+    int r = describe_field(fields[i], max_iters, (dirs_given && dirs_given[i]) ? 1 : 0, d, target,
+                           n);
     if (r) return r;
     d.tile_base = P.total_tiles;
     d.seg_base = P.total_segs;
@@ -1441,7 +1444,8 @@ int pmsz_field_workspace_size(const pmsz_grid* grid, size_t* bytes) {
   if (r) return r;
   if (!bytes) return fail(PMSZ_ERR_INVALID_ARG, "bytes is NULL");
   const TileGeo G = make_tile_geo(grid->ndim, grid->nx, grid->ny, grid->nz,
-                                  engine_chunk(grid->ndim, grid->nx, grid->ny, grid->nz));
+                                  engine_chunk(grid->ndim, grid->nx, grid->ny, grid->nz,
+                                               default_tiles_target(1)));
   *bytes = field_layout(G, false).total;
   return PMSZ_OK;
 }

@@ -256,14 +256,23 @@ inline FieldLayout field_layout(const TileGeo& G, bool dirs_given) {
 
 // Tile height (planes per 3D tile, rows per 2D strip) for the engine: about
 // `tiles_target` tiles per field, between 2 and 32 planes / rows.  The target
-// is the autotuned knob (default 2048: enough tiles to spread one small field
-// over the chip); results do not depend on it.
-constexpr int32_t kDefaultTilesTarget = 2048;
-inline int engine_chunk(int ndim, int64_t nx, int64_t ny, int64_t nz,
-                        int32_t tiles_target = kDefaultTilesTarget) {
+// is the autotuned knob; results do not depend on it.  Without a set or
+// tuned target a batch of nf fields takes 2048 / nf, between 32 and 256: a
+// field of up to a few million vertices runs fastest in about 256 tiles
+// (fewer, taller tiles than blocks: a march's first planes are halo), and a
+// batch of many fields in about 32 each (measured on one MI355X, device time
+// per correction against a target of 2048: 64^3 267 against 286 us, 96^3 338
+// against 392 us, 1024^2 315 against 380 us; the 256-field batch 15.4 ms at
+// 32 against 16.2 ms at 256).  Large fields reach the 32-plane limit at any
+// of these targets.
+inline int32_t default_tiles_target(int64_t nf) {
+  const int64_t t = 2048 / (nf > 0 ? nf : 1);
+  return (int32_t)(t < 32 ? 32 : t > 256 ? 256 : t);
+}
+inline int engine_chunk(int ndim, int64_t nx, int64_t ny, int64_t nz, int32_t tiles_target) {
   const int64_t cols = ndim == 3 ? ((nx + TX - 1) / TX) * ((ny + TY - 1) / TY) : (nx + RX - 1) / RX;
   const int64_t depth = ndim == 3 ? nz : ny;
-  int64_t c = depth * cols / (tiles_target > 0 ? tiles_target : kDefaultTilesTarget);
+  int64_t c = depth * cols / (tiles_target > 0 ? tiles_target : default_tiles_target(1));
   if (c < 2) c = 2;
   if (c > kMaxChunk) c = kMaxChunk;
   return (int)c;

@@ -90,20 +90,21 @@ def test_blocks_workspace_size_host_only():
 
 
 def test_tiles_target_host_only():
-    """The tile-height policy: per (ndim, dtype), 0 restores the default, bad
-    arguments are rejected, and workspace sizes do not depend on it."""
+    """The tile-height policy: per (ndim, dtype), 0 restores the default rule
+    (reported as 0), bad arguments are rejected, and workspace sizes do not
+    depend on it."""
     import paper_2601_01787_amd as pmsz
     lib = pmsz.load()
     t = ctypes.c_int32()
-    assert lib.pmsz_get_tiles_target(3, pmsz.F32, ctypes.byref(t)) == 0 and t.value == 2048
+    assert lib.pmsz_get_tiles_target(3, pmsz.F32, ctypes.byref(t)) == 0 and t.value == 0
     g = pmsz.Grid(3, pmsz.F32, 300, 200, 100)
     before = pmsz.workspace_size(g, pmsz.WS_CORRECT)
     assert lib.pmsz_set_tiles_target(3, pmsz.F32, 64) == 0
     assert lib.pmsz_get_tiles_target(3, pmsz.F32, ctypes.byref(t)) == 0 and t.value == 64
-    assert lib.pmsz_get_tiles_target(2, pmsz.F32, ctypes.byref(t)) == 0 and t.value == 2048
+    assert lib.pmsz_get_tiles_target(2, pmsz.F32, ctypes.byref(t)) == 0 and t.value == 0
     assert pmsz.workspace_size(g, pmsz.WS_CORRECT) == before
     assert lib.pmsz_set_tiles_target(3, pmsz.F32, 0) == 0
-    assert lib.pmsz_get_tiles_target(3, pmsz.F32, ctypes.byref(t)) == 0 and t.value == 2048
+    assert lib.pmsz_get_tiles_target(3, pmsz.F32, ctypes.byref(t)) == 0 and t.value == 0
     assert lib.pmsz_set_tiles_target(4, pmsz.F32, 64) == 1
     assert lib.pmsz_set_tiles_target(3, 9, 64) == 1
     assert lib.pmsz_set_tiles_target(3, pmsz.F32, -1) == 1
@@ -128,6 +129,6 @@ def test_tune_cache_is_read_before_the_first_target(tmp_path):
                              capture_output=True, text=True).stdout
         return [int(v) for v in out.split()]
 
-    assert targets(json.dumps({"3d_f32": 96, "2d_f64": 7})) == [96, 7, 2048, 2048]
-    assert targets('{"2d_f32" :  40 ,\n "3d_f64": 0}') == [2048, 2048, 40, 2048]
-    assert targets("not json at all") == [2048, 2048, 2048, 2048]
+    assert targets(json.dumps({"3d_f32": 96, "2d_f64": 7})) == [96, 7, 0, 0]
+    assert targets('{"2d_f32" :  40 ,\n "3d_f64": 0}') == [0, 0, 40, 0]
+    assert targets("not json at all") == [0, 0, 0, 0]
