@@ -368,11 +368,12 @@ void fill_stats(const FieldIter& it, pmsz_stats& o) {
   }
 }
 
-// Bytes of host staging run_batch needs for n fields (descriptors up, control
-// block, round trace and states down).
+// Bytes of host staging run_batch needs for n fields (descriptors up; control
+// block, states and round trace down, the last two as laid out in the
+// workspace, so that one copy brings both).
 size_t batch_stage_bytes(int32_t n) {
   const size_t up = sizeof(FieldDesc) * (size_t)n;
-  const size_t down = kCtlHostBytes + kTraceBytes + sizeof(FieldIter) * (size_t)n;
+  const size_t down = kCtlHostBytes + align_up(sizeof(FieldIter) * (size_t)n) + kTraceBytes;
   return up > down ? up : down;
 }
 
@@ -460,13 +461,15 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
   // kSplitVoxels vertices or more sweeps tiles; the host then runs that
   // round's tile detection as a sweep kernel and launches the engine again.
   a.split_tiles = split ? 1 : 0;
-  HIP_TRY(engine_launch(dtype, a, s, &grid));
+  // (the workspace, barrier state included, was cleared at the start)
+  HIP_TRY(engine_launch(dtype, a, s, &grid, false));
   if (a.tail_ok) HIP_TRY(engine_tail(dtype, a, s));
   if (timed) HIP_TRY(hipEventRecord(tm.ev[5], s));
   const EngineCtl* hc = (const EngineCtl*)stage;
-  const unsigned long long* tr = (const unsigned long long*)((char*)stage + kCtlHostBytes);
-  const FieldIter* hs =
-      (const FieldIter*)((char*)stage + kCtlHostBytes + kTraceBytes);
+  // staging: [control block][states, padded as in the workspace][trace]
+  const FieldIter* hs = (const FieldIter*)((char*)stage + kCtlHostBytes);
+  const unsigned long long* tr =
+      (const unsigned long long*)((char*)stage + kCtlHostBytes + (P.trace - P.out));
   // the sweeps of those later tile rounds: ms by round (timed runs), count
   float late_ms[kTraceRounds] = {};
   int64_t late = 0;
@@ -477,11 +480,10 @@ int run_batch(int dtype, BatchPlan& P, const uint8_t* const* dirs_given, void* w
     // the staging buffer is reused for the results: the upload above is
     // stream-ordered before this copy, so it has been consumed
     HIP_TRY(hipMemcpyAsync(stage, ctl, kCtlHostBytes, hipMemcpyDeviceToHost, s));
-    if (timed)
-      HIP_TRY(hipMemcpyAsync((char*)stage + kCtlHostBytes, a.trace, kTraceBytes,
-                             hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync((char*)stage + kCtlHostBytes + kTraceBytes, out,
-                           sizeof(FieldIter) * (size_t)n, hipMemcpyDeviceToHost, s));
+    // the states, and the trace right after them in the workspace
+    HIP_TRY(hipMemcpyAsync((char*)stage + kCtlHostBytes, out,
+                           timed ? (P.trace - P.out) + kTraceBytes : sizeof(FieldIter) * (size_t)n,
+                           hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (hc->error) return fail(PMSZ_ERR_DEVICE, "grid barrier timed out in the correction engine");
     if (hc->handoff == kHandToEngine || hc->handoff == kTailDone) {

@@ -1646,7 +1646,7 @@ hipError_t engine_apply_first(int dtype, const EngineArgs& a, hipStream_t s) {
 }
 
 template <class T>
-static hipError_t launch_t(const EngineArgs& a, hipStream_t s, int* grid_out) {
+static hipError_t launch_t(const EngineArgs& a, hipStream_t s, int* grid_out, bool clear) {
   int dev = 0;
   hipError_t e = hipGetDevice(&dev);
   if (e != hipSuccess) return e;
@@ -1656,8 +1656,10 @@ static hipError_t launch_t(const EngineArgs& a, hipStream_t s, int* grid_out) {
   // the XCD and compute-unit barrier state starts cleared in every launch
   // (the round totals after it are kept: a sweep kernel may have added to
   // the current round's already)
-  e = engine_fill(&a.ctl->xbar[0], offsetof(EngineCtl, tot) - offsetof(EngineCtl, xbar), 0u, s);
-  if (e != hipSuccess) return e;
+  if (clear &&
+      (e = engine_fill(&a.ctl->xbar[0], offsetof(EngineCtl, tot) - offsetof(EngineCtl, xbar), 0u,
+                       s)) != hipSuccess)
+    return e;
   int64_t want = a.total_tiles > a.total_segs ? a.total_tiles : a.total_segs;
   if (want < 1) want = 1;
   int64_t cap = (int64_t)per_cu * cus;
@@ -1669,9 +1671,10 @@ static hipError_t launch_t(const EngineArgs& a, hipStream_t s, int* grid_out) {
   return hipLaunchCooperativeKernel((const void*)k_engine<T>, dim3(grid), dim3(256), args, 0, s);
 }
 
-hipError_t engine_launch(int dtype, const EngineArgs& a, hipStream_t s, int* grid_out) {
-  if (dtype == PMSZ_F32) return launch_t<float>(a, s, grid_out);
-  return launch_t<double>(a, s, grid_out);
+hipError_t engine_launch(int dtype, const EngineArgs& a, hipStream_t s, int* grid_out,
+                         bool clear) {
+  if (dtype == PMSZ_F32) return launch_t<float>(a, s, grid_out, clear);
+  return launch_t<double>(a, s, grid_out, clear);
 }
 
 // kTailGrid blocks, all resident (cooperative); an engine launch that hands

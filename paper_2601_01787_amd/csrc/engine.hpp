@@ -181,7 +181,10 @@ constexpr int kTraceSlots = 7;
 constexpr size_t kTraceBytes = (kTraceRounds * kTraceSlots + 1) * 8;
 
 // Host side (engine.hip).
-hipError_t engine_launch(int dtype, const EngineArgs& a, hipStream_t s, int* grid_out);
+// clear: clear the launch's barrier state first (not needed on a workspace
+// cleared since the last launch).
+hipError_t engine_launch(int dtype, const EngineArgs& a, hipStream_t s, int* grid_out,
+                         bool clear = true);
 // The tail (k_tail) after an engine launch with tail_ok set: ends at once
 // unless that launch handed its remaining rounds over.
 hipError_t engine_tail(int dtype, const EngineArgs& a, hipStream_t s);
