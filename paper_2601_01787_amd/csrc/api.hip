@@ -1611,7 +1611,10 @@ int pmsz_session_step_ex(pmsz_session* S, int64_t max_rounds, int32_t flags) {
   a.trace = nullptr;
   a.stop_on_done = (flags & PMSZ_STEP_STOP_ON_DONE) ? 1 : 0;
   a.stop_host = S->stop_word;
-  a.tail_ok = 0;  // a step's launches end on the host's stop words and round budget
+  // the step's last launch may hand its last rounds to the tail kernel when
+  // the step has no round budget (the tail reads the stop words too)
+  a.tail_ok = 0;
+  const int32_t tail_ok = (max_rounds < 0 && n <= 256) ? 1 : 0;
   // a stop requested before this launch is spent (the host's store is
   // ordered before the launch that reads the word)
   __atomic_store_n(S->stop_word, 0u, __ATOMIC_RELEASE);
@@ -1638,10 +1641,14 @@ int pmsz_session_step_ex(pmsz_session* S, int64_t max_rounds, int32_t flags) {
     a.max_rounds = max_rounds < 0 ? -1 : max_rounds - 1;
     if (a.max_rounds != 0) {
       HIP_TRY(engine_sweep(S->dtype, KIND_NEXT, false, dims, a, S->stream));
+      a.tail_ok = tail_ok;
       HIP_TRY(engine_launch(S->dtype, a, S->stream, &grid));
+      if (a.tail_ok) HIP_TRY(engine_tail(S->dtype, a, S->stream));
     }
   } else {
+    a.tail_ok = tail_ok;
     HIP_TRY(engine_launch(S->dtype, a, S->stream, &grid));
+    if (a.tail_ok) HIP_TRY(engine_tail(S->dtype, a, S->stream));
   }
   HIP_TRY(hipMemcpyAsync(down, S->ws, kCtlHostBytes, hipMemcpyDeviceToHost, S->stream));
   HIP_TRY(hipMemcpyAsync((char*)down + kCtlHostBytes, a.out, sizeof(FieldIter) * (size_t)n,

@@ -1169,7 +1169,10 @@ __device__ __forceinline__ int tail_round(const EngineArgs& a, const XcdBar& xb,
   if (__syncthreads_or(sweeps)) return 2;
   if (tracer && E < kTraceRounds) a.trace[kTraceSlots * E] = wall_clock64();
   if (blockIdx.x == 0) {
-    persist_round<true>(a, E, E0, p, qn);
+    // (the tail's first round is checked against the round before it, which
+    // the engine launch ran: a field it finished ends the step after this
+    // round, as the engine would have)
+    persist_round<true>(a, E, E == E0 && E0 > 0 ? E0 - 1 : E0, p, qn);
     if (tid < a.nf && items > 0) {
       relaxed_add(&as_global(a.fd[tid].st)->c[q].s[0].swept, (unsigned long long)items);
       atomicAdd(&ctl->tot[q][0].swept, (unsigned long long)items);
