@@ -536,10 +536,11 @@ class Session:
             self._h = None
             self._keep.clear()
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # at interpreter shutdown the HIP runtime may already be gone: a
-        # session not closed by then is left to the process exit
-        if sys.is_finalizing():
+        # session not closed by then is left to the process exit (the check
+        # is bound at definition: module globals may be cleared by then)
+        if _finalizing():
             return
         try:
             self.close()
