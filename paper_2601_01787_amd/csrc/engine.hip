@@ -242,7 +242,7 @@ __device__ __forceinline__ bool engine_failed(EngineCtl* ctl) {
 // counters start cleared).  Spins are bounded like the barriers'.  Returns
 // false for a block that leaves.
 __device__ __forceinline__ bool tail_census(EngineCtl* ctl, XcdBar& xb) {
-  __shared__ unsigned s_info[3];  // lead, rank, members
+  __shared__ unsigned s_info[3];  // XCD, rank among the lead XCD's blocks, their number
   if (threadIdx.x == 0) {
     const unsigned xcc = xcd_of_block();
     if (blockIdx.x == 0)
