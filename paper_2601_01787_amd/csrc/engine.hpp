@@ -134,7 +134,7 @@ constexpr int64_t kSplitVoxels = int64_t(1) << 23;
 // find each other's data in that L2 instead of in HBM.  A round in which a
 // field sweeps tiles ends k_tail before it starts (handoff kHandToEngine) and
 // the host launches the engine again.
-constexpr int kTailExams = 2;
+constexpr int kTailExams = 4;
 constexpr int kTailGrid = 256;  // blocks of a tail launch (32 per XCD)
 // The tail's apply pass takes each segment marked by its detection whole: the
 // engine hands over only once a round edits at most kTailSegs vertices (or
