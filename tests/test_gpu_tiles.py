@@ -67,3 +67,19 @@ def test_tuner_installs_a_candidate_and_keeps_inputs(tmp_path, monkeypatch):
     assert json.loads(cache.read_text())["2d_f32"] == best
     for (_, fh, _), k in zip(fields, keep):
         assert torch.equal(fh, k)
+
+
+def test_default_rule_by_batch_size():
+    """Without a set or tuned target a batch of n fields takes 2048 / n tiles
+    per field, between 32 and 256: a 256-wide strip field of 512 rows is cut
+    into 256 tiles alone (2 rows each) and into 32 tiles (16 rows each) in a
+    batch of 64 such fields; the results match the field alone."""
+    assert pmsz.get_tiles_target(2, torch.float32) == 0
+    f, fhat, xi = synth.make_2d_case(256, 512, 1e-3, 5)
+    g1, st1 = pmsz.correct(f.to("cuda:0"), fhat.to("cuda:0"), xi)
+    assert pmsz.last_timing()["tiles"] == 256
+    fields = [(f.to("cuda:0"), fhat.to("cuda:0"), xi) for _ in range(64)]
+    stats = pmsz.correct_batched(fields)
+    assert pmsz.last_timing()["tiles"] == 64 * 32
+    for (_, g, _), st in zip(fields, stats):
+        assert st == st1 and torch.equal(g, g1)
