@@ -474,7 +474,9 @@ __device__ __forceinline__ void mark_box(const FieldDesc& d, const TileBox& b, g
     const int32_t bx = (k & 1) ? b.x1 : b.x0, by = (k & 2) ? b.y1 : b.y0,
                   bz = (k & 4) ? b.z1 : b.z0;
     idx[k] = bx + d.geo.tiles_x * (by + d.geo.tiles_y * bz);
-    cur[k] = ld<CO>(nxt + idx[k]);
+    // (the tail stores without reading: its few edits gain more from one
+    // round trip less than from the stores a read saves)
+    cur[k] = CO ? uint8_t(0) : ld<CO>(nxt + idx[k]);
   }
 #pragma unroll
   for (int k = 0; k < 8; ++k)
@@ -534,6 +536,34 @@ __device__ __forceinline__ long long sparse_items(const FieldDesc& d, const Fiel
   }
   if (over) return -1;
   return (long long)n * (d.geo.ndim == 3 ? 15 : 7);
+}
+
+// The same count from list lengths loaded beforehand (nk, by load_nlist,
+// whose loads then overlap those of the field's state: the tail).
+__device__ __forceinline__ long long sparse_items_of(const FieldDesc& d, const FieldIter& s,
+                                                     const unsigned long long* nk,
+                                                     uint32_t* cnt) {
+  if (!s.started || s.done) return -1;
+  const unsigned long long cap = (unsigned long long)(d.list_cap / list_slices(d.words));
+  unsigned long long n = 0;
+  bool over = false;
+#pragma unroll
+  for (int k = 0; k < kCtrSlots; ++k) {
+    over |= nk[k] > cap;
+    n += nk[k];
+    cnt[k] = (uint32_t)nk[k];
+  }
+  if (over) return -1;
+  return (long long)n * (d.geo.ndim == 3 ? 15 : 7);
+}
+
+// List lengths of round E's sparse examination (the previous round's apply
+// pass appended the targets), device-scope loads.
+__device__ __forceinline__ void load_nlist(const FieldDesc& d, unsigned long long E,
+                                           unsigned long long* nk) {
+  const gptr<const FieldCtr> c = &as_global((const FieldState*)d.st)->c[(E + 2) % 3];
+#pragma unroll
+  for (int k = 0; k < kCtrSlots; ++k) nk[k] = ld<true>(&c->s[k].nlist);
 }
 
 // Signed vertex offset of a direction code.
@@ -806,6 +836,25 @@ __device__ __forceinline__ void apply_segment(const FieldDesc& d, int32_t w0, in
       }
     }
     const int n = total - base < kApplyCap ? total - base : kApplyCap;
+    // In the tail, the first targets' gathers (below) go out before the
+    // list-slot atomic, so that the two round trips overlap.
+    int32_t t0[kEditUnroll];
+    T gt0[kEditUnroll], ft0[kEditUnroll];
+    if constexpr (CO) {
+      lds_barrier();  // the list is complete
+      if (tid < n) {
+#pragma unroll
+        for (int u = 0; u < kEditUnroll; ++u) {
+          const int j = tid + 256 * u;
+          t0[u] = (int32_t)list[j < n ? j : tid];
+        }
+#pragma unroll
+        for (int u = 0; u < kEditUnroll; ++u) {
+          gt0[u] = ld<CO>(g + t0[u]);
+          ft0[u] = f[t0[u]];
+        }
+      }
+    }
     // room in this block's slice of the field's target list for this pass
     // (next round's sparse examination); entries past the slice are
     // dropped, and the count then sends the next round to a tile sweep
@@ -821,15 +870,24 @@ __device__ __forceinline__ void apply_segment(const FieldDesc& d, int32_t w0, in
     for (int j0 = tid; j0 < n; j0 += 256 * kEditUnroll) {
       int32_t t[kEditUnroll];
       T gt[kEditUnroll], ft[kEditUnroll];
+      if (CO && j0 == tid) {
 #pragma unroll
-      for (int u = 0; u < kEditUnroll; ++u) {
-        const int j = j0 + 256 * u;
-        t[u] = (int32_t)list[j < n ? j : j0];
-      }
+        for (int u = 0; u < kEditUnroll; ++u) {
+          t[u] = t0[u];
+          gt[u] = gt0[u];
+          ft[u] = ft0[u];
+        }
+      } else {
 #pragma unroll
-      for (int u = 0; u < kEditUnroll; ++u) {
-        gt[u] = ld<CO>(g + t[u]);
-        ft[u] = f[t[u]];
+        for (int u = 0; u < kEditUnroll; ++u) {
+          const int j = j0 + 256 * u;
+          t[u] = (int32_t)list[j < n ? j : j0];
+        }
+#pragma unroll
+        for (int u = 0; u < kEditUnroll; ++u) {
+          gt[u] = ld<CO>(g + t[u]);
+          ft[u] = f[t[u]];
+        }
       }
 #pragma unroll
       for (int u = 0; u < kEditUnroll; ++u) {
@@ -1159,8 +1217,10 @@ __device__ __forceinline__ int tail_round(const EngineArgs& a, const XcdBar& xb,
   int sweeps = 0;
   if (tid < a.nf) {
     const FieldDesc& d = a.fd[tid];
+    unsigned long long nk[kCtrSlots];
+    load_nlist(d, E, nk);
     const FieldIter s = state_at<true>(d, E, E0);
-    items = sparse_items<true>(d, s, E, L.slot + tid * kCtrSlots);
+    items = sparse_items_of(d, s, nk, L.slot + tid * kCtrSlots);
     if (items < 0) {
       sweeps = !s.done;
       items = 0;
